@@ -1,0 +1,201 @@
+"""Pins of the oracle's time step against what the paper and the mathematics
+fix: reduction to the paper's 0+1-D algorithm, the discrete energy balance,
+conservation, second-order accuracy in time and space, and the ideal and
+viscous hydrodynamic limits (paper Sec. IV.D, IV.E, eq. (hydroeq))."""
+import numpy as np
+import pytest
+
+from oracle import hydro
+from oracle import step as st
+from oracle.bjorken import Bjorken01
+from oracle.eos import HBARC, ConstMassEoS, TanhEoS
+from oracle.lattice import Lattice
+
+
+@pytest.fixture(scope="module")
+def lat():
+    return Lattice(5, 5, 4, 1.0)
+
+
+@pytest.fixture(scope="module")
+def eos():
+    return TanhEoS(width=0.03)
+
+
+def test_uniform_grid_reduces_to_paper_0p1d(lat, eos):
+    # A homogeneous transverse grid is the paper's 0+1-D algorithm
+    prm = st.Params(dx=0.2, eta_over_s=0.08)
+    e0 = np.full((2, 3), float(eos.eps(0.4)) / HBARC ** 3)
+    F, l = st.init_state(lat, eos, e0)
+    b = Bjorken01(lat, eos, 0.08)
+    f1, l1 = b.init(0.4)
+    assert np.max(np.abs(F[:, 0, 0] - f1)) < 1e-14 * f1.max()
+    tau = 0.5
+    for _ in range(3):
+        F, l = st.heun_step(lat, eos, prm, F, l, tau, 0.01)
+        f1, l1 = b.step(f1, l1, tau, 0.01)
+        tau += 0.01
+    for iy in range(2):
+        for ix in range(3):
+            assert np.max(np.abs(F[:, iy, ix] - f1)) < 1e-13 * f1.max()
+            assert abs(l[iy, ix] - l1) < 1e-14
+
+
+def _energy_balance_residual(b, T0, tau0, dtau, nstep):
+    """sum over steps of eps(tau+dt) - eps(tau) + trapezoid of (eps + P_L)/tau."""
+    f, l = b.init(T0)
+    tau = tau0
+    e0, pl0, _ = b.energy_density(f, l)
+    res = 0.0
+    for _ in range(nstep):
+        f, l = b.step(f, l, tau, dtau)
+        e1, pl1, _ = b.energy_density(f, l)
+        res += e1 - e0 + 0.5 * dtau * ((e0 + pl0) / tau + (e1 + pl1) / (tau + dtau))
+        e0, pl0 = e1, pl1
+        tau += dtau
+    return res / b.energy_density(*b.init(T0))[0]
+
+
+def test_total_energy_balance_includes_bag_and_mass_evolution(eos):
+    # Bjorken: d eps/d tau = -(eps + P_L)/tau with eps, P_L including B(T)
+    # (conservation of eq. (tmunufull)).  It holds to O(dtau^2) only if the
+    # mass evolution of eq. (masschange) is right (with the cosh^2 factor).
+    # Free streaming (tau_R = inf, the paper's eta/s = inf run) keeps the mass
+    # evolving with the energy density while the BGK term, whose lattice
+    # equilibrium moments carry a quadrature error, is off.
+    lat1 = Lattice(5, 5, 1, 1.0)
+    b = Bjorken01(lat1, eos, np.inf)
+    r1 = _energy_balance_residual(b, 0.3, 0.5, 0.02, 5)
+    r2 = _energy_balance_residual(b, 0.3, 0.5, 0.01, 10)
+    assert abs(r1) < 3e-4
+    assert 3.6 < r1 / r2 < 4.4
+
+
+def test_dropping_cosh2_in_mass_predictor_breaks_energy_balance(eos):
+    # the printed predictor without cosh^2 xi does not conserve energy:
+    # a planted mistake (in the oracle, on the CPU) must fail the pin above
+    lat1 = Lattice(5, 5, 1, 1.0)
+
+    class Printed(Bjorken01):
+        def rates(self, f, lnM, tau):
+            df, dl, T = super().rates(f, lnM, tau)
+            lat = self.lat
+            dl_true = dl
+            # recompute with the printed numerator (no cosh^2)
+            S1 = lat.apply_slices(lat.D1, f)
+            S2 = lat.apply_slices(lat.D2, f)
+            # collision part recovered from df = S1/tau + dl S2 - coll
+            coll = S1 / tau + dl_true * S2 - df
+            Ta = np.array([T])
+            dBde = float(self.eos.dB(Ta)[0]) / (T * float(self.eos.ds(Ta)[0]))
+            dl_pr = -dBde * np.sum(lat.w * (S1 / tau - coll)) / np.sum(lat.w * f)
+            return S1 / tau + dl_pr * S2 - coll, dl_pr, T
+
+    r = _energy_balance_residual(Printed(lat1, eos, np.inf), 0.3, 0.5, 0.01, 10)
+    assert abs(r) > 1e-3
+
+
+def test_free_streaming_conservation_minkowski(lat):
+    # Minkowski metric, no collisions, constant mass: the periodic box
+    # conserves total energy and momentum exactly (up to rounding)
+    eos = ConstMassEoS(Z=3.0, M0=0.4)
+    prm = st.Params(dx=0.2, eta_over_s=np.inf, metric=st.METRIC_MINKOWSKI)
+    rng = np.random.default_rng(1)
+    e0 = 2 + rng.random((5, 6))
+    F, l = st.init_state(lat, eos, e0, 0.3 * rng.standard_normal((5, 6)), 0.3 * rng.standard_normal((5, 6)))
+    T0, _ = lat.moments(F, l)
+    for _ in range(3):
+        F, l = st.heun_step(lat, eos, prm, F, l, 1.0, 0.05)
+    T1, _ = lat.moments(F, l)
+    for a in range(3):
+        assert abs(T1[0, a].sum() - T0[0, a].sum()) < 1e-13 * T0[0, 0].sum()
+
+
+def test_free_streaming_energy_balance_milne(lat):
+    # Milne, no collisions, constant mass: d(tau E)/dtau = -sum T^{YY} holds
+    # exactly on the lattice; the Heun step leaves an O(dtau^3) residual
+    eos = ConstMassEoS(Z=3.0, M0=0.4)
+    prm = st.Params(dx=0.2, eta_over_s=np.inf)
+    rng = np.random.default_rng(1)
+    e0 = 2 + rng.random((4, 5))
+    F, l = st.init_state(lat, eos, e0, 0.3 * rng.standard_normal((4, 5)), 0.3 * rng.standard_normal((4, 5)))
+    res = []
+    for dt in (0.02, 0.01):
+        T0, _ = lat.moments(F, l)
+        Fn, ln = st.heun_step(lat, eos, prm, F, l, 0.5, dt)
+        T1, _ = lat.moments(Fn, ln)
+        r = ((0.5 + dt) * T1[0, 0].sum() - 0.5 * T0[0, 0].sum()
+             + 0.5 * dt * (T0[3, 3].sum() + T1[3, 3].sum())) / (0.5 * T0[0, 0].sum())
+        res.append(r)
+    assert abs(res[0]) < 1e-4
+    assert 6.0 < res[0] / res[1] < 10.0
+
+
+def test_second_order_in_time(eos):
+    # Sec. IV.D: time-integrated quantities are accurate to O(dtau^2)
+    lat1 = Lattice(5, 5, 1, 1.0)
+    b = Bjorken01(lat1, eos, 0.2)
+
+    def run(dt):
+        f, l = b.init(0.35)
+        tau = 0.5
+        for _ in range(int(round(0.1 / dt))):
+            f, l = b.step(f, l, tau, dt)
+            tau += dt
+        return b.temperature(f, l)
+
+    ref = run(0.00625)
+    e1 = abs(run(0.05) - ref)
+    e2 = abs(run(0.025) - ref)
+    e3 = abs(run(0.0125) - ref)
+    assert 3.0 < e1 / e2 < 5.5 and 3.0 < e2 / e3 < 5.5
+
+
+def test_second_order_in_space():
+    # transport only (Minkowski, no collisions, constant mass): each node is
+    # advected at v^x/gamma; error of the scheme falls ~4x per halving of dx
+    lat = Lattice(3, 3, 4, 1.0)
+    eos = ConstMassEoS(Z=3.0, M0=0.4)
+    L, t_end, cfl = 6.4, 0.8, 0.2
+
+    def err(nx):
+        dx = L / nx
+        prm = st.Params(dx=dx, eta_over_s=np.inf, metric=st.METRIC_MINKOWSKI)
+        xs = (np.arange(nx) + 0.5) * dx
+        base = eos.Z * np.exp(-0.4 * lat.gamma / 0.3)
+        prof = lambda x: 1 + 0.2 * np.exp(-((x - L / 2 + L) % L - L / 2) ** 2 / (2 * 0.6 ** 2))
+        F = base[:, None, None] * prof(xs)[None, None, :]
+        l = np.full((1, nx), np.log(0.4))
+        dt = cfl * dx
+        nst = int(round(t_end / dt))
+        for _ in range(nst):
+            F, l = st.heun_step(lat, eos, prm, F, l, 1.0, dt)
+        vx = lat.V[1] / lat.gamma
+        exact = base[:, None] * prof(xs[None, :] - vx[:, None] * nst * dt)
+        return np.max(np.abs(F[:, 0, :] - exact)) / base.max()
+
+    e1, e2, e3 = err(32), err(64), err(128)
+    assert 3.0 < e1 / e2 < 5.5 and 3.2 < e2 / e3 < 5.0
+
+
+def test_ideal_and_first_order_viscous_limits():
+    # Sec. IV.E: the LB tends to fluid dynamics as eta/s -> 0; the deviation
+    # from ideal Bjorken flow is first order in eta/s, and first-order viscous
+    # hydrodynamics (eta = (eta/s) s, zeta of Sec. IV.A) absorbs it.
+    eos = TanhEoS(width=0.03)
+    lat1 = Lattice(5, 5, 1, 2.6)
+    taus = np.linspace(1.0, 2.0, 51)
+    dev_id, dev_ns = [], []
+    for eta in (0.01, 0.02):
+        b = Bjorken01(lat1, eos, eta)
+        f, l = b.init(0.35)
+        for i in range(50):
+            f, l = b.step(f, l, taus[i], 0.02)
+        T_lb = b.temperature(f, l)
+        Ti = hydro.ideal(eos, 0.35, 1.0, taus)[-1]
+        Tn = hydro.navier_stokes(eos, 0.35, 1.0, taus, eta)[-1]
+        dev_id.append((T_lb - Ti) / Ti)
+        dev_ns.append((T_lb - Tn) / Tn)
+    assert dev_id[0] > 0 and 1.5 < dev_id[1] / dev_id[0] < 2.5
+    for di, dn in zip(dev_id, dev_ns):
+        assert abs(dn) < 0.35 * abs(di)

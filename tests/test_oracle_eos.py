@@ -1,0 +1,128 @@
+"""Pins of the oracle's quasiparticle EoS (paper Sec. II.A, III, III.A, IV.A)
+against thermodynamics, the paper's closed forms and numerical derivatives."""
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.special import kv
+
+from oracle.eos import HBARC, ConstMassEoS, TanhEoS
+
+T = np.array([0.08, 0.12, 0.16, 0.17, 0.19, 0.22, 0.3, 0.5, 1.0, 2.0])
+
+
+def _fd(f, x, h):
+    return (f(x + h) - f(x - h)) / (2 * h)
+
+
+@pytest.fixture(scope="module")
+def eos():
+    return TanhEoS(width=0.03)
+
+
+def test_entropy_and_its_derivative_are_derivatives_of_p(eos):
+    # eq. (thermo) at mu = 0: s = dp/dT; the analytic s' is d s/dT
+    h = 1e-6
+    assert np.allclose(eos.s(T), _fd(eos.p, T, h), rtol=1e-7)
+    assert np.allclose(eos.ds(T), _fd(eos.s, T, h), rtol=1e-6)
+
+
+def test_bag_function_solves_consistency_ode(eos):
+    # eq. (cdef2): dB/dT = -Z M^2 T K_1(M/T) M'(T)/(2 pi^2); B = p_kin - p
+    h = 1e-6
+    num = _fd(eos.B, T, h)
+    ana = eos.dB(T)
+    assert np.allclose(ana, num, rtol=2e-6, atol=1e-12)
+    # the paper integrates up from small T where B ~ 0: |B| is below 1e-3 of
+    # the Stefan-Boltzmann pressure of the same degrees of freedom there
+    Tl = np.array([0.05, 0.06, 0.08, 0.1])
+    assert np.all(np.abs(eos.B(Tl)) < 1e-3 * eos.c * Tl ** 4)
+    # M' from implicit differentiation against a numerical derivative of M(T)
+    assert np.allclose(eos.dM(T), _fd(eos.M, T, h), rtol=1e-6)
+
+
+def test_kinetic_energy_plus_bag_is_eos_energy(eos):
+    # eq. (epsp): eps = Z M^2 T^2 [3 K2 + (M/T) K1]/(2 pi^2) + B, p = p_kin - B
+    assert np.allclose(eos.eps_kin_eq(T) + eos.B(T), eos.eps(T), rtol=1e-12)
+    # and the kinetic entropy Z M^3 K_3/(2 pi^2) is the input s(T) (Sec. III.A)
+    M = eos.M(T)
+    s_qp = eos.Z * M ** 3 * kv(3, M / T) / (2 * np.pi ** 2)
+    assert np.allclose(s_qp, eos.s(T), rtol=1e-12)
+
+
+def test_beta_is_dB_deps_kin(eos):
+    # beta = dB/d(eps - B); beta/(1+beta) = dB/deps (mass predictor of Sec. IV.D)
+    h = 1e-6
+    dB = _fd(eos.B, T, h)
+    deps = _fd(eos.eps, T, h)
+    assert np.allclose(eos.beta(T) / (1 + eos.beta(T)), dB / deps, rtol=1e-5, atol=1e-9)
+
+
+def test_high_temperature_mass_limit():
+    # s -> 4 g pi^2 T^3/90 = (Z/kappa) 4 T^3/pi^2, so z^3 K_3(z) -> 8/kappa
+    e = TanhEoS(width=0.03, kappa=2.0)
+    z = e.z_of_T(np.array([3.0]))[0]
+    assert abs(z ** 3 * kv(3, z) - 4.0) < 1e-10
+
+
+def test_config_eos_is_unstable_and_stable_reading_is_not():
+    # The width-0.02 EoS has d eps/dT < 0 on a band near 0.19 GeV (c_s^2 < 0);
+    # the width-0.03 reading is stable and causal on [0.05, 3] GeV.
+    Tg = np.linspace(0.05, 3.0, 60001)
+    e02, e03 = TanhEoS(width=0.02), TanhEoS(width=0.03)
+    d02 = Tg * e02.ds(Tg)
+    assert np.any(d02 < 0)
+    band = Tg[d02 < 0]
+    assert 0.184 < band.min() < 0.185 and 0.196 < band.max() < 0.197
+    cs2 = e03.s(Tg) / (Tg * e03.ds(Tg))
+    assert np.all(cs2 > 0) and np.all(cs2 <= 1.0)
+    # the matched quantity eps - B stays monotone for both
+    for e in (e02, e03):
+        assert np.all(np.diff(e.eps_kin_eq(Tg[::20])) > 0)
+
+
+def test_constant_mass_gas_sound_speed_and_bessel_forms():
+    # Sec. II.A: c_s^2 = (3 + (m/T) K2/K3)^-1 and n = p/T for a constant mass
+    e = ConstMassEoS(Z=3.0, M0=0.5)
+    h = 1e-6
+    cs2 = _fd(e.p, T, h) / _fd(e.eps, T, h)
+    z = 0.5 / T
+    assert np.allclose(cs2, 1.0 / (3 + z * kv(2, z) / kv(3, z)), rtol=1e-7)
+    eps_ref = 3.0 * 0.25 * T * (3 * T * kv(2, z) + 0.5 * kv(1, z)) / (2 * np.pi ** 2)
+    assert np.allclose(e.eps(T), eps_ref, rtol=1e-12)
+    assert np.allclose(e.beta(T), 0.0) and np.allclose(e.B(T), 0.0)
+
+
+def test_shear_viscosity_limits():
+    # Sec. IV.A: massless eta = tau_R (eps + P)/5; constant mass
+    # eta = (tau_R/T) int_0^T dT' (eps + P)
+    Tt = np.array([0.2, 0.4])
+    e0 = ConstMassEoS(Z=3.0, M0=1e-4)
+    assert np.allclose(e0.h(Tt), (e0.eps(Tt) + e0.p(Tt)) / 5.0, rtol=1e-6)
+    e = ConstMassEoS(Z=3.0, M0=0.5)
+    for t in Tt:
+        I, _ = quad(lambda tp: e.eps(np.array([tp]))[0] + e.p(np.array([tp]))[0], 1e-3, t,
+                    epsabs=0, epsrel=1e-12)
+        assert abs(e.h(np.array([t]))[0] - I / t) < 1e-9 * I / t
+
+
+def test_relaxation_time_rules(eos):
+    Tt = np.array([0.2, 0.4, 1.0])
+    assert np.allclose(eos.tau_R(Tt, 0.1, "massless"), 0.5 / Tt * HBARC, rtol=1e-15)
+    # CE rule: eta = tau_R h(T) equals (eta/s) s
+    tr = eos.tau_R(Tt, 0.1, "ce") / HBARC
+    assert np.allclose(tr * eos.h(Tt), 0.1 * eos.s(Tt), rtol=1e-13)
+
+
+def test_inversions():
+    e = TanhEoS(width=0.03)
+    Tt = np.array([0.06, 0.15, 0.2, 0.4, 2.5])
+    assert np.allclose(e.T_from_eps_kin_eq(e.eps_kin_eq(Tt)), Tt, rtol=1e-13)
+    assert np.allclose(e.T_from_eps_largest(e.eps(Tt)), Tt, rtol=1e-13)
+    # the unstable EoS: an energy density with three roots gives the largest
+    e2 = TanhEoS(width=0.02)
+    target = 3.19 * HBARC ** 3
+    Tr = e2.T_from_eps_largest(np.array([target]))[0]
+    assert abs(e2.eps(Tr) - target) < 1e-13 * target
+    Tg = np.linspace(Tr + 1e-6, 3.0, 20000)
+    assert np.all(e2.eps(Tg) > target)
+    assert Tr > 0.196

@@ -1,0 +1,128 @@
+"""Pins of the oracle's discrete momentum set, moments, weak-form operators
+and Landau matching (paper Sec. IV.B-IV.D, eqs. (emtnew), (sanity))."""
+import numpy as np
+import pytest
+from scipy.special import kv
+
+from oracle.lattice import Lattice
+from oracle.step import landau
+
+PI2 = np.pi ** 2
+
+
+@pytest.fixture(scope="module")
+def lat():
+    return Lattice(5, 5, 4, 1.0)
+
+
+def _feq(lat, Z, M, T, u=(1.0, 0.0, 0.0)):
+    ut, ux, uy = u
+    return Z * np.exp(-M * (ut * lat.gamma - ux * lat.V[1] - uy * lat.V[2]) / T)
+
+
+def test_equilibrium_moments_exact_at_reference_mass(lat):
+    # At M/T = z0 the weights make the lattice sums exact Gauss quadratures of
+    # the Bessel forms (Sec. II.A): eps = Z M^2 T (3 T K2 + M K1)/(2 pi^2),
+    # p = Z M^2 T^2 K2/(2 pi^2), n = p/T.
+    Z, T = 3.0, 0.4
+    M = lat.z0 * T
+    F = _feq(lat, Z, M, T)
+    Tk, Nk = lat.moments(F[:, None], np.array([np.log(M)]))
+    eps = Z * M ** 2 * T * (3 * T * kv(2, M / T) + M * kv(1, M / T)) / (2 * PI2)
+    p = Z * M ** 2 * T ** 2 * kv(2, M / T) / (2 * PI2)
+    assert abs(Tk[0, 0, 0] / eps - 1) < 1e-14
+    for a in (1, 2, 3):
+        assert abs(Tk[a, a, 0] / p - 1) < 1e-14
+    assert abs(Nk[0, 0] / (p / T) - 1) < 1e-14
+    off = [Tk[0, 1, 0], Tk[0, 2, 0], Tk[0, 3, 0], Tk[1, 2, 0], Tk[1, 3, 0], Tk[2, 3, 0]]
+    assert np.max(np.abs(off)) < 1e-15 * eps
+
+
+@pytest.mark.parametrize("z,tol", [(1.3, 1e-5), (2.0, 5e-3), (2.6, 5e-3), (0.5, 1e-2)])
+def test_equilibrium_moments_away_from_reference(lat, z, tol):
+    # Elsewhere the lattice error grows with |M/T - z0| (Sec. IV.E: most
+    # accurate at the reference temperature)
+    Z, T = 3.0, 0.4
+    M = z * T
+    F = _feq(lat, Z, M, T)
+    Tk, _ = lat.moments(F[:, None], np.array([np.log(M)]))
+    eps = Z * M ** 2 * T * (3 * T * kv(2, z) + M * kv(1, z)) / (2 * PI2)
+    p = Z * M ** 2 * T ** 2 * kv(2, z) / (2 * PI2)
+    assert abs(Tk[0, 0, 0] / eps - 1) < tol
+    assert abs(Tk[1, 1, 0] / p - 1) < tol
+
+
+def test_weak_form_energy_identities(lat):
+    # Discrete integration by parts (Sec. IV.D, eq. (edchange)): for any F
+    #   sum w gamma^2 S2[F] = sum w F - 4 sum w gamma^2 F
+    #   sum w gamma^2 S1[F] = -sum w F (gamma^2 + (v^Y)^2)
+    #   sum w S2[F]          = -sum w F (2 + 1/gamma^2)
+    # so the scheme's d eps/dtau = -(eps + P_L)/tau holds exactly on the lattice.
+    rng = np.random.default_rng(7)
+    g2 = lat.gamma ** 2
+    for _ in range(5):
+        F = rng.random(lat.N)
+        S1 = lat.apply_slices(lat.D1, F)
+        S2 = lat.apply_slices(lat.D2, F)
+        ref2 = np.sum(lat.w * F) - 4 * np.sum(lat.w * g2 * F)
+        ref1 = -np.sum(lat.w * F * (g2 + lat.V[3] ** 2))
+        assert abs(np.sum(lat.w * g2 * S2) - ref2) < 1e-13 * np.sum(lat.w * g2 * F)
+        assert abs(np.sum(lat.w * g2 * S1) - ref1) < 1e-13 * np.sum(lat.w * g2 * F)
+        ref0 = -np.sum(lat.w * F * (2 + 1 / g2))
+        assert abs(np.sum(lat.w * S2) - ref0) < 1e-13 * np.sum(lat.w * F)
+
+
+def test_weak_form_operators_act_per_slice_and_radially(lat):
+    # S2 = p.d/dp is a radial derivative; S1 = p^Y d/dp^Y mixes xi and theta
+    # but not phi; a slice-constant F gives slice-constant results.
+    nt = lat.n_theta
+    D2 = lat.D2.reshape(lat.n_xi, nt, lat.n_xi, nt)
+    for j in range(nt):
+        for jp in range(nt):
+            if j != jp:
+                assert np.max(np.abs(D2[:, j, :, jp])) < 1e-12 * np.max(np.abs(lat.D2))
+
+
+def test_operators_approximate_the_derivatives(lat):
+    # On smooth functions the weak forms approximate v.d_v F and v^Y d_{v^Y} F
+    z0 = lat.z0
+    x = lat.gamma
+    mu = lat.V[3] / np.sqrt(np.maximum(x ** 2 - 1, 1e-300))
+    F = np.exp(-z0 * x) * (1 + 0.3 * x)
+    S2 = lat.apply_slices(lat.D2, F)
+    # exact: r d/dr with r d x/dr = (x^2 - 1)/x
+    dF = np.exp(-z0 * x) * (-z0 * (1 + 0.3 * x) + 0.3) * (x ** 2 - 1) / x
+    wt = lat.w * x ** 2
+    assert np.sum(wt * np.abs(S2 - dF)) < 0.1 * np.sum(wt * np.abs(dF))
+    # F = exp(-z0 x) mu^2: v^Y d/dv^Y = mu^2 r d/dr + (1 - mu^2) mu d/dmu
+    F1 = np.exp(-z0 * x) * mu ** 2
+    S1 = lat.apply_slices(lat.D1, F1)
+    ex = mu ** 2 * (-z0 * np.exp(-z0 * x) * mu ** 2 * (x ** 2 - 1) / x) \
+        + (1 - mu ** 2) * mu * np.exp(-z0 * x) * 2 * mu
+    assert np.sum(wt * np.abs(S1 - ex)) < 0.1 * np.sum(wt * np.abs(ex))
+
+
+def test_landau_matching_round_trip():
+    # eq. (sanity): U_mu T^{mu nu} = eps U^nu for T = eps u u - P Delta + pi
+    rng = np.random.default_rng(3)
+    g = np.diag([1.0, -1.0, -1.0])
+    n = 200
+    T3 = np.zeros((3, 3, n))
+    u_ref = np.zeros((3, n))
+    e_ref = rng.uniform(0.5, 5.0, n)
+    for i in range(n):
+        ux, uy = rng.normal(0, 1.0, 2)
+        u = np.array([np.sqrt(1 + ux * ux + uy * uy), ux, uy])
+        P = e_ref[i] * rng.uniform(0.1, 0.4)
+        Delta = np.linalg.inv(g) - np.outer(u, u)
+        # shear: symmetric, orthogonal to u, traceless, small
+        a = rng.normal(0, 0.05 * P, (3, 3))
+        a = a + a.T
+        proj = Delta @ g
+        pi = proj @ a @ proj.T
+        pi -= 0.5 * np.trace(g @ pi) * Delta   # traceless in the 2-D transverse space
+        T3[:, :, i] = e_ref[i] * np.outer(u, u) - P * Delta + pi
+        u_ref[:, i] = u
+    u, lam = landau(T3)
+    assert np.max(np.abs(lam - e_ref) / e_ref) < 1e-12
+    assert np.max(np.abs(u - u_ref)) < 1e-11 * np.max(np.abs(u_ref))
