@@ -1,0 +1,165 @@
+"""Benchmark of the lattice-Boltzmann step on one MI355X.
+
+A step is one Heun step (predictor + corrector stage kernels) over the whole
+256 x 256 transverse lattice of the precision workload (Gaussian + 5% white
+noise, dx = 0.025 fm, eta/s = 0.08, 200 momentum nodes per site, synthetic
+QCD-like EoS).  The metric is lattice-site updates per second of the
+FP32-with-FP64-matching step; the FP64 step on the same workload and the
+FP32-vs-FP64 T^{mu nu} difference after the timed steps are reported beside
+it.  Prints one JSON line.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import platform
+import resource
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N_NODES = 200
+
+
+def site_bytes(precision, stage):
+    """Algorithmic HBM bytes per site of one stage kernel: the state (N nodes
+    and ln M) read and written once; the corrector also reads the base state."""
+    elt = 4 if precision == "fp32" else 8
+    f = N_NODES * elt
+    return (2 * f + 16) if stage == 0 else (3 * f + 24)
+
+
+def run_gpu(lb, wl, torch, precision, steps, warmup):
+    w = wl.WORKLOADS["prec"]
+    prec = lb.LB_FP32_FP64MATCH if precision == "fp32" else lb.LB_FP64
+    p = lb.make_params(w["nx"], w["ny"], w["dx"], tau0_fm=w["tau0"], eta_over_s=w["eta_over_s"], precision=prec)
+    e_peak = lb.eos_eval(p, [0.4])[0, 0] / lb.HBARC ** 3
+    e0 = e_peak * wl.gaussian_shape(w["nx"], w["ny"], w["dx"], 2.0) * wl.white_noise_factor(w["nx"], w["ny"])
+    c = lb.Context(p, torch.from_numpy(e0).to("cuda:0"))
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    c.step(warmup, dtau)
+    torch.cuda.synchronize()
+    c.profile(1)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    c.step(steps, dtau)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    (ms_pred, ms_corr), (n_pred, n_corr) = c.profile_read()
+    c.profile(0)
+    if c.status() != lb.LB_OK:
+        raise RuntimeError(lb.last_error())
+    n_sites = w["nx"] * w["ny"]
+    obs = c.moments().cpu().numpy()
+    return dict(ms=ms, wall=wall, n_sites=n_sites, pred_ms=ms_pred / max(n_pred, 1),
+                corr_ms=ms_corr / max(n_corr, 1), obs=obs, e0=e0, dtau=dtau)
+
+
+def cpu_baseline(wl, e0, dtau, n_steps=3):
+    """The oracle as it stands on a bounded sample: a 64 x 64 periodic window
+    of the same initial state (centre of the grid), n_steps Heun steps."""
+    from oracle import step as st
+    from oracle.eos import TanhEntropyEoS
+    from oracle.lattice import Lattice
+    w = wl.WORKLOADS["prec"]
+    lat = Lattice(5, 5, 4, 1.0)
+    eos = TanhEntropyEoS()
+    prm = st.Params(dx=w["dx"], eta_over_s=w["eta_over_s"])
+    c0 = w["nx"] // 2 - 32
+    sub = e0[c0:c0 + 64, c0:c0 + 64]
+    F, l = st.init_state(lat, eos, sub)
+    F, l = st.heun_step(lat, eos, prm, F, l, w["tau0"], dtau)   # warm-up
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    tau = w["tau0"] + dtau
+    for _ in range(n_steps):
+        F, l = st.heun_step(lat, eos, prm, F, l, tau, dtau)
+        tau += dtau
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu_s = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    cores = max(1, int(round(cpu_s / wall)))
+    return dict(value=n_steps * 64 * 64 / wall, unit="site-updates/s", cores=cores, kind="oracle",
+                sample=f"64x64 centre window of the 256x256 workload, {n_steps} Heun steps after 1 warm-up, "
+                       f"{wall:.1f} s wall, host {platform.processor() or platform.machine()}, "
+                       f"nproc {os.cpu_count()}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the lattice-Boltzmann step runs on a single MI355X "
+              "(multi-GPU execution is not part of this build); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1108_5561_amd as lb
+    from paper_1108_5561_amd import workloads as wl
+
+    r32 = run_gpu(lb, wl, torch, "fp32", args.steps, args.warmup)
+    r64 = run_gpu(lb, wl, torch, "fp64", args.steps, args.warmup)
+    n = r32["n_sites"]
+    sups32 = args.steps * n / (r32["ms"] / 1e3)
+    sups64 = args.steps * n / (r64["ms"] / 1e3)
+
+    # roofline of the dominant kernel (the longer of the two stages)
+    stage = 1 if r32["corr_ms"] >= r32["pred_ms"] else 0
+    kms = r32["corr_ms"] if stage == 1 else r32["pred_ms"]
+    bytes_launch = site_bytes("fp32", stage) * n
+    achieved = bytes_launch / (kms / 1e3) / 1e9
+    step_bytes = (site_bytes("fp32", 0) + site_bytes("fp32", 1)) * n
+
+    w = 1.0
+    d = r32["obs"][:7] - r64["obs"][:7]
+    wts = np.array([1, 2, 2, 1, 2, 1, 1.0])[:, None, None]
+    rel = float(np.max(np.sqrt(np.sum(wts * d ** 2, 0)) / np.sqrt(np.sum(wts * r64["obs"][:7] ** 2, 0))))
+
+    out = {
+        "metric": "site-updates/s & HBM GB/s: FP32+FP64-match vs FP64 step at 1e-5 rel err",
+        "value": sups32,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256x256 Milne grid, dx 0.025 fm, Gaussian T0 0.4 GeV width 2 fm x (1 + 5% "
+                               "white noise, rng 2), eta/s 0.08, 5x5x8 momentum nodes, QCD-like "
+                               "crossover EoS on s/T^3 (g 37, Tc 0.17, w 0.02 GeV, kappa 2)",
+                   "sites": n, "nodes_per_site": N_NODES, "dtau_fm": r32["dtau"]},
+        "algorithmic_GBps_step": step_bytes * args.steps / (r32["ms"] / 1e3) / 1e9,
+        "fp64": {"value": sups64, "ms_per_step": r64["ms"] / args.steps,
+                 "pred_ms": r64["pred_ms"], "corr_ms": r64["corr_ms"]},
+        "fp32_vs_fp64_tmunu_rel_err": rel,
+        "kernels_ms": {"pred": r32["pred_ms"], "corr": r32["corr_ms"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage_kernel<float,5,5,%d>" % stage},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, r32["e0"], r32["dtau"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * lb.h - C ABI of the relativistic quasiparticle lattice-Boltzmann step
+ * (P. Romatschke, "Relativistic (Lattice) Boltzmann Equation with Non-Ideal
+ * Equation of State", arXiv:1108.5561), for AMD Instinct MI355X (gfx950).
+ *
+ * The library advances the on-shell distribution F_n(x, y) of one uncharged
+ * quasiparticle species with a temperature-dependent mass M(T), in
+ * boost-invariant Milne coordinates (tau, x, y, eta_s) with a periodic
+ * transverse (x, y) lattice.  Per lattice site and stage it forms T^{mu nu}
+ * over the discrete momenta (eq. (emtnew)), Landau-matches (eq. (sanity)),
+ * inverts the equation of state for T and M(T) (Sec. III.A), relaxes towards
+ * the equilibrium with the BGK term (eq. (bgk)) and streams with the Milne and
+ * mass-gradient force terms (eqs. (Bmilne), (newBeq)); a step is the
+ * predictor / trapezoid-corrector pair of Sec. IV.D.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Units: GeV (T, M), fm (tau, dx), GeV/fm^3 (energy density, T^{mu nu}),
+ *         fm^-3 (N^mu); hbar c = 0.1973269804 GeV fm.
+ *  Memory: every pointer named d_* is device memory on the current HIP
+ *         device, owned by the caller; the library never allocates or frees
+ *         device memory (it carves its buffers out of the caller's
+ *         workspace).  Host pointers (params, host arrays) are read during the
+ *         call only.
+ *  Streams: calls are asynchronous on the stream given to lb_init, except
+ *         lb_init itself, lb_status, lb_profile_read and the host-only
+ *         helpers, which return with the work finished.
+ *  Errors: every function returns LB_OK (0) or a negative LB_E_* code.
+ *         Argument errors are detected on the host before any device work
+ *         and change no state.  Errors found by the kernels (non-finite
+ *         values, no timelike eigenvector, temperature outside the table) set
+ *         a sticky device error word which lb_status returns.  lb_last_error
+ *         gives a thread-local message for the last failure.
+ *  Node order (canonical, used by lb_get_state / lb_set_state):
+ *         n = (k * n_theta + j) * (2 n_phi) + l, where k indexes the radial
+ *         nodes xi_k, j the polar nodes theta_j and l the azimuthal nodes
+ *         phi_l (Sec. IV.C).  Site order: site = y * nx + x.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_ctx lb_ctx; /* opaque, host memory owned by the library */
+
+enum {
+  LB_OK = 0,
+  LB_E_ARG = -1,       /* invalid argument, size or workspace */
+  LB_E_HIP = -2,       /* a HIP runtime call failed */
+  LB_E_EOS = -3,       /* EoS has no quasiparticle mass, is unstable, or a
+                          temperature left the table range */
+  LB_E_MATCH = -4,     /* Landau matching found no timelike eigenvector */
+  LB_E_NONFINITE = -5, /* non-finite input or state */
+  LB_E_STATE = -6,     /* call out of order (e.g. context not initialised) */
+  LB_E_NOTIMPL = -7    /* entry point not implemented in this build */
+};
+
+enum { LB_FP64 = 0, LB_FP32_FP64MATCH = 1 };          /* storage / node arithmetic */
+enum { LB_TAUR_CE = 0, LB_TAUR_MASSLESS = 1 };        /* how tau_R follows eta/s */
+enum { LB_METRIC_MILNE = 0, LB_METRIC_MINKOWSKI = 1 };
+enum { LB_EOS_TANH_P = 0, LB_EOS_CONST_MASS = 1, LB_EOS_TANH_S = 2 };
+
+/*
+ * Problem statement (Sec. IV.D: an initial condition is the distribution plus
+ * T and M; the step size; the relaxation time tau_R set through eta/s,
+ * eq. (bgk) and Sec. IV.A; the EoS through M(T), B(T), Sec. III.A; the
+ * momentum lattice N_xi, N_theta, N_phi, z0 = M0/T0, Sec. IV.C; the Milne
+ * metric and tau, Sec. IV.D).
+ */
+typedef struct lb_params {
+  int32_t n_xi;        /* radial nodes (roots of R_{N_xi}); this build: 5 */
+  int32_t n_theta;     /* polar nodes (roots of L_{N_theta}); this build: 5 */
+  int32_t n_phi;       /* azimuths phi_l = l pi / n_phi, l < 2 n_phi; this build: 4 */
+  double z0;           /* reference M0/T0 of the radial weight exp(-z0 cosh xi) (> 0) */
+  double Z;            /* degeneracy of eq. (feq) (> 0) */
+  int32_t nx, ny;      /* periodic transverse lattice, >= 1 each */
+  double dx_fm;        /* lattice spacing (> 0) */
+  double tau0_fm;      /* initial Milne time (> 0; any value for Minkowski) */
+  double eta_over_s;   /* > 0; +INFINITY means tau_R = infinity (free streaming) */
+  int32_t taur_rule;   /* LB_TAUR_CE: tau_R = (eta/s) s(T)/h(T) with h the
+                          Chapman-Enskog eta/tau_R of Sec. IV.A at M = M(T);
+                          LB_TAUR_MASSLESS: tau_R = 5 (eta/s)/T */
+  int32_t precision;   /* LB_FP64, or LB_FP32_FP64MATCH: FP32 distributions,
+                          streaming and moment sums, FP64 Landau matching,
+                          EoS inversion and mass evolution */
+  int32_t metric;      /* LB_METRIC_MILNE, or LB_METRIC_MINKOWSKI (no
+                          Christoffel term; for tests) */
+  int32_t eos_kind;    /* LB_EOS_TANH_S: s/T^3 = (2 pi^2/45) g (1 + tanh((T - Tc)/w))/2,
+                          p = int_0^T s dT' (c_s^2 in (0, 1/3] for any w);
+                          LB_EOS_TANH_P: p/T^4 = (pi^2/90) g (1 + tanh((T - Tc)/w))/2
+                          (c_s^2 > 1/3 above Tc; rejected where d eps/dT <= 0);
+                          LB_EOS_CONST_MASS: Boltzmann gas of mass eos_mass (B = 0) */
+  double eos_g;        /* g of the tanh EoS (Stefan-Boltzmann degrees of freedom) */
+  double eos_Tc_GeV;   /* Tc of the tanh EoS */
+  double eos_width_GeV;/* w of the tanh EoS */
+  double eos_mass_GeV; /* mass of the constant-mass EoS */
+  double T_min_GeV;    /* EoS table range; temperatures outside are an */
+  double T_max_GeV;    /*   LB_E_EOS device error (typ. 0.05 and 3.0) */
+} lb_params;
+
+/*
+ * Device workspace size in bytes for these parameters, or 0 on an invalid
+ * parameter set (message in lb_last_error).  Host only; no device call.
+ */
+size_t lb_workspace_bytes(const lb_params* p);
+
+/*
+ * Create a context and set the initial state (Sec. IV.D: the state is the
+ * distribution plus T and M).  Per site, T0 is the root of eps_EoS(T0) = e0
+ * on [T_min, T_max] (eps_EoS is monotone for an accepted EoS), M = M(T0), and
+ * F_n is the local equilibrium Z exp(-(u . P_n)/T0) with P_n = M V_n and
+ * u = (sqrt(1 + ux^2 + uy^2), ux, uy).
+ *   out         receives the context (host memory; free with lb_destroy).
+ *   p           parameters; copied.
+ *   d_workspace device buffer of at least lb_workspace_bytes(p) bytes, 256-byte
+ *               aligned, owned by the caller, not touched by anyone else
+ *               while the context lives.
+ *   d_e0        [ny][nx] FP64 energy density in GeV/fm^3 (read during the call).
+ *   d_ux0, d_uy0 [ny][nx] FP64 initial transverse flow, or NULL for zero.
+ *   hip_stream  the hipStream_t all later calls of this context run on
+ *               (NULL = the null stream).
+ * Builds the momentum lattice, the weak-form operators and the EoS tables on
+ * the host in FP64/long double and copies them into the workspace.  Returns
+ * LB_E_ARG on invalid parameters, LB_E_EOS if M(T) has no solution or the EoS
+ * is thermodynamically unstable (d eps/dT <= 0) anywhere in [T_min, T_max],
+ * LB_E_NONFINITE / LB_E_EOS if e0 is non-finite or outside the table; it
+ * synchronises the stream before returning.
+ */
+int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes,
+            const double* d_e0, const double* d_ux0, const double* d_uy0, void* hip_stream);
+
+/*
+ * Advance n_steps >= 0 Heun steps of size dtau_fm > 0 (Sec. IV.D: predictor
+ * F* = F + dtau K(F), corrector F_new = F + dtau/2 (K(F) + K(F*)), and the
+ * same for ln M).  Each step is two kernel launches.  Returns LB_E_ARG if
+ * dtau is not finite and positive or if the streaming CFL number
+ * max_n (|v^x_n| + |v^y_n|)/gamma_n * dtau/dx exceeds 0.5 (the stability
+ * limit of the second-order upwind transverse streaming under Heun).
+ */
+int lb_step(lb_ctx* c, int32_t n_steps, double dtau_fm);
+
+/*
+ * Per-site observables into d_out, FP64 [14][ny][nx]:
+ *   T^{tau tau}, T^{tau x}, T^{tau y}, T^{xx}, T^{xy}, T^{yy}, T^{YY}  (GeV/fm^3,
+ *     Milne-orthonormal components of eq. (emtnew), including B(T) g^{mu nu}),
+ *   N^tau, N^x, N^y (fm^-3, eq. (NTdisc)),
+ *   T (GeV) and u^x, u^y from Landau matching (eq. (sanity)), M (GeV).
+ */
+int lb_moments(lb_ctx* c, double* d_out);
+
+/* Current state in canonical order, FP64: d_F [N][ny][nx], d_lnM [ny][nx]
+ * (N = n_xi n_theta 2 n_phi), and the current Milne time (host). */
+int lb_get_state(lb_ctx* c, double* d_F, double* d_lnM, double* tau_fm);
+
+/* Replace the state (same layouts; FP32 contexts round to FP32) and the time.
+ * For checkpoint / restart and for tests that start both precisions from one
+ * state. */
+int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_fm);
+
+/*
+ * Reverse-mode adjoint of one lb_step (the differentiable form).  Not
+ * implemented in this build: returns LB_E_NOTIMPL and changes nothing.
+ */
+int lb_adjoint_step(lb_ctx* c, int32_t step_index, const void* d_fwd_state_k, void* d_adj_state,
+                    double* d_grad_eta_over_s, double* d_grad_e0);
+
+/* Synchronise the context's stream and return the sticky device error
+ * (LB_OK if none). */
+int lb_status(lb_ctx* c);
+
+/* Release the context (the workspace stays the caller's). */
+int lb_destroy(lb_ctx* c);
+
+/* Thread-local message of the last failure ("" if none). */
+const char* lb_last_error(void);
+
+/* ---- host-only helpers (no device call) ---- */
+
+/*
+ * Momentum lattice and factored weak-form operators as built for the device
+ * (Sec. IV.C, IV.D).  With out == NULL returns the number of doubles needed;
+ * otherwise fills out with
+ *   x_k = cosh xi_k [n_xi], w^xi_k [n_xi], mu_j = cos theta_j [n_theta],
+ *   w^theta_j [n_theta], cos phi_l [2 n_phi], sin phi_l [2 n_phi],
+ *   A1 [n_xi][n_xi], A2 [n_xi][n_xi], Ath [n_theta][n_theta]
+ * where on every phi slice S2[F]_{kj} = sum_k' A2_{kk'} F_{k'j} and
+ * S1[F]_{kj} = mu_j^2 sum_k' A1_{kk'} F_{k'j} - sum_j' Ath_{jj'} F_{kj'}.
+ * Returns the count, or a negative LB_E_* code.
+ */
+int64_t lb_lattice_info(const lb_params* p, double* out, int64_t n_out);
+
+/*
+ * Host evaluation of the equation of state at n temperatures T_GeV[i]:
+ * out[8 i + 0..7] = eps, p, s (GeV^4, GeV^4, GeV^3), M (GeV), B (GeV^4),
+ * eps - B (GeV^4), beta = dB/d(eps - B), tau_R (fm).  table != 0 evaluates
+ * the interpolated device tables instead of the exact functions (M, B,
+ * eps - B, beta, tau_R only; eps, p, s are then the exact values).
+ */
+int lb_eos_eval(const lb_params* p, int64_t n, const double* T_GeV, double* out, int32_t table);
+
+/* Kernel timing with HIP events on the context's stream: enable != 0 starts
+ * recording (and clears totals); lb_profile_read synchronises and returns the
+ * summed milliseconds and launch counts of the predictor [0] and corrector
+ * [1] stage kernels. */
+int lb_profile(lb_ctx* c, int32_t enable);
+int lb_profile_read(lb_ctx* c, double* ms_out, int64_t* count_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

@@ -230,6 +230,45 @@ class TanhEoS(QuasiparticleEoS):
         return self.c * (12 * T ** 2 * h0 + 8 * T ** 3 * h1 + T ** 4 * h2)
 
 
+class TanhEntropyEoS(QuasiparticleEoS):
+    """Synthetic QCD-like crossover on the entropy density:
+    s/T^3 = (2 pi^2/45) g (1 + tanh((T - Tc)/w)) / 2, p(T) = int_0^T s dT'.
+
+    The paper's quasiparticle construction takes s(T) as its input
+    (Sec. III.A: (eps + p)/T = Z M^3 K_3/(2 pi^2) = s).  With the crossover
+    on s/T^3 the speed of sound c_s^2 = s/(T s') = h/(3 h + T h') lies in
+    (0, 1/3] for every width, as for QCD; a tanh on p/T^4 instead has
+    c_s^2 > 1/3 above Tc (and d eps/dT < 0 for w = 0.02), where the
+    Chapman-Enskog bulk viscosity of Sec. IV.A is negative.
+    """
+
+    def __init__(self, g=37.0, Tc=0.17, width=0.02, kappa=2.0):
+        self.g, self.Tc, self.width, self.kappa = float(g), float(Tc), float(width), float(kappa)
+        self.Z = self.kappa * self.g * np.pi ** 4 / 90.0
+        self.cs = 4 * PI2 / 90.0 * self.g
+
+    def _h(self, T):
+        th = np.tanh((T - self.Tc) / self.width)
+        return 0.5 * (1 + th), 0.5 * (1 - th * th) / self.width
+
+    def s(self, T):
+        T = np.asarray(T, dtype=float)
+        return self.cs * T ** 3 * self._h(T)[0]
+
+    def ds(self, T):
+        T = np.asarray(T, dtype=float)
+        h0, h1 = self._h(T)
+        return self.cs * (3 * T ** 2 * h0 + T ** 3 * h1)
+
+    def p(self, T):
+        """p = int_0^T s dT' = cs T^4 int_0^1 t^3 h(t T) dt (adaptive quadrature)."""
+        T = np.asarray(T, dtype=float)
+        Tf = np.atleast_1d(T).ravel()
+        f = lambda t: t ** 3 * self._h(t * Tf)[0]
+        v, _ = quad_vec(f, 0.0, 1.0, epsabs=0.0, epsrel=1e-14, limit=4000)
+        return (self.cs * Tf ** 4 * v).reshape(T.shape)
+
+
 class ConstMassEoS(QuasiparticleEoS):
     """Boltzmann gas of constant mass M0 (Sec. II.A): B = 0, M(T) = M0."""
 

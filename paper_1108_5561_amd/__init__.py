@@ -1,0 +1,242 @@
+"""Python binding of liblbmi.so, the C-ABI library of the relativistic
+quasiparticle lattice-Boltzmann step (see include/lb.h for the contract).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  Importing this
+module fails loudly if the library has not been built
+(``python -m paper_1108_5561_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmi.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "lb.h")
+
+LB_OK, LB_E_ARG, LB_E_HIP, LB_E_EOS, LB_E_MATCH, LB_E_NONFINITE, LB_E_STATE, LB_E_NOTIMPL = 0, -1, -2, -3, -4, -5, -6, -7
+LB_FP64, LB_FP32_FP64MATCH = 0, 1
+LB_TAUR_CE, LB_TAUR_MASSLESS = 0, 1
+LB_METRIC_MILNE, LB_METRIC_MINKOWSKI = 0, 1
+LB_EOS_TANH_P, LB_EOS_CONST_MASS, LB_EOS_TANH_S = 0, 1, 2
+HBARC = 0.1973269804  # GeV fm
+N_OBS = 14
+OBS_NAMES = ("Ttt", "Ttx", "Tty", "Txx", "Txy", "Tyy", "TYY", "Nt", "Nx", "Ny", "T", "ux", "uy", "M")
+
+_ERR_NAMES = {LB_E_ARG: "LB_E_ARG", LB_E_HIP: "LB_E_HIP", LB_E_EOS: "LB_E_EOS", LB_E_MATCH: "LB_E_MATCH",
+              LB_E_NONFINITE: "LB_E_NONFINITE", LB_E_STATE: "LB_E_STATE", LB_E_NOTIMPL: "LB_E_NOTIMPL"}
+
+
+class LbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lb_params(ctypes.Structure):
+    _fields_ = [
+        ("n_xi", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32),
+        ("z0", ctypes.c_double), ("Z", ctypes.c_double),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("dx_fm", ctypes.c_double), ("tau0_fm", ctypes.c_double), ("eta_over_s", ctypes.c_double),
+        ("taur_rule", ctypes.c_int32), ("precision", ctypes.c_int32), ("metric", ctypes.c_int32),
+        ("eos_kind", ctypes.c_int32),
+        ("eos_g", ctypes.c_double), ("eos_Tc_GeV", ctypes.c_double), ("eos_width_GeV", ctypes.c_double),
+        ("eos_mass_GeV", ctypes.c_double), ("T_min_GeV", ctypes.c_double), ("T_max_GeV", ctypes.c_double),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1108_5561_amd.build`")
+    # torch bundles its own HIP runtime under the same soname
+    # (libamdhip64.so.7).  Loading torch first makes the dynamic loader bind
+    # the library to that copy, so one HIP runtime serves the process and
+    # device pointers and streams from torch are valid in the library.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(lb_params)
+    vp, dp, i32, i64, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "lb_workspace_bytes": (sz, [P]),
+        "lb_init": (ctypes.c_int, [ctypes.POINTER(vp), P, vp, sz, vp, vp, vp, vp]),
+        "lb_step": (ctypes.c_int, [vp, i32, ctypes.c_double]),
+        "lb_moments": (ctypes.c_int, [vp, vp]),
+        "lb_get_state": (ctypes.c_int, [vp, vp, vp, dp]),
+        "lb_set_state": (ctypes.c_int, [vp, vp, vp, ctypes.c_double]),
+        "lb_adjoint_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
+        "lb_status": (ctypes.c_int, [vp]),
+        "lb_destroy": (ctypes.c_int, [vp]),
+        "lb_last_error": (ctypes.c_char_p, []),
+        "lb_lattice_info": (i64, [P, dp, i64]),
+        "lb_eos_eval": (ctypes.c_int, [P, i64, dp, dp, i32]),
+        "lb_profile": (ctypes.c_int, [vp, i32]),
+        "lb_profile_read": (ctypes.c_int, [vp, dp, ctypes.POINTER(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def header_functions():
+    """Names of the functions declared in include/lb.h."""
+    txt = open(HEADER_PATH).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_]+)\s*\(", txt)))
+
+
+def last_error():
+    return lib.lb_last_error().decode()
+
+
+def check(rc):
+    if rc != LB_OK:
+        raise LbError(rc, last_error())
+    return rc
+
+
+def degeneracy(kappa, g):
+    """Z = kappa g pi^4/90 (g bosonic-equivalent degrees of freedom)."""
+    return kappa * g * math.pi ** 4 / 90.0
+
+
+def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, metric=LB_METRIC_MILNE,
+                taur_rule=LB_TAUR_CE, eos_kind=LB_EOS_TANH_S, eos_g=37.0, eos_Tc_GeV=0.17, eos_width_GeV=0.02,
+                eos_mass_GeV=0.0, kappa=2.0, Z=None, z0=1.0, n_xi=5, n_theta=5, n_phi=4,
+                T_min_GeV=0.05, T_max_GeV=3.0):
+    p = lb_params()
+    p.n_xi, p.n_theta, p.n_phi, p.z0 = n_xi, n_theta, n_phi, z0
+    p.Z = degeneracy(kappa, eos_g) if Z is None else Z
+    p.nx, p.ny, p.dx_fm, p.tau0_fm, p.eta_over_s = nx, ny, dx_fm, tau0_fm, eta_over_s
+    p.taur_rule, p.precision, p.metric, p.eos_kind = taur_rule, precision, metric, eos_kind
+    p.eos_g, p.eos_Tc_GeV, p.eos_width_GeV, p.eos_mass_GeV = eos_g, eos_Tc_GeV, eos_width_GeV, eos_mass_GeV
+    p.T_min_GeV, p.T_max_GeV = T_min_GeV, T_max_GeV
+    return p
+
+
+def workspace_bytes(p):
+    n = lib.lb_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise LbError(LB_E_ARG, last_error())
+    return n
+
+
+def lattice_info(p):
+    """dict of the lattice and factored operators (lb_lattice_info)."""
+    import numpy as np
+    n = lib.lb_lattice_info(ctypes.byref(p), None, 0)
+    if n < 0:
+        raise LbError(int(n), last_error())
+    buf = (ctypes.c_double * n)()
+    r = lib.lb_lattice_info(ctypes.byref(p), buf, n)
+    if r < 0:
+        raise LbError(int(r), last_error())
+    a = np.frombuffer(buf, dtype=np.float64).copy()
+    nxi, nth, nph = p.n_xi, p.n_theta, 2 * p.n_phi
+    out, o = {}, 0
+    for name, size, shape in [("x", nxi, None), ("w_xi", nxi, None), ("mu", nth, None), ("w_th", nth, None),
+                              ("cos", nph, None), ("sin", nph, None), ("A1", nxi * nxi, (nxi, nxi)),
+                              ("A2", nxi * nxi, (nxi, nxi)), ("Ath", nth * nth, (nth, nth))]:
+        v = a[o:o + size]
+        out[name] = v.reshape(shape) if shape else v
+        o += size
+    return out
+
+
+def eos_eval(p, T, table=False):
+    """(n, 8) array: eps, p, s, M, B, eps-B, beta, tau_R (lb_eos_eval)."""
+    import numpy as np
+    T = np.ascontiguousarray(np.atleast_1d(np.asarray(T, dtype=np.float64)))
+    out = np.zeros((T.size, 8))
+    dptr = ctypes.POINTER(ctypes.c_double)
+    check(lib.lb_eos_eval(ctypes.byref(p), T.size, T.ctypes.data_as(dptr), out.ctypes.data_as(dptr), int(table)))
+    return out
+
+
+class Context:
+    """One lattice-Boltzmann state on the current GPU (lb_init .. lb_destroy).
+
+    Device memory (workspace, inputs, outputs) is held in torch tensors; the
+    library runs on torch's current stream.
+    """
+
+    def __init__(self, params, e0, ux0=None, uy0=None, device=None):
+        import torch
+        self.torch = torch
+        self.params = params
+        dev = e0.device if device is None else torch.device(device)
+        if dev.type != "cuda":
+            raise LbError(LB_E_ARG, "inputs must be GPU tensors")
+        for t in (e0, ux0, uy0):
+            if t is not None and (t.dtype != torch.float64 or tuple(t.shape) != (params.ny, params.nx)
+                                  or not t.is_contiguous() or t.device != dev):
+                raise LbError(LB_E_ARG, "e0/ux0/uy0 must be contiguous float64 [ny, nx] on the same GPU")
+        self.device = dev
+        nbytes = workspace_bytes(params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        self._ctx = ctypes.c_void_p()
+        check(lib.lb_init(ctypes.byref(self._ctx), ctypes.byref(params), self.workspace.data_ptr(), nbytes,
+                          e0.data_ptr(), ux0.data_ptr() if ux0 is not None else None,
+                          uy0.data_ptr() if uy0 is not None else None, self.stream.cuda_stream))
+        self.N = params.n_xi * params.n_theta * 2 * params.n_phi
+
+    def step(self, n_steps, dtau_fm):
+        check(lib.lb_step(self._ctx, int(n_steps), float(dtau_fm)))
+
+    def moments(self, out=None):
+        torch = self.torch
+        if out is None:
+            out = torch.empty((N_OBS, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
+        check(lib.lb_moments(self._ctx, out.data_ptr()))
+        return out
+
+    def get_state(self):
+        torch = self.torch
+        F = torch.empty((self.N, self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
+        lnM = torch.empty((self.params.ny, self.params.nx), dtype=torch.float64, device=self.device)
+        tau = ctypes.c_double()
+        check(lib.lb_get_state(self._ctx, F.data_ptr(), lnM.data_ptr(), ctypes.byref(tau)))
+        return F, lnM, tau.value
+
+    def set_state(self, F, lnM, tau_fm):
+        torch = self.torch
+        if F.dtype != torch.float64 or lnM.dtype != torch.float64 or not F.is_contiguous() or not lnM.is_contiguous():
+            raise LbError(LB_E_ARG, "F and lnM must be contiguous float64")
+        if tuple(F.shape) != (self.N, self.params.ny, self.params.nx) or tuple(lnM.shape) != (self.params.ny, self.params.nx):
+            raise LbError(LB_E_ARG, "state shape mismatch")
+        check(lib.lb_set_state(self._ctx, F.data_ptr(), lnM.data_ptr(), float(tau_fm)))
+
+    def status(self):
+        return lib.lb_status(self._ctx)
+
+    def profile(self, enable):
+        check(lib.lb_profile(self._ctx, int(enable)))
+
+    def profile_read(self):
+        ms = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int64 * 2)()
+        check(lib.lb_profile_read(self._ctx, ms, cnt))
+        return (ms[0], ms[1]), (cnt[0], cnt[1])
+
+    def adjoint_step(self, *args):
+        return lib.lb_adjoint_step(self._ctx, 0, None, None, None, None)
+
+    def close(self):
+        if self._ctx:
+            lib.lb_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

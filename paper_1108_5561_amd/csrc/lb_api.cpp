@@ -1,0 +1,460 @@
+// C ABI of the lattice-Boltzmann library: parameter validation, workspace
+// carving, host setup upload, kernel launches (declarations in include/lb.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lb.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+using namespace lbmi;
+
+struct lb_ctx {
+  lb_params p;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* F[3] = {nullptr, nullptr, nullptr};
+  double* lnM[3] = {nullptr, nullptr, nullptr};
+  int cur = 0;  // index of the current state
+  int* err = nullptr;
+  EosTable tb{};
+  HostLattice lat;
+  LatticeConst<float, 5, 5> cf{};
+  LatticeConst<double, 5, 5> cd{};
+  double tau = 0;
+  bool initialised = false;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // 3 per step
+  size_t ev_used = 0;
+  double prof_ms[2] = {0, 0};
+  int64_t prof_n[2] = {0, 0};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t F[3], lnM[3], pts, inv_ek, inv_ee, err, total;
+};
+
+std::string validate(const lb_params* p) {
+  if (!p) return "params is NULL";
+  if (p->n_xi != 5 || p->n_theta != 5 || p->n_phi != 4)
+    return "this build supports n_xi = n_theta = 5 and n_phi = 4";
+  if (!(p->z0 > 0) || !std::isfinite(p->z0)) return "z0 must be finite and > 0";
+  if (!(p->Z > 0) || !std::isfinite(p->Z)) return "Z must be finite and > 0";
+  if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
+  if ((int64_t)p->nx * p->ny * 8 > (int64_t)INT32_MAX) return "grid too large (nx*ny*8 must fit in int32)";
+  if (!(p->dx_fm > 0) || !std::isfinite(p->dx_fm)) return "dx_fm must be finite and > 0";
+  if (!std::isfinite(p->tau0_fm)) return "tau0_fm must be finite";
+  if (p->metric == LB_METRIC_MILNE && !(p->tau0_fm > 0)) return "tau0_fm must be > 0 for the Milne metric";
+  if (p->metric != LB_METRIC_MILNE && p->metric != LB_METRIC_MINKOWSKI) return "unknown metric";
+  if (!(p->eta_over_s > 0)) return "eta_over_s must be > 0 (or +inf)";
+  if (p->taur_rule != LB_TAUR_CE && p->taur_rule != LB_TAUR_MASSLESS) return "unknown taur_rule";
+  if (p->precision != LB_FP64 && p->precision != LB_FP32_FP64MATCH) return "unknown precision";
+  if (p->eos_kind == LB_EOS_TANH_P || p->eos_kind == LB_EOS_TANH_S) {
+    if (!(p->eos_g > 0) || !(p->eos_width_GeV > 0) || !std::isfinite(p->eos_Tc_GeV))
+      return "tanh EoS needs g > 0, width > 0, finite Tc";
+  } else if (p->eos_kind == LB_EOS_CONST_MASS) {
+    if (!(p->eos_mass_GeV > 0) || !std::isfinite(p->eos_mass_GeV)) return "constant-mass EoS needs mass > 0";
+  } else {
+    return "unknown eos_kind";
+  }
+  if (!(p->T_min_GeV > 0) || !(p->T_max_GeV > 2 * p->T_min_GeV) || !std::isfinite(p->T_max_GeV))
+    return "need 0 < T_min and T_max > 2 T_min";
+  return "";
+}
+
+Layout layout(const lb_params* p) {
+  Layout L;
+  const size_t sites = (size_t)p->nx * p->ny;
+  const size_t nodes = (size_t)p->n_xi * p->n_theta * 2 * p->n_phi;
+  const size_t elt = p->precision == LB_FP64 ? 8 : 4;
+  size_t off = 0;
+  for (int i = 0; i < 3; ++i) {
+    L.F[i] = off;
+    off = align_up(off + nodes * sites * elt);
+  }
+  for (int i = 0; i < 3; ++i) {
+    L.lnM[i] = off;
+    off = align_up(off + sites * 8);
+  }
+  L.pts = off;
+  off = align_up(off + (size_t)kTablePoints * kFields * 8);
+  L.inv_ek = off;
+  off = align_up(off + (size_t)kInvPoints * 8);
+  L.inv_ee = off;
+  off = align_up(off + (size_t)kInvPoints * 8);
+  L.err = off;
+  off = align_up(off + 256);
+  L.total = off;
+  return L;
+}
+
+template <typename R>
+void fill_const(const HostLattice& L, LatticeConst<R, 5, 5>* C) {
+  const int nxi = 5, nth = 5;
+  for (int k = 0; k < nxi; ++k) {
+    C->x[k] = (R)L.x[k];
+    C->inv_x[k] = (R)(1.0 / L.x[k]);
+    C->sh2[k] = (R)(L.x[k] * L.x[k] - 1.0);
+  }
+  for (int j = 0; j < nth; ++j) C->mu2[j] = (R)(L.mu[j] * L.mu[j]);
+  for (int k = 0; k < nxi; ++k)
+    for (int j = 0; j < nth; ++j) {
+      const int q = k * nth + j;
+      const double sh = std::sqrt(L.x[k] * L.x[k] - 1.0);
+      const double sth = std::sqrt(1.0 - L.mu[j] * L.mu[j]);
+      const double sig = sh * sth, vY = sh * L.mu[j];
+      const double w = std::exp(L.z0 * L.x[k]) * L.wxi[k] * L.wth[j] / (4.0 * L.nphi);
+      C->sig[q] = (R)sig;
+      C->vY[q] = (R)vY;
+      C->w[q] = (R)w;
+      C->wx2[q] = (R)(w * L.x[k] * L.x[k]);
+      C->wxs[q] = (R)(w * L.x[k] * sig);
+      C->ws2[q] = (R)(w * sig * sig);
+      C->wvY2[q] = (R)(w * vY * vY);
+      C->wx[q] = (R)(w * L.x[k]);
+    }
+  for (int i = 0; i < nxi * nxi; ++i) {
+    C->A1[i] = (R)L.A1[i];
+    C->A2[i] = (R)L.A2[i];
+  }
+  for (int i = 0; i < nth * nth; ++i) C->Ath[i] = (R)L.Ath[i];
+  for (int l = 0; l < 8; ++l) {
+    C->cosl[l] = (R)L.cosl[l];
+    C->sinl[l] = (R)L.sinl[l];
+  }
+}
+
+StageArgs stage_args(const lb_ctx* c, double tau, double dtau) {
+  StageArgs a;
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.n_sites = c->p.nx * c->p.ny;
+  a.metric = c->p.metric;
+  a.inv2dx = 0.5 / c->p.dx_fm;
+  a.inv_dx = 1.0 / c->p.dx_fm;
+  a.tau = tau;
+  a.dtau = dtau;
+  a.inv_eta_hbarc = std::isinf(c->p.eta_over_s) ? 0.0 : 1.0 / (c->p.eta_over_s * kHbarC);
+  a.Z = c->p.Z;
+  return a;
+}
+
+const void* lat_const(const lb_ctx* c) {
+  return c->p.precision == LB_FP64 ? (const void*)&c->cd : (const void*)&c->cf;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(LB_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int read_err(lb_ctx* c) {
+  int h = 0;
+  hipError_t e = hipMemcpyAsync(&h, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(error word)");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  if (h & kErrNonfinite) return fail(LB_E_NONFINITE, "device: non-finite value in the state or input");
+  if (h & kErrMatch) return fail(LB_E_MATCH, "device: Landau matching found no timelike eigenvector");
+  if (h & kErrEos) return fail(LB_E_EOS, "device: temperature or energy density outside the EoS table");
+  return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+size_t lb_workspace_bytes(const lb_params* p) {
+  std::string m = validate(p);
+  if (!m.empty()) {
+    fail(LB_E_ARG, m);
+    return 0;
+  }
+  return layout(p).total;
+}
+
+int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes, const double* d_e0,
+            const double* d_ux0, const double* d_uy0, void* hip_stream) {
+  g_err.clear();
+  if (!out) return fail(LB_E_ARG, "out is NULL");
+  *out = nullptr;
+  std::string m = validate(p);
+  if (!m.empty()) return fail(LB_E_ARG, m);
+  if (!d_workspace) return fail(LB_E_ARG, "workspace is NULL");
+  if ((uintptr_t)d_workspace % kAlign) return fail(LB_E_ARG, "workspace must be 256-byte aligned");
+  if (!d_e0) return fail(LB_E_ARG, "e0 is NULL");
+  Layout L = layout(p);
+  if (ws_bytes < L.total)
+    return fail(LB_E_ARG, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  lb_ctx* c = new lb_ctx();
+  c->p = *p;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)d_workspace;
+  c->ws_bytes = ws_bytes;
+  m = build_lattice(*p, &c->lat);
+  if (!m.empty()) {
+    delete c;
+    return fail(LB_E_ARG, m);
+  }
+  HostTables T;
+  m = build_tables(*p, &T);
+  if (!m.empty()) {
+    delete c;
+    return fail(LB_E_EOS, m);
+  }
+  fill_const(c->lat, &c->cf);
+  fill_const(c->lat, &c->cd);
+  for (int i = 0; i < 3; ++i) {
+    c->F[i] = c->ws + L.F[i];
+    c->lnM[i] = (double*)(c->ws + L.lnM[i]);
+  }
+  double* d_pts = (double*)(c->ws + L.pts);
+  double* d_iek = (double*)(c->ws + L.inv_ek);
+  double* d_iee = (double*)(c->ws + L.inv_ee);
+  c->err = (int*)(c->ws + L.err);
+  c->tb = T.desc;
+  c->tb.pts = d_pts;
+  c->tb.inv_ek = d_iek;
+  c->tb.inv_ee = d_iee;
+  hipError_t e;
+  if ((e = hipGetDevice(&c->device)) != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
+  // synchronous copies: the host staging buffers die with this call
+  if ((e = hipMemcpy(d_pts, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_iek, T.inv_ek.data(), T.inv_ek.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_iee, T.inv_ee.data(), T.inv_ee.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemsetAsync(c->err, 0, sizeof(int), c->stream)) != hipSuccess) {
+    delete c;
+    return hip_fail(e, "upload of EoS tables");
+  }
+  c->tau = p->tau0_fm;
+  c->cur = 0;
+  StageArgs a = stage_args(c, c->tau, 0.0);
+  if ((e = launch_init(p->precision, d_e0, d_ux0, d_uy0, c->F[0], c->lnM[0], lat_const(c), c->tb, a, c->err,
+                       c->stream)) != hipSuccess) {
+    delete c;
+    return hip_fail(e, "init kernel launch");
+  }
+  int rc = read_err(c);
+  if (rc != LB_OK) {
+    delete c;
+    return rc;
+  }
+  c->initialised = true;
+  *out = c;
+  return LB_OK;
+}
+
+int lb_step(lb_ctx* c, int32_t n_steps, double dtau) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  if (n_steps < 0) return fail(LB_E_ARG, "n_steps must be >= 0");
+  if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
+  const double cfl = c->lat.vsum_max * dtau / c->p.dx_fm;
+  if (cfl > 0.5)
+    return fail(LB_E_ARG, "CFL number " + std::to_string(cfl) + " > 0.5 (reduce dtau or increase dx)");
+  const int prec = c->p.precision;
+  const void* lc = lat_const(c);
+  for (int s = 0; s < n_steps; ++s) {
+    const int i0 = c->cur, i1 = (c->cur + 1) % 3, i2 = (c->cur + 2) % 3;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (c->prof) {
+      while (c->ev.size() < c->ev_used + 3) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return fail(LB_E_HIP, "hipEventCreate");
+        c->ev.push_back(ev);
+      }
+      e0 = c->ev[c->ev_used];
+      e1 = c->ev[c->ev_used + 1];
+      e2 = c->ev[c->ev_used + 2];
+      c->ev_used += 3;
+      hipEventRecord(e0, c->stream);
+    }
+    StageArgs a = stage_args(c, c->tau, dtau);
+    hipError_t e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], lc,
+                                c->tb, a, c->err, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "predictor launch");
+    if (c->prof) hipEventRecord(e1, c->stream);
+    a.tau = c->tau + dtau;
+    e = launch_stage(prec, 1, c->F[i1], c->F[i0], c->F[i2], c->lnM[i1], c->lnM[i0], c->lnM[i2], lc, c->tb, a,
+                     c->err, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "corrector launch");
+    if (c->prof) hipEventRecord(e2, c->stream);
+    c->cur = i2;
+    c->tau += dtau;
+  }
+  return LB_OK;
+}
+
+int lb_moments(lb_ctx* c, double* d_out) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  if (!d_out) return fail(LB_E_ARG, "out is NULL");
+  StageArgs a = stage_args(c, c->tau, 0.0);
+  hipError_t e = launch_moments(c->p.precision, c->F[c->cur], c->lnM[c->cur], d_out, lat_const(c), c->tb, a,
+                                c->err, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "moments launch");
+  return LB_OK;
+}
+
+int lb_get_state(lb_ctx* c, double* d_F, double* d_lnM, double* tau_fm) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  const int n_sites = c->p.nx * c->p.ny, n_q = c->p.n_xi * c->p.n_theta;
+  if (d_F) {
+    hipError_t e = launch_get_state(c->p.precision, c->F[c->cur], d_F, n_q, n_sites, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "get_state launch");
+  }
+  if (d_lnM) {
+    hipError_t e = hipMemcpyAsync(d_lnM, c->lnM[c->cur], (size_t)n_sites * 8, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy of ln M");
+  }
+  if (tau_fm) *tau_fm = c->tau;
+  return LB_OK;
+}
+
+int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_fm) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  if (!d_F || !d_lnM) return fail(LB_E_ARG, "F and lnM must be given");
+  if (!std::isfinite(tau_fm) || (c->p.metric == LB_METRIC_MILNE && !(tau_fm > 0)))
+    return fail(LB_E_ARG, "tau must be finite (and > 0 for Milne)");
+  const int n_sites = c->p.nx * c->p.ny, n_q = c->p.n_xi * c->p.n_theta;
+  hipError_t e = launch_set_state(c->p.precision, d_F, c->F[c->cur], n_q, n_sites, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "set_state launch");
+  e = hipMemcpyAsync(c->lnM[c->cur], d_lnM, (size_t)n_sites * 8, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "copy of ln M");
+  c->tau = tau_fm;
+  return LB_OK;
+}
+
+int lb_adjoint_step(lb_ctx* c, int32_t, const void*, void*, double*, double*) {
+  (void)c;
+  return fail(LB_E_NOTIMPL, "lb_adjoint_step is not implemented in this build");
+}
+
+int lb_status(lb_ctx* c) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  return read_err(c);
+}
+
+int lb_destroy(lb_ctx* c) {
+  if (!c) return LB_OK;
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  delete c;
+  return LB_OK;
+}
+
+int lb_profile(lb_ctx* c, int32_t enable) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  if (enable) {
+    hipStreamSynchronize(c->stream);
+    c->ev_used = 0;
+  }
+  c->prof = enable != 0;
+  c->prof_ms[0] = c->prof_ms[1] = 0;
+  c->prof_n[0] = c->prof_n[1] = 0;
+  return LB_OK;
+}
+
+int lb_profile_read(lb_ctx* c, double* ms_out, int64_t* count_out) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (size_t i = 0; i + 2 < c->ev_used; i += 3) {
+    float a = 0, b = 0;
+    hipEventElapsedTime(&a, c->ev[i], c->ev[i + 1]);
+    hipEventElapsedTime(&b, c->ev[i + 1], c->ev[i + 2]);
+    c->prof_ms[0] += a;
+    c->prof_ms[1] += b;
+    c->prof_n[0] += 1;
+    c->prof_n[1] += 1;
+  }
+  c->ev_used = 0;
+  if (ms_out) {
+    ms_out[0] = c->prof_ms[0];
+    ms_out[1] = c->prof_ms[1];
+  }
+  if (count_out) {
+    count_out[0] = c->prof_n[0];
+    count_out[1] = c->prof_n[1];
+  }
+  return LB_OK;
+}
+
+int64_t lb_lattice_info(const lb_params* p, double* out, int64_t n_out) {
+  if (!p) return fail(LB_E_ARG, "params is NULL");
+  if (p->n_xi < 1 || p->n_theta < 1 || p->n_phi < 1 || !(p->z0 > 0))
+    return fail(LB_E_ARG, "need n_xi, n_theta, n_phi >= 1 and z0 > 0");
+  const int64_t nxi = p->n_xi, nth = p->n_theta, nph = 2 * p->n_phi;
+  const int64_t need = 2 * nxi + 2 * nth + 2 * nph + 2 * nxi * nxi + nth * nth;
+  if (!out) return need;
+  if (n_out < need) return fail(LB_E_ARG, "output too small");
+  HostLattice L;
+  std::string m = build_lattice(*p, &L);
+  if (!m.empty()) return fail(LB_E_ARG, m);
+  double* o = out;
+  for (auto* v : {&L.x, &L.wxi, &L.mu, &L.wth, &L.cosl, &L.sinl, &L.A1, &L.A2, &L.Ath})
+    for (double d : *v) *o++ = d;
+  return need;
+}
+
+int lb_eos_eval(const lb_params* p, int64_t n, const double* T, double* out, int32_t table) {
+  std::string m = validate(p);
+  if (!m.empty()) return fail(LB_E_ARG, m);
+  if (n < 0 || (n > 0 && (!T || !out))) return fail(LB_E_ARG, "bad arrays");
+  HostEos eos(*p);
+  HostTables tabs;
+  if (table) {
+    m = build_tables(*p, &tabs);
+    if (!m.empty()) return fail(LB_E_EOS, m);
+  }
+  double zg = 2.0;
+  for (int64_t i = 0; i < n; ++i) {
+    HostEos::Point pt;
+    double zu;
+    if (!(T[i] > 0) || !eos.eval(T[i], zg, &pt, &zu)) return fail(LB_E_EOS, "no quasiparticle mass at T");
+    zg = zu;
+    double tauR = std::isinf(p->eta_over_s) ? INFINITY : p->eta_over_s * kHbarC * pt.q / T[i];
+    if (table) {
+      double t, w[4], dw[4];
+      const double u = std::log(T[i]);
+      const int j = eos_locate(tabs.desc, u, &t);
+      lagrange4(t, w, dw);
+      pt.M = eos_field(tabs.desc, j, w, kZ) * T[i];
+      pt.B = eos_field(tabs.desc, j, w, kBt4) * T[i] * T[i] * T[i] * T[i];
+      pt.ekin = std::exp(eos_field(tabs.desc, j, w, kLnEk));
+      pt.beta = eos_field(tabs.desc, j, w, kBeta);
+      const double q = eos_field(tabs.desc, j, w, kQ);
+      tauR = std::isinf(p->eta_over_s) ? INFINITY : p->eta_over_s * kHbarC * q / T[i];
+    }
+    double* o = out + 8 * i;
+    o[0] = pt.eps;
+    o[1] = pt.p;
+    o[2] = pt.s;
+    o[3] = pt.M;
+    o[4] = pt.B;
+    o[5] = pt.ekin;
+    o[6] = pt.beta;
+    o[7] = tauR;
+  }
+  return LB_OK;
+}
+
+}  // extern "C"

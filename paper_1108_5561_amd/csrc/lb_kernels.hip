@@ -1,0 +1,491 @@
+// Device kernels of the Milne quasiparticle lattice-Boltzmann step for
+// gfx950 (paper Sec. IV.D, eqs. (Bmilne), (newBeq), (bgk), (sanity),
+// (emtnew), (masschange)).
+//
+// Work mapping: eight lanes per lattice site, lane l owning the phi_l slice
+// (N_xi x N_theta nodes) of that site.  The weak-form operators S1, S2 act
+// within one phi slice, so they are lane-local; the moments and the mass
+// evolution sums are reduced over the eight lanes with xor shuffles (all
+// lanes end with bitwise-identical sums, so the per-site FP64 work they
+// repeat gives identical results).
+//
+// Distribution layout in HBM: F[q][site][l], q = k * N_theta + j, so a wave
+// (8 sites x 8 slices) reads and writes 64 consecutive values per node.
+#include <hip/hip_runtime.h>
+
+#include "../../include/lb.h"
+#include "kernels.hpp"
+#include "lb_common.hpp"
+
+namespace lbmi {
+
+constexpr int kSl = 8;        // phi slices (n_phi = 4)
+constexpr int kBlock = 256;   // 32 sites per block
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+template <typename R>
+__device__ __forceinline__ R sum8(R v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+
+template <typename R>
+__device__ __forceinline__ R rexp(R x);
+template <>
+__device__ __forceinline__ float rexp<float>(float x) { return expf(x); }
+template <>
+__device__ __forceinline__ double rexp<double>(double x) { return exp(x); }
+
+template <typename R>
+__device__ __forceinline__ R rsqrt_(R x);
+template <>
+__device__ __forceinline__ float rsqrt_<float>(float x) { return sqrtf(x); }
+template <>
+__device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
+
+__device__ __forceinline__ void flag(int* err, int bit) { atomicOr(err, bit); }
+
+// Landau matching (eq. (sanity)) of the 3x3 (tau, x, y) block.  t = {Ttt, Ttx,
+// Tty, Txx, Txy, Tyy}.  lambda is the largest root of det(lambda - T g), by
+// Newton from T^{tau tau} (an upper bound, reached monotonically from
+// above); u is the null vector of T g - lambda (a cross product of two rows),
+// normalised to u.u = 1, u^tau > 0.
+__device__ inline bool landau3(const double t[6], double* lam_out, double u[3]) {
+  const double t00 = t[0], t01 = t[1], t02 = t[2], t11 = t[3], t12 = t[4], t22 = t[5];
+  const double c2 = t00 - t11 - t22;
+  const double c1 = (t01 * t01 - t00 * t11) + (t02 * t02 - t00 * t22) + (t11 * t22 - t12 * t12);
+  const double c0 = t00 * (t11 * t22 - t12 * t12) - t01 * (t01 * t22 - t12 * t02) + t02 * (t01 * t12 - t11 * t02);
+  double lam = t00;
+  for (int it = 0; it < 60; ++it) {
+    const double p = ((lam - c2) * lam + c1) * lam - c0;
+    const double dp = (3.0 * lam - 2.0 * c2) * lam + c1;
+    const double d = p / dp;
+    if (!(d > 0.0)) break;  // monotone from above: done once the step vanishes
+    lam -= d;
+    if (d <= 1e-16 * fabs(lam)) break;
+  }
+  const double r0[3] = {t00 - lam, -t01, -t02};
+  const double r1[3] = {t01, -t11 - lam, -t12};
+  const double r2[3] = {t02, -t12, -t22 - lam};
+  double c[3][3];
+  c[0][0] = r0[1] * r1[2] - r0[2] * r1[1];
+  c[0][1] = r0[2] * r1[0] - r0[0] * r1[2];
+  c[0][2] = r0[0] * r1[1] - r0[1] * r1[0];
+  c[1][0] = r0[1] * r2[2] - r0[2] * r2[1];
+  c[1][1] = r0[2] * r2[0] - r0[0] * r2[2];
+  c[1][2] = r0[0] * r2[1] - r0[1] * r2[0];
+  c[2][0] = r1[1] * r2[2] - r1[2] * r2[1];
+  c[2][1] = r1[2] * r2[0] - r1[0] * r2[2];
+  c[2][2] = r1[0] * r2[1] - r1[1] * r2[0];
+  int best = 0;
+  double bn = -1.0;
+  for (int i = 0; i < 3; ++i) {
+    const double n2 = c[i][0] * c[i][0] + c[i][1] * c[i][1] + c[i][2] * c[i][2];
+    if (n2 > bn) { bn = n2; best = i; }
+  }
+  const double mn = c[best][0] * c[best][0] - c[best][1] * c[best][1] - c[best][2] * c[best][2];
+  *lam_out = lam;
+  if (!(mn > 0.0) || !(lam > 0.0)) {
+    u[0] = 1.0; u[1] = 0.0; u[2] = 0.0;
+    return false;
+  }
+  double sc = 1.0 / sqrt(mn);
+  if (c[best][0] < 0.0) sc = -sc;
+  u[0] = c[best][0] * sc;
+  u[1] = c[best][1] * sc;
+  u[2] = c[best][2] * sc;
+  return true;
+}
+
+// Temperature from lambda = eps_kin,eq(T) and the EoS functions there.
+struct EosAt {
+  double T, M_eq, beta, q, Bt4;
+};
+
+__device__ inline bool eos_from_lambda(const EosTable& tb, double lam, EosAt* o) {
+  double u;
+  bool ok = (lam > 0.0) && eos_invert(tb, kLnEk, tb.inv_ek, tb.gk0, tb.gk_h, tb.gk_inv_h, log(lam), &u);
+  if (!ok) u = (lam > 0.0 && log(lam) > tb.gk0) ? tb.u_hi : tb.u_lo;
+  if (u < tb.u_lo) { u = tb.u_lo; ok = false; }
+  if (u > tb.u_hi) { u = tb.u_hi; ok = false; }
+  double t, w[4], dw[4];
+  const int i = eos_locate(tb, u, &t);
+  lagrange4(t, w, dw);
+  o->T = exp(u);
+  o->M_eq = eos_field(tb, i, w, kZ) * o->T;
+  o->beta = eos_field(tb, i, w, kBeta);
+  o->q = eos_field(tb, i, w, kQ);
+  o->Bt4 = eos_field(tb, i, w, kBt4);
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
+// One Heun stage (Sec. IV.D).  STAGE 0 = predictor, 1 = corrector.
+template <typename R, int NXI, int NTH, int STAGE>
+__global__ __launch_bounds__(kBlock) void stage_kernel(
+    const R* __restrict__ Fin, const R* __restrict__ Fbase, R* __restrict__ Fout,
+    const double* __restrict__ lnMin, const double* __restrict__ lnMbase, double* __restrict__ lnMout,
+    const LatticeConst<R, NXI, NTH> C, const EosTable tb, const StageArgs a, int* __restrict__ err) {
+  constexpr int Q = NXI * NTH;
+  const int tid = blockIdx.x * kBlock + threadIdx.x;
+  const int site = tid >> 3;
+  const int l = tid & 7;
+  if (site >= a.n_sites) return;  // whole 8-lane groups leave together
+  const int y = site / a.nx;
+  const int x = site - y * a.nx;
+  const size_t plane = (size_t)a.n_sites * kSl;
+  const size_t me = (size_t)site * kSl + l;
+
+  // ---- load the slice and accumulate partial moments (eq. (emtnew)) ----
+  R f[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) f[q] = Fin[q * plane + me];
+  R p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    p0 += C.wx2[q] * f[q];
+    p1 += C.wxs[q] * f[q];
+    p2 += C.ws2[q] * f[q];
+    p3 += C.w[q] * f[q];
+  }
+  const R cl = C.cosl[l], sl = C.sinl[l];
+  R m00 = sum8(p0), m01 = sum8(p1 * cl), m02 = sum8(p1 * sl);
+  R m11 = sum8(p2 * cl * cl), m12 = sum8(p2 * cl * sl), m22 = sum8(p2 * sl * sl);
+  const R wF = sum8(p3);
+
+  // ---- per-site FP64: Landau matching, EoS, gradient ----
+  const double lnM = lnMin[site];
+  const double M = exp(lnM);
+  const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
+  const double tk[6] = {G * (double)m00, G * (double)m01, G * (double)m02,
+                        G * (double)m11, G * (double)m12, G * (double)m22};
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
+  double lam, u[3];
+  const bool matched = landau3(tk, &lam, u);
+  EosAt E;
+  const bool eos_ok = eos_from_lambda(tb, lam, &E);
+  if (l == 0) {
+    if (!finite) flag(err, kErrNonfinite);
+    else if (!matched) flag(err, kErrMatch);
+    else if (!eos_ok) flag(err, kErrEos);
+  }
+  const double rate = E.T * a.inv_eta_hbarc / E.q;  // 1/tau_R [fm^-1]
+  const int xp = wrap(x + 1, a.nx), xm = wrap(x - 1, a.nx);
+  const int yp = wrap(y + 1, a.ny), ym = wrap(y - 1, a.ny);
+  const double gx = (lnMin[y * a.nx + xp] - lnMin[y * a.nx + xm]) * a.inv2dx;
+  const double gy = (lnMin[yp * a.nx + x] - lnMin[ym * a.nx + x]) * a.inv2dx;
+
+  // ---- node pass: F_eq, BGK, S1, S2, transport, mass-gradient force ----
+  const R ut = (R)u[0], ux = (R)u[1], uy = (R)u[2];
+  const R invT = (R)(1.0 / E.T), Mr = (R)M, Meq = (R)E.M_eq, rr = (R)rate, Zr = (R)a.Z;
+  const R cu = ux * cl + uy * sl;            // u_perp . (cos phi, sin phi)
+  const R Gl = (R)gx * cl + (R)gy * sl;      // grad ln M . (cos phi, sin phi)
+  const R gu = (R)(gx * u[1] + gy * u[2]);   // grad ln M . u_perp
+  const R MinvT = Mr * invT;
+  R Eeq[NXI], iEeq[NXI];
+#pragma unroll
+  for (int k = 0; k < NXI; ++k) {
+    Eeq[k] = rsqrt_<R>(Meq * Meq + Mr * Mr * C.sh2[k]);
+    iEeq[k] = (R)1 / Eeq[k];
+  }
+  // upwind neighbours: along +cos phi take x-1, x-2, etc.
+  const int dxr = (cl > (R)0) ? 1 : ((cl < (R)0) ? -1 : 0);
+  const int dyr = (sl > (R)0) ? 1 : ((sl < (R)0) ? -1 : 0);
+  const size_t sx1 = ((size_t)(y * a.nx + wrap(x - dxr, a.nx))) * kSl + l;
+  const size_t sx2 = ((size_t)(y * a.nx + wrap(x - 2 * dxr, a.nx))) * kSl + l;
+  const size_t sy1 = ((size_t)(wrap(y - dyr, a.ny) * a.nx + x)) * kSl + l;
+  const size_t sy2 = ((size_t)(wrap(y - 2 * dyr, a.ny) * a.nx + x)) * kSl + l;
+  const R ax = (R)(fabs((double)cl) * a.inv2dx), ay = (R)(fabs((double)sl) * a.inv2dx);
+  const R invtau = (R)(1.0 / a.tau);
+
+  R S2[Q], R0[Q];
+  // S2 (radial) and S1 = mu^2 A1 F - Ath F (stored in R0 for now)
+#pragma unroll
+  for (int k = 0; k < NXI; ++k) {
+#pragma unroll
+    for (int j = 0; j < NTH; ++j) {
+      R s2 = 0, s1r = 0, s1t = 0;
+#pragma unroll
+      for (int kp = 0; kp < NXI; ++kp) {
+        s2 += C.A2[k * NXI + kp] * f[kp * NTH + j];
+        s1r += C.A1[k * NXI + kp] * f[kp * NTH + j];
+      }
+#pragma unroll
+      for (int jp = 0; jp < NTH; ++jp) s1t += C.Ath[j * NTH + jp] * f[k * NTH + jp];
+      S2[k * NTH + j] = s2;
+      R0[k * NTH + j] = C.mu2[j] * s1r - s1t;
+    }
+  }
+
+  R nsum = 0, dsum = 0;
+#pragma unroll
+  for (int k = 0; k < NXI; ++k) {
+#pragma unroll
+    for (int j = 0; j < NTH; ++j) {
+      const int q = k * NTH + j;
+      const R sg = C.sig[q];
+      const R ig = C.inv_x[k];
+      const R fq = f[q];
+      // equilibrium with E_eq = sqrt(M_eq^2 + M^2 sinh^2 xi)
+      const R feq = Zr * rexp<R>(-(ut * Eeq[k] - Mr * sg * cu) * invT);
+      const R uvg = ut - sg * cu * ig;  // (u.V)/gamma
+      const R coll = uvg * (fq - feq) * rr;
+      // second-order upwind streaming, periodic
+      const R fx1 = Fin[q * plane + sx1], fx2 = Fin[q * plane + sx2];
+      const R fy1 = Fin[q * plane + sy1], fy2 = Fin[q * plane + sy2];
+      const R tr = ax * ((R)3 * fq - (R)4 * fx1 + fx2) + ay * ((R)3 * fq - (R)4 * fy1 + fy2);
+      const R adv = -(sg * ig) * tr;
+      // mass-gradient force applied to F_eq
+      const R grf = -(feq * MinvT) * (Gl * sg * ut * Mr * C.x[k] * iEeq[k] - (Gl * cu * sg * sg + gu) * ig);
+      R r0 = adv + grf - coll;
+      if (a.metric == LB_METRIC_MILNE) r0 += R0[q] * invtau;
+      const R uv = C.x[k] * uvg;
+      const R wuv2 = C.w[q] * uv * uv;
+      nsum += wuv2 * r0;
+      dsum += wuv2 * ((R)4 * fq + S2[q]);
+      R0[q] = r0;
+    }
+  }
+  nsum = sum8(nsum);
+  dsum = sum8(dsum);
+
+  // ---- mass evolution (eq. (masschange)), FP64 ----
+  const double beta = E.beta;
+  const double X = -beta * (double)nsum / ((double)wF + beta * (double)dsum);
+  const R Xr = (R)X;
+  const R dt = (R)a.dtau;
+
+  if (STAGE == 0) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) Fout[q * plane + me] = f[q] + dt * (R0[q] + Xr * S2[q]);
+    if (l == 0) lnMout[site] = lnM + a.dtau * X;
+  } else {
+    const R hdt = (R)(0.5 * a.dtau);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const R fb = Fbase[q * plane + me];
+      Fout[q * plane + me] = (R)0.5 * (fb + f[q]) + hdt * (R0[q] + Xr * S2[q]);
+    }
+    if (l == 0) lnMout[site] = 0.5 * (lnMbase[site] + lnM) + 0.5 * a.dtau * X;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial local equilibrium (Sec. IV.D): T0 from eps_EoS(T0) = e0.
+template <typename R, int NXI, int NTH>
+__global__ __launch_bounds__(kBlock) void init_kernel(const double* __restrict__ e0,
+                                                      const double* __restrict__ ux0,
+                                                      const double* __restrict__ uy0, R* __restrict__ F,
+                                                      double* __restrict__ lnM,
+                                                      const LatticeConst<R, NXI, NTH> C,
+                                                      const EosTable tb, const StageArgs a,
+                                                      int* __restrict__ err) {
+  constexpr int Q = NXI * NTH;
+  const int tid = blockIdx.x * kBlock + threadIdx.x;
+  const int site = tid >> 3;
+  const int l = tid & 7;
+  if (site >= a.n_sites) return;
+  const double e = e0[site] * (kHbarC * kHbarC * kHbarC);
+  const double vx = ux0 ? ux0[site] : 0.0, vy = uy0 ? uy0[site] : 0.0;
+  int bad = 0;
+  if (!isfinite(e) || !(e > 0.0) || !isfinite(vx) || !isfinite(vy)) bad = kErrNonfinite;
+  double uu = tb.u_lo;
+  if (!bad && !eos_invert(tb, kLnEeos, tb.inv_ee, tb.ge0, tb.ge_h, tb.ge_inv_h, log(e), &uu)) bad = kErrEos;
+  if (!bad && (uu < tb.u_lo || uu > tb.u_hi)) bad = kErrEos;
+  if (bad) uu = tb.u_lo;
+  double t, w[4], dw[4];
+  const int i = eos_locate(tb, uu, &t);
+  lagrange4(t, w, dw);
+  const double T0 = exp(uu);
+  const double M = eos_field(tb, i, w, kZ) * T0;
+  const double ut = sqrt(1.0 + vx * vx + vy * vy);
+  const double cu = vx * (double)C.cosl[l] + vy * (double)C.sinl[l];
+  const size_t plane = (size_t)a.n_sites * kSl;
+  const size_t me = (size_t)site * kSl + l;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = q / NTH;
+    const double uP = M * (ut * (double)C.x[k] - cu * (double)C.sig[q]);
+    F[q * plane + me] = (R)(a.Z * exp(-uP / T0));
+  }
+  if (l == 0) {
+    lnM[site] = log(M);
+    if (bad) flag(err, bad);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Observables: T^{ab} with B g^{ab}, N^a, T, u, M (eqs. (emtnew), (NTdisc)).
+template <typename R, int NXI, int NTH>
+__global__ __launch_bounds__(kBlock) void moments_kernel(const R* __restrict__ F,
+                                                         const double* __restrict__ lnMv,
+                                                         double* __restrict__ out,
+                                                         const LatticeConst<R, NXI, NTH> C,
+                                                         const EosTable tb, const StageArgs a,
+                                                         int* __restrict__ err) {
+  constexpr int Q = NXI * NTH;
+  const int tid = blockIdx.x * kBlock + threadIdx.x;
+  const int site = tid >> 3;
+  const int l = tid & 7;
+  if (site >= a.n_sites) return;
+  const size_t plane = (size_t)a.n_sites * kSl;
+  const size_t me = (size_t)site * kSl + l;
+  double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p5 = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const double fq = (double)F[q * plane + me];
+    p0 += (double)C.wx2[q] * fq;
+    p1 += (double)C.wxs[q] * fq;
+    p2 += (double)C.ws2[q] * fq;
+    p3 += (double)C.wvY2[q] * fq;
+    p4 += (double)C.wx[q] * fq;
+    p5 += (double)C.w[q] * (double)C.sig[q] * fq;
+  }
+  const double cl = (double)C.cosl[l], sl = (double)C.sinl[l];
+  const double m00 = sum8(p0), m01 = sum8(p1 * cl), m02 = sum8(p1 * sl);
+  const double m11 = sum8(p2 * cl * cl), m12 = sum8(p2 * cl * sl), m22 = sum8(p2 * sl * sl);
+  const double mYY = sum8(p3), n0 = sum8(p4), n1 = sum8(p5 * cl), n2 = sum8(p5 * sl);
+  const double lnM = lnMv[site];
+  const double M = exp(lnM);
+  const double G = M * M * M * M / (2.0 * kPi * kPi);
+  const double G3 = M * M * M / (2.0 * kPi * kPi);
+  const double tk[6] = {G * m00, G * m01, G * m02, G * m11, G * m12, G * m22};
+  double lam, u[3];
+  const bool matched = landau3(tk, &lam, u);
+  EosAt E;
+  const bool eos_ok = eos_from_lambda(tb, lam, &E);
+  if (l == 0) {
+    bool finite = true;
+    for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
+    if (!finite) flag(err, kErrNonfinite);
+    else if (!matched) flag(err, kErrMatch);
+    else if (!eos_ok) flag(err, kErrEos);
+    const double B = E.Bt4 * E.T * E.T * E.T * E.T;
+    const double c3 = 1.0 / (kHbarC * kHbarC * kHbarC);
+    const size_t ns = (size_t)a.n_sites;
+    out[0 * ns + site] = (tk[0] + B) * c3;
+    out[1 * ns + site] = tk[1] * c3;
+    out[2 * ns + site] = tk[2] * c3;
+    out[3 * ns + site] = (tk[3] - B) * c3;
+    out[4 * ns + site] = tk[4] * c3;
+    out[5 * ns + site] = (tk[5] - B) * c3;
+    out[6 * ns + site] = (G * mYY - B) * c3;
+    out[7 * ns + site] = G3 * n0 * c3;
+    out[8 * ns + site] = G3 * n1 * c3;
+    out[9 * ns + site] = G3 * n2 * c3;
+    out[10 * ns + site] = E.T;
+    out[11 * ns + site] = u[1];
+    out[12 * ns + site] = u[2];
+    out[13 * ns + site] = M;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void get_state_kernel(const R* __restrict__ F, double* __restrict__ Fc, int n_q, int n_sites) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)n_q * n_sites * kSl;
+  if (i >= total) return;
+  // internal index i = (q * n_sites + site) * 8 + l
+  const int l = (int)(i % kSl);
+  const size_t rest = i / kSl;
+  const int site = (int)(rest % n_sites);
+  const int q = (int)(rest / n_sites);
+  Fc[((size_t)q * kSl + l) * n_sites + site] = (double)F[i];
+}
+
+template <typename R>
+__global__ void set_state_kernel(const double* __restrict__ Fc, R* __restrict__ F, int n_q, int n_sites) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)n_q * n_sites * kSl;
+  if (i >= total) return;
+  const int l = (int)(i % kSl);
+  const size_t rest = i / kSl;
+  const int site = (int)(rest % n_sites);
+  const int q = (int)(rest / n_sites);
+  F[i] = (R)Fc[((size_t)q * kSl + l) * n_sites + site];
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+inline dim3 grid_for(int n_sites) { return dim3((unsigned)(((size_t)n_sites * kSl + kBlock - 1) / kBlock)); }
+}  // namespace
+
+hipError_t launch_stage(int precision, int stage, const void* Fin, const void* Fbase, void* Fout,
+                        const double* lnMin, const double* lnMbase, double* lnMout, const void* lc,
+                        const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
+  const dim3 g = grid_for(a.n_sites), b(kBlock);
+  if (precision == LB_FP32_FP64MATCH) {
+    const auto& C = *static_cast<const LatticeConst<float, 5, 5>*>(lc);
+    if (stage == 0)
+      hipLaunchKernelGGL((stage_kernel<float, 5, 5, 0>), g, b, 0, s, (const float*)Fin, (const float*)Fbase,
+                         (float*)Fout, lnMin, lnMbase, lnMout, C, tb, a, err);
+    else
+      hipLaunchKernelGGL((stage_kernel<float, 5, 5, 1>), g, b, 0, s, (const float*)Fin, (const float*)Fbase,
+                         (float*)Fout, lnMin, lnMbase, lnMout, C, tb, a, err);
+  } else {
+    const auto& C = *static_cast<const LatticeConst<double, 5, 5>*>(lc);
+    if (stage == 0)
+      hipLaunchKernelGGL((stage_kernel<double, 5, 5, 0>), g, b, 0, s, (const double*)Fin,
+                         (const double*)Fbase, (double*)Fout, lnMin, lnMbase, lnMout, C, tb, a, err);
+    else
+      hipLaunchKernelGGL((stage_kernel<double, 5, 5, 1>), g, b, 0, s, (const double*)Fin,
+                         (const double*)Fbase, (double*)Fout, lnMin, lnMbase, lnMout, C, tb, a, err);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int precision, const double* e0, const double* ux0, const double* uy0, void* F,
+                       double* lnM, const void* lc, const EosTable& tb, const StageArgs& a, int* err,
+                       hipStream_t s) {
+  const dim3 g = grid_for(a.n_sites), b(kBlock);
+  if (precision == LB_FP32_FP64MATCH)
+    hipLaunchKernelGGL((init_kernel<float, 5, 5>), g, b, 0, s, e0, ux0, uy0, (float*)F, lnM,
+                       *static_cast<const LatticeConst<float, 5, 5>*>(lc), tb, a, err);
+  else
+    hipLaunchKernelGGL((init_kernel<double, 5, 5>), g, b, 0, s, e0, ux0, uy0, (double*)F, lnM,
+                       *static_cast<const LatticeConst<double, 5, 5>*>(lc), tb, a, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int precision, const void* F, const double* lnM, double* out, const void* lc,
+                          const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
+  const dim3 g = grid_for(a.n_sites), b(kBlock);
+  if (precision == LB_FP32_FP64MATCH)
+    hipLaunchKernelGGL((moments_kernel<float, 5, 5>), g, b, 0, s, (const float*)F, lnM, out,
+                       *static_cast<const LatticeConst<float, 5, 5>*>(lc), tb, a, err);
+  else
+    hipLaunchKernelGGL((moments_kernel<double, 5, 5>), g, b, 0, s, (const double*)F, lnM, out,
+                       *static_cast<const LatticeConst<double, 5, 5>*>(lc), tb, a, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(int precision, const void* F, double* Fc, int n_q, int n_sites, hipStream_t s) {
+  const size_t total = (size_t)n_q * n_sites * kSl;
+  const dim3 g((unsigned)((total + 255) / 256)), b(256);
+  if (precision == LB_FP32_FP64MATCH)
+    hipLaunchKernelGGL(get_state_kernel<float>, g, b, 0, s, (const float*)F, Fc, n_q, n_sites);
+  else
+    hipLaunchKernelGGL(get_state_kernel<double>, g, b, 0, s, (const double*)F, Fc, n_q, n_sites);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(int precision, const double* Fc, void* F, int n_q, int n_sites, hipStream_t s) {
+  const size_t total = (size_t)n_q * n_sites * kSl;
+  const dim3 g((unsigned)((total + 255) / 256)), b(256);
+  if (precision == LB_FP32_FP64MATCH)
+    hipLaunchKernelGGL(set_state_kernel<float>, g, b, 0, s, Fc, (float*)F, n_q, n_sites);
+  else
+    hipLaunchKernelGGL(set_state_kernel<double>, g, b, 0, s, Fc, (double*)F, n_q, n_sites);
+  return hipGetLastError();
+}
+
+}  // namespace lbmi

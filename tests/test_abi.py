@@ -1,0 +1,153 @@
+"""C-ABI contract on the CPU: the library loads, exports every function the
+header declares, validates on the host before any device call, and its
+independently derived host setup (lattice, factored operators, EoS tables)
+agrees with the oracle."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import paper_1108_5561_amd as lb
+from oracle import quadrature as oq
+from oracle.eos import HBARC, ConstMassEoS, TanhEntropyEoS, TanhEoS
+from oracle.lattice import Lattice
+
+
+def test_library_exports_every_header_function():
+    names = lb.header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lb.lib, n), n
+
+
+def test_workspace_bytes_and_validation():
+    p = lb.make_params(32, 32, 0.2)
+    n = lb.workspace_bytes(p)
+    assert n >= 3 * 200 * 1024 * 8
+    p32 = lb.make_params(32, 32, 0.2, precision=lb.LB_FP32_FP64MATCH)
+    assert lb.workspace_bytes(p32) < n
+    for bad in [dict(nx=0), dict(ny=-1), dict(dx_fm=0.0), dict(dx_fm=float("nan")), dict(eta_over_s=0.0),
+                dict(n_xi=3), dict(n_phi=3), dict(z0=-1.0), dict(T_min_GeV=0.0), dict(eos_width_GeV=0.0),
+                dict(tau0_fm=0.0), dict(precision=7), dict(metric=5), dict(taur_rule=3), dict(Z=0.0)]:
+        q = lb.make_params(32, 32, 0.2)
+        for k, v in bad.items():
+            setattr(q, k, v)
+        assert lb.lib.lb_workspace_bytes(ctypes.byref(q)) == 0, bad
+        assert lb.last_error() != ""
+
+
+def _init_rc(p, ws=256, e0=512):
+    ctx = ctypes.c_void_p()
+    return lb.lib.lb_init(ctypes.byref(ctx), ctypes.byref(p), ws, 1 << 40, e0, None, None, None), ctx
+
+
+def test_init_rejects_on_host_before_device_work():
+    p = lb.make_params(8, 8, 0.2)
+    assert lb.lib.lb_init(None, ctypes.byref(p), 256, 1 << 40, 512, None, None, None) == lb.LB_E_ARG
+    q = lb.make_params(8, 8, 0.2)
+    q.nx = 0
+    assert _init_rc(q)[0] == lb.LB_E_ARG
+    assert _init_rc(p, ws=None)[0] == lb.LB_E_ARG
+    assert _init_rc(p, ws=257)[0] == lb.LB_E_ARG            # misaligned
+    assert _init_rc(p, e0=None)[0] == lb.LB_E_ARG
+    ctx = ctypes.c_void_p()
+    assert lb.lib.lb_init(ctypes.byref(ctx), ctypes.byref(p), 256, 1024, 512, None, None, None) == lb.LB_E_ARG
+
+
+def test_unstable_or_massless_eos_is_rejected():
+    # the tanh EoS of width 0.02 GeV has d eps/dT < 0 near 0.19 GeV: the mass
+    # equation of the scheme is singular there
+    p = lb.make_params(8, 8, 0.2, eos_kind=lb.LB_EOS_TANH_P, eos_width_GeV=0.02)
+    rc, _ = _init_rc(p)
+    assert rc == lb.LB_E_EOS and "unstable" in lb.last_error()
+    # kappa = 1: the quasiparticle entropy cannot reach s(T), no M(T)
+    p = lb.make_params(8, 8, 0.2, eos_kind=lb.LB_EOS_TANH_P, eos_width_GeV=0.03, kappa=1.0)
+    rc, _ = _init_rc(p)
+    assert rc == lb.LB_E_EOS and "mass" in lb.last_error()
+
+
+def test_calls_without_context():
+    assert lb.lib.lb_step(None, 1, 0.01) == lb.LB_E_STATE
+    assert lb.lib.lb_moments(None, None) == lb.LB_E_STATE
+    assert lb.lib.lb_status(None) == lb.LB_E_STATE
+    assert lb.lib.lb_destroy(None) == lb.LB_OK
+    assert lb.lib.lb_adjoint_step(None, 0, None, None, None, None) == lb.LB_E_NOTIMPL
+
+
+@pytest.mark.parametrize("z0", [1.0, 2.6])
+def test_host_lattice_matches_oracle(z0):
+    p = lb.make_params(8, 8, 0.2, z0=z0)
+    info = lb.lattice_info(p)
+    x, w = oq.radial_rule(z0, 5)
+    mu, wt = oq.gauss_legendre(5)
+    assert np.allclose(info["x"], x, rtol=1e-14, atol=0)
+    assert np.allclose(info["w_xi"], w, rtol=1e-13, atol=0)
+    assert np.allclose(info["mu"], mu, rtol=0, atol=1e-15)
+    assert np.allclose(info["w_th"], wt, rtol=1e-13, atol=0)
+    _, c, s = oq.phi_nodes(4)
+    assert np.allclose(info["cos"], c, rtol=0, atol=3e-16)
+    assert np.allclose(info["sin"], s, rtol=0, atol=3e-16)
+
+
+@pytest.mark.parametrize("z0", [1.0, 2.6])
+def test_factored_operators_equal_oracle_dense_operators(z0):
+    # The device applies S1, S2 as mu^2 (A1 x) - (Ath x) and (A2 x) on each
+    # phi slice; rebuilt densely they must equal the oracle's literal
+    # weak-form matrices of Sec. IV.D.
+    p = lb.make_params(8, 8, 0.2, z0=z0)
+    info = lb.lattice_info(p)
+    lat = Lattice(5, 5, 4, z0)
+    I5 = np.eye(5)
+    D2 = np.kron(info["A2"], I5)
+    D1 = np.kron(info["A1"], I5) * np.tile(info["mu"] ** 2, 5)[:, None] - np.kron(I5, info["Ath"])
+    scale1 = np.max(np.abs(lat.D1))
+    scale2 = np.max(np.abs(lat.D2))
+    assert np.max(np.abs(D1 - lat.D1)) < 1e-11 * scale1
+    assert np.max(np.abs(D2 - lat.D2)) < 1e-11 * scale2
+
+
+@pytest.mark.parametrize("kind", ["s", "p"])
+def test_host_eos_matches_oracle(kind):
+    if kind == "s":
+        p = lb.make_params(8, 8, 0.2, eta_over_s=0.1)
+        e = TanhEntropyEoS()
+    else:
+        p = lb.make_params(8, 8, 0.2, eta_over_s=0.1, eos_kind=lb.LB_EOS_TANH_P, eos_width_GeV=0.03)
+        e = TanhEoS(width=0.03)
+    T = np.array([0.06, 0.12, 0.17, 0.2, 0.35, 1.0, 2.9])
+    out = lb.eos_eval(p, T)
+    ref = [e.eps(T), e.p(T), e.s(T), e.M(T), e.B(T), e.eps_kin_eq(T), e.beta(T), e.tau_R(T, 0.1)]
+    for i, r in enumerate(ref):
+        scale = np.maximum(np.abs(r), 1e-300)
+        if i == 4:  # B is a difference of nearly equal pressures at low T
+            scale = np.maximum(np.abs(r), 1e-12 * e.p(T))
+        assert np.all(np.abs(out[:, i] - r) <= 1e-10 * scale), (i, out[:, i], r)
+
+
+def test_device_tables_interpolate_exact_eos():
+    # The kernels read the EoS from tables on a uniform ln T grid with
+    # 4-point Lagrange interpolation: error bound h^4 f''''/ (~43) with
+    # h = 1.25e-4.  Check at off-grid temperatures.
+    p = lb.make_params(8, 8, 0.2, eta_over_s=0.1)
+    rng = np.random.default_rng(0)
+    T = np.exp(rng.uniform(np.log(0.05), np.log(3.0), 400))
+    ex = lb.eos_eval(p, T)
+    tb = lb.eos_eval(p, T, table=True)
+    rel = lambda a, b: np.max(np.abs(a - b) / np.abs(b))
+    # measured at 2000 off-grid temperatures: ~5e-13 (M, tau_R, B, beta) and
+    # ~7e-12 (eps - B, steepest in relative terms at low T)
+    assert rel(tb[:, 3], ex[:, 3]) < 2e-12        # M
+    assert rel(tb[:, 5], ex[:, 5]) < 2e-11        # eps - B
+    assert rel(tb[:, 7], ex[:, 7]) < 2e-12        # tau_R
+    assert np.max(np.abs(tb[:, 6] - ex[:, 6])) < 1e-11   # beta
+    assert np.max(np.abs(tb[:, 4] - ex[:, 4]) / (np.abs(ex[:, 0]))) < 2e-12  # B relative to eps
+
+
+def test_const_mass_eos():
+    p = lb.make_params(8, 8, 0.2, eos_kind=lb.LB_EOS_CONST_MASS, eos_mass_GeV=0.4, Z=3.0)
+    T = np.array([0.1, 0.3, 1.0])
+    out = lb.eos_eval(p, T)
+    e = ConstMassEoS(3.0, 0.4)
+    assert np.allclose(out[:, 0], e.eps(T), rtol=1e-13)
+    assert np.allclose(out[:, 3], 0.4) and np.all(out[:, 4] == 0) and np.all(out[:, 6] == 0)

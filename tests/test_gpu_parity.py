@@ -1,0 +1,244 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances
+* FP64 path: the kernels read M(T), B(T), beta(T), tau_R(T) from tables whose
+  interpolation error is below 1e-12 relative (1e-10 absolute for beta); one
+  step therefore differs from the oracle by ~1e-12 relative in T^{mu nu}.
+  Bars: 1e-10 per step, 1e-8 after the 150-step small workload.
+* FP32 distributions with FP64 matching: T^{mu nu} relative error at most
+  1e-5 per step and 1e-4 after a full run.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1108_5561_amd as lb  # noqa: E402
+from oracle import step as st  # noqa: E402
+from oracle.bjorken import Bjorken01  # noqa: E402
+from oracle.eos import HBARC, ConstMassEoS, TanhEntropyEoS  # noqa: E402
+from oracle.lattice import Lattice  # noqa: E402
+from paper_1108_5561_amd import workloads as wl  # noqa: E402
+
+from _helpers import patch, tmunu_rel_err  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "small_fp64_oracle.npz")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lat():
+    return Lattice(5, 5, 4, 1.0)
+
+
+@pytest.fixture(scope="module")
+def eos():
+    return TanhEntropyEoS()
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def make_ctx(nx, ny, dx, e0, precision=lb.LB_FP64, ux=None, uy=None, **kw):
+    p = lb.make_params(nx, ny, dx, precision=precision, **kw)
+    c = lb.Context(p, gpu(e0), None if ux is None else gpu(ux), None if uy is None else gpu(uy))
+    return c
+
+
+def gaussian_e0(eos, nx, ny, dx, width=2.0, T=0.4):
+    return float(eos.eps(T)) / HBARC ** 3 * wl.gaussian_shape(nx, ny, dx, width)
+
+
+def test_init_matches_oracle(lat, eos):
+    e0 = gaussian_e0(eos, 37, 23, 0.2)
+    ux, uy = wl.random_flow(37, 23, 0.2, seed=11)
+    c = make_ctx(37, 23, 0.2, e0, ux=ux, uy=uy)
+    F, l = st.init_state(lat, eos, e0, ux, uy)
+    Fg, lg, tau = c.get_state()
+    assert tau == 0.5
+    assert np.max(np.abs(cpu(Fg) - F)) < 1e-11 * F.max()
+    assert np.max(np.abs(cpu(lg) - l)) < 1e-12
+    obs = cpu(c.moments())
+    ref = st.observables(lat, eos, st.Params(dx=0.2, eta_over_s=0.08), F, l)
+    assert tmunu_rel_err(obs, ref) < 1e-11
+    assert np.max(np.abs(obs[10] - ref[10]) / ref[10]) < 1e-11
+    assert np.max(np.abs(obs[11:13] - ref[11:13])) < 1e-11
+    assert c.status() == lb.LB_OK
+
+
+def _one_step_parity(lat, eos, precision, nx, ny, dx, dtau, seed, eta=0.08, metric=lb.LB_METRIC_MILNE):
+    e0 = gaussian_e0(eos, nx, ny, dx, width=0.25 * nx * dx)
+    ux, uy = wl.random_flow(nx, ny, 0.15, seed=seed)
+    F, l = st.init_state(lat, eos, e0, ux, uy)
+    # a non-equilibrium state: perturb F and ln M smoothly
+    rng = np.random.default_rng(seed)
+    F = F * (1 + 0.05 * rng.random(F.shape))
+    l = l + 0.02 * rng.standard_normal(l.shape)
+    c = make_ctx(nx, ny, dx, e0, precision=precision, eta_over_s=eta, metric=metric)
+    c.set_state(gpu(F), gpu(l), 0.7)
+    prm = st.Params(dx=dx, eta_over_s=eta, metric=metric)
+    if precision == lb.LB_FP32_FP64MATCH:
+        F = F.astype(np.float32).astype(np.float64)   # both start from the same values
+    Fo, lo = st.heun_step(lat, eos, prm, F, l, 0.7, dtau)
+    c.step(1, dtau)
+    Fg, lg, tau = c.get_state()
+    assert abs(tau - (0.7 + dtau)) < 1e-15
+    assert c.status() == lb.LB_OK
+    ref = st.observables(lat, eos, prm, Fo, lo)
+    return cpu(Fg), cpu(lg), cpu(c.moments()), Fo, lo, ref
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 23), (8, 5), (1, 1), (2, 3)])
+def test_one_step_fp64(lat, eos, nx, ny):
+    Fg, lg, obs, Fo, lo, ref = _one_step_parity(lat, eos, lb.LB_FP64, nx, ny, 0.2, 0.01, seed=nx * 100 + ny)
+    assert np.max(np.abs(Fg - Fo)) < 1e-10 * Fo.max()
+    assert np.max(np.abs(lg - lo)) < 1e-11
+    assert tmunu_rel_err(obs, ref) < 1e-10
+
+
+def test_one_step_fp64_minkowski_free_streaming(lat):
+    eos = ConstMassEoS(Z=3.0, M0=0.4)
+    nx, ny, dx = 16, 9, 0.1
+    rng = np.random.default_rng(5)
+    e0 = 1.0 + rng.random((ny, nx))
+    ux, uy = wl.random_flow(nx, ny, 0.3, seed=6)
+    F, l = st.init_state(lat, eos, e0, ux, uy)
+    p = lb.make_params(nx, ny, dx, metric=lb.LB_METRIC_MINKOWSKI, eta_over_s=float("inf"),
+                       eos_kind=lb.LB_EOS_CONST_MASS, eos_mass_GeV=0.4, Z=3.0)
+    c = lb.Context(p, gpu(e0), gpu(ux), gpu(uy))
+    prm = st.Params(dx=dx, eta_over_s=np.inf, metric=st.METRIC_MINKOWSKI)
+    for _ in range(3):
+        F, l = st.heun_step(lat, eos, prm, F, l, 1.0, 0.02)
+    c.step(3, 0.02)
+    Fg, lg, _ = c.get_state()
+    assert np.max(np.abs(cpu(Fg) - F)) < 1e-11 * F.max()
+    assert np.max(np.abs(cpu(lg) - l)) < 1e-14
+
+
+def test_one_step_fp32(lat, eos):
+    Fg, lg, obs, Fo, lo, ref = _one_step_parity(lat, eos, lb.LB_FP32_FP64MATCH, 37, 23, 0.2, 0.01, seed=3)
+    assert tmunu_rel_err(obs, ref) < 1e-5
+    assert np.max(np.abs(lg - lo)) < 1e-6
+
+
+def test_uniform_grid_is_paper_0p1d_algorithm(eos):
+    lat1 = Lattice(5, 5, 4, 1.0)
+    e_peak = float(eos.eps(0.35)) / HBARC ** 3
+    c = make_ctx(4, 3, 0.2, np.full((3, 4), e_peak))
+    b = Bjorken01(lat1, eos, 0.08)
+    f, l = b.init(0.35)
+    tau = 0.5
+    for _ in range(10):
+        f, l = b.step(f, l, tau, 0.02)
+        tau += 0.02
+    c.step(10, 0.02)
+    Fg, lg, _ = c.get_state()
+    Fg = cpu(Fg)
+    for iy in range(3):
+        for ix in range(4):
+            assert np.max(np.abs(Fg[:, iy, ix] - f)) < 1e-10 * f.max()
+    assert np.max(np.abs(cpu(lg) - l)) < 1e-11
+
+
+def test_small_workload_full_run_fp64_and_fp32(eos):
+    g = np.load(GOLDEN)
+    w = wl.WORKLOADS["small"]
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    res = {}
+    for prec in (lb.LB_FP64, lb.LB_FP32_FP64MATCH):
+        c = make_ctx(w["nx"], w["ny"], w["dx"], g["e0"], precision=prec, eta_over_s=w["eta_over_s"])
+        errs = {0: tmunu_rel_err(cpu(c.moments()), g["obs_0"])}
+        done = 0
+        for target in (1, 10, w["steps"]):
+            c.step(target - done, dtau)
+            done = target
+            errs[target] = tmunu_rel_err(cpu(c.moments()), g[f"obs_{target}"])
+        assert c.status() == lb.LB_OK
+        res[prec] = errs
+    print("small workload T^{mu nu} rel err vs oracle:", res)
+    assert res[lb.LB_FP64][1] < 1e-10 and res[lb.LB_FP64][w["steps"]] < 1e-8
+    assert res[lb.LB_FP32_FP64MATCH][1] < 1e-5 and res[lb.LB_FP32_FP64MATCH][w["steps"]] < 1e-4
+
+
+def test_prec_workload_sampled_parity(lat, eos):
+    # 256 x 256 at the benchmark's launch configuration: run a few steps, then
+    # check one more step at sampled sites against the oracle on 9 x 9
+    # periodic windows (the corrector reaches 4 sites: 2 for the predictor's
+    # stencil, 2 for its own)
+    w = wl.WORKLOADS["prec"]
+    e0 = gaussian_e0(eos, w["nx"], w["ny"], w["dx"]) * wl.white_noise_factor(w["nx"], w["ny"])
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    prm = st.Params(dx=w["dx"], eta_over_s=w["eta_over_s"])
+    c = make_ctx(w["nx"], w["ny"], w["dx"], e0, precision=lb.LB_FP32_FP64MATCH, eta_over_s=w["eta_over_s"])
+    c.step(5, dtau)
+    F0, l0, tau = c.get_state()
+    F0, l0 = cpu(F0), cpu(l0)
+    c.step(1, dtau)
+    obs = cpu(c.moments())
+    assert c.status() == lb.LB_OK
+    rng = np.random.default_rng(17)
+    sites = [(0, 0), (255, 255), (128, 128), (0, 200)] + [tuple(rng.integers(0, 256, 2)) for _ in range(6)]
+    for (cy, cx) in sites:
+        Fp, lp = patch(F0, cy, cx, 4), patch(l0, cy, cx, 4)
+        Fo, lo = st.heun_step(lat, eos, prm, Fp, lp, tau, dtau)
+        ref = st.observables(lat, eos, prm, Fo, lo)[:, 4:5, 4:5]
+        got = obs[:, cy:cy + 1, cx:cx + 1]
+        assert tmunu_rel_err(got, ref) < 1e-5, (cy, cx)
+
+
+def test_prec_workload_fp32_vs_fp64_full_run(eos):
+    # the precision form against the FP64 GPU step over the whole 1000-step run
+    w = wl.WORKLOADS["prec"]
+    e0 = gaussian_e0(eos, w["nx"], w["ny"], w["dx"]) * wl.white_noise_factor(w["nx"], w["ny"])
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    out = {}
+    for prec in (lb.LB_FP64, lb.LB_FP32_FP64MATCH):
+        c = make_ctx(w["nx"], w["ny"], w["dx"], e0, precision=prec, eta_over_s=w["eta_over_s"])
+        c.step(w["steps"], dtau)
+        out[prec] = cpu(c.moments())
+        assert c.status() == lb.LB_OK
+    err = tmunu_rel_err(out[lb.LB_FP32_FP64MATCH], out[lb.LB_FP64])
+    print("prec workload, 1000 steps, FP32-match vs FP64 T^{mu nu} rel err:", err)
+    assert err < 1e-4
+
+
+def test_deterministic(eos):
+    e0 = gaussian_e0(eos, 40, 40, 0.1) * wl.white_noise_factor(40, 40)
+    outs = []
+    for _ in range(2):
+        c = make_ctx(40, 40, 0.1, e0, precision=lb.LB_FP32_FP64MATCH)
+        c.step(20, 0.005)
+        outs.append(cpu(c.get_state()[0]))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_error_paths(eos):
+    e0 = gaussian_e0(eos, 8, 8, 0.2)
+    bad = e0.copy()
+    bad[3, 3] = np.nan
+    with pytest.raises(lb.LbError) as ei:
+        make_ctx(8, 8, 0.2, bad)
+    assert ei.value.code == lb.LB_E_NONFINITE
+    hot = e0.copy()
+    hot[2, 2] = 1e9   # far above eps(T_max)
+    with pytest.raises(lb.LbError) as ei:
+        make_ctx(8, 8, 0.2, hot)
+    assert ei.value.code == lb.LB_E_EOS
+    c = make_ctx(8, 8, 0.2, e0)
+    with pytest.raises(lb.LbError) as ei:
+        c.step(1, 0.2)          # CFL > 0.5
+    assert ei.value.code == lb.LB_E_ARG
+    with pytest.raises(lb.LbError):
+        c.step(1, -0.01)
+    assert c.adjoint_step() == lb.LB_E_NOTIMPL
+    c.step(0, 0.01)
+    assert c.status() == lb.LB_OK

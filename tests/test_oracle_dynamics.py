@@ -8,7 +8,7 @@ import pytest
 from oracle import hydro
 from oracle import step as st
 from oracle.bjorken import Bjorken01
-from oracle.eos import HBARC, ConstMassEoS, TanhEoS
+from oracle.eos import HBARC, ConstMassEoS, TanhEntropyEoS, TanhEoS
 from oracle.lattice import Lattice
 
 
@@ -19,7 +19,7 @@ def lat():
 
 @pytest.fixture(scope="module")
 def eos():
-    return TanhEoS(width=0.03)
+    return TanhEntropyEoS()
 
 
 def test_uniform_grid_reduces_to_paper_0p1d(lat, eos):
@@ -182,7 +182,7 @@ def test_ideal_and_first_order_viscous_limits():
     # Sec. IV.E: the LB tends to fluid dynamics as eta/s -> 0; the deviation
     # from ideal Bjorken flow is first order in eta/s, and first-order viscous
     # hydrodynamics (eta = (eta/s) s, zeta of Sec. IV.A) absorbs it.
-    eos = TanhEoS(width=0.03)
+    eos = TanhEntropyEoS()
     lat1 = Lattice(5, 5, 1, 2.6)
     taus = np.linspace(1.0, 2.0, 51)
     dev_id, dev_ns = [], []

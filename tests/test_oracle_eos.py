@@ -5,7 +5,8 @@ import pytest
 from scipy.integrate import quad
 from scipy.special import kv
 
-from oracle.eos import HBARC, ConstMassEoS, TanhEoS
+from oracle import hydro
+from oracle.eos import HBARC, ConstMassEoS, TanhEntropyEoS, TanhEoS
 
 T = np.array([0.08, 0.12, 0.16, 0.17, 0.19, 0.22, 0.3, 0.5, 1.0, 2.0])
 
@@ -14,9 +15,11 @@ def _fd(f, x, h):
     return (f(x + h) - f(x - h)) / (2 * h)
 
 
-@pytest.fixture(scope="module")
-def eos():
-    return TanhEoS(width=0.03)
+@pytest.fixture(scope="module", params=["entropy", "pressure"])
+def eos(request):
+    # crossover on s/T^3 (the workloads' EoS) and on p/T^4 (the printed form,
+    # at the smallest width with d eps/dT > 0 and c_s^2 <= 1)
+    return TanhEntropyEoS() if request.param == "entropy" else TanhEoS(width=0.03)
 
 
 def test_entropy_and_its_derivative_are_derivatives_of_p(eos):
@@ -35,7 +38,8 @@ def test_bag_function_solves_consistency_ode(eos):
     # the paper integrates up from small T where B ~ 0: |B| is below 1e-3 of
     # the Stefan-Boltzmann pressure of the same degrees of freedom there
     Tl = np.array([0.05, 0.06, 0.08, 0.1])
-    assert np.all(np.abs(eos.B(Tl)) < 1e-3 * eos.c * Tl ** 4)
+    p_sb = np.pi ** 2 / 90 * eos.g * Tl ** 4
+    assert np.all(np.abs(eos.B(Tl)) < 1e-3 * p_sb)
     # M' from implicit differentiation against a numerical derivative of M(T)
     assert np.allclose(eos.dM(T), _fd(eos.M, T, h), rtol=1e-6)
 
@@ -111,6 +115,23 @@ def test_relaxation_time_rules(eos):
     # CE rule: eta = tau_R h(T) equals (eta/s) s
     tr = eos.tau_R(Tt, 0.1, "ce") / HBARC
     assert np.allclose(tr * eos.h(Tt), 0.1 * eos.s(Tt), rtol=1e-13)
+
+
+def test_entropy_form_sound_speed_and_bulk_viscosity():
+    # tanh on s/T^3: c_s^2 = h/(3h + T h') in (0, 1/3]; the Chapman-Enskog bulk
+    # viscosity of Sec. IV.A stays non-negative (up to quadrature rounding
+    # where M/T is constant at high T and zeta -> 0)
+    e = TanhEntropyEoS()
+    Tg = np.linspace(0.05, 3.0, 30001)
+    cs2 = e.s(Tg) / (Tg * e.ds(Tg))
+    assert np.all(cs2 > 0) and np.all(cs2 <= 1 / 3 + 1e-12)
+    for t in (0.12, 0.16, 0.17, 0.18, 0.2, 0.25, 0.3, 0.4):
+        z = hydro.zeta_over_tauR(e, t)
+        assert z > -1e-6 * e.h(np.array([t]))[0], t
+    # the printed p/T^4 form has c_s^2 > 1/3 above Tc, where the same formula
+    # gives a negative bulk viscosity (a linearly unstable kinetic evolution)
+    e_p = TanhEoS(width=0.03)
+    assert hydro.zeta_over_tauR(e_p, 0.2) < -0.2 * e_p.h(np.array([0.2]))[0]
 
 
 def test_inversions():
