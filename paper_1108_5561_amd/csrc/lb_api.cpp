@@ -60,7 +60,8 @@ std::string validate(const lb_params* p) {
   if (!(p->z0 > 0) || !std::isfinite(p->z0)) return "z0 must be finite and > 0";
   if (!(p->Z > 0) || !std::isfinite(p->Z)) return "Z must be finite and > 0";
   if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
-  if ((int64_t)p->nx * p->ny * 8 > (int64_t)INT32_MAX) return "grid too large (nx*ny*8 must fit in int32)";
+  // a node plane (8 slices x sites, FP64) must be addressable with 32-bit byte offsets
+  if ((int64_t)p->nx * p->ny >= ((int64_t)1 << 26)) return "grid too large (nx*ny must be below 2^26 sites)";
   if (!(p->dx_fm > 0) || !std::isfinite(p->dx_fm)) return "dx_fm must be finite and > 0";
   if (!std::isfinite(p->tau0_fm)) return "tau0_fm must be finite";
   if (p->metric == LB_METRIC_MILNE && !(p->tau0_fm > 0)) return "tau0_fm must be > 0 for the Milne metric";

@@ -66,7 +66,8 @@ __host__ __device__ inline double eos_field(const EosTable& tb, int i, const dou
 // from the inverse table, then Newton on the interpolant.  Returns false if g
 // is outside the inverse table.
 __host__ __device__ inline bool eos_invert(const EosTable& tb, int field, const double* inv, double g0,
-                                           double gh, double gh_inv, double g, double* u_out) {
+                                           double gh, double gh_inv, double g, double* u_out,
+                                           int newton_iters = 4) {
   double s = (g - g0) * gh_inv;
   if (!(s >= 0.0) || !(s <= (double)(tb.n_inv - 1))) return false;
   int j = (int)s;
@@ -74,7 +75,7 @@ __host__ __device__ inline bool eos_invert(const EosTable& tb, int field, const 
   double f = s - (double)j;
   double u = inv[j] + f * (inv[j + 1] - inv[j]);
   double w[4], dw[4], t;
-  for (int it = 0; it < 4; ++it) {
+  for (int it = 0; it < newton_iters; ++it) {
     int i = eos_locate(tb, u, &t);
     lagrange4(t, w, dw);
     double val = eos_field(tb, i, w, field);

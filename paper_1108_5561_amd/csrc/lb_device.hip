@@ -61,14 +61,18 @@ __device__ inline bool landau3(const double t[6], double* lam_out, double u[3]) 
   const double c2 = t00 - t11 - t22;
   const double c1 = (t01 * t01 - t00 * t11) + (t02 * t02 - t00 * t22) + (t11 * t22 - t12 * t12);
   const double c0 = t00 * (t11 * t22 - t12 * t12) - t01 * (t01 * t22 - t12 * t02) + t02 * (t01 * t12 - t11 * t02);
-  double lam = t00;
-  for (int it = 0; it < 60; ++it) {
+  // start: the ideal-fluid value T00 - |T0i|^2 / (T00 + (Txx + Tyy)/2), exact
+  // for isotropic transverse pressure; above the inflection point c2/3 of the
+  // cubic Newton converges to the largest root (after at most one overshoot),
+  // otherwise start from the upper bound T00
+  double lam = t00 - (t01 * t01 + t02 * t02) / (t00 + 0.5 * (t11 + t22));
+  if (!(lam > c2 * (1.0 / 3.0)) || !(lam <= t00)) lam = t00;
+  for (int it = 0; it < 40; ++it) {
     const double p = ((lam - c2) * lam + c1) * lam - c0;
     const double dp = (3.0 * lam - 2.0 * c2) * lam + c1;
     const double d = p / dp;
-    if (!(d > 0.0)) break;  // monotone from above: done once the step vanishes
     lam -= d;
-    if (d <= 1e-16 * fabs(lam)) break;
+    if (!(fabs(d) > 4e-16 * fabs(lam))) break;
   }
   const double r0[3] = {t00 - lam, -t01, -t02};
   const double r1[3] = {t01, -t11 - lam, -t12};
@@ -110,7 +114,7 @@ struct EosAt {
 
 __device__ inline bool eos_from_lambda(const EosTable& tb, double lam, EosAt* o) {
   double u;
-  bool ok = (lam > 0.0) && eos_invert(tb, kLnEk, tb.inv_ek, tb.gk0, tb.gk_h, tb.gk_inv_h, log(lam), &u);
+  bool ok = (lam > 0.0) && eos_invert(tb, kLnEk, tb.inv_ek, tb.gk0, tb.gk_h, tb.gk_inv_h, log(lam), &u, 2);
   if (!ok) u = (lam > 0.0 && log(lam) > tb.gk0) ? tb.u_hi : tb.u_lo;
   if (u < tb.u_lo) { u = tb.u_lo; ok = false; }
   if (u > tb.u_hi) { u = tb.u_hi; ok = false; }
@@ -126,26 +130,135 @@ __device__ inline bool eos_from_lambda(const EosTable& tb, double lam, EosAt* o)
 }
 
 // ---------------------------------------------------------------------------
+// EoS at lambda = eps - B from one table cell: an initial u = ln T from the
+// inverse table, the 4-point stencil around it loaded once, Newton on that
+// cell's cubic, then M_eq/T, beta, q and B/T^4 from the same stencil.
+__device__ inline bool eos_cell(const EosTable& tb, double lam, EosAt* o) {
+  const double g = log(lam);
+  double s = (g - tb.gk0) * tb.gk_inv_h;
+  bool ok = (lam > 0.0) && (s >= 0.0) && (s <= (double)(tb.n_inv - 1));
+  if (!ok) s = (s > 0.0) ? (double)(tb.n_inv - 1) : 0.0;
+  int j = (int)s;
+  if (j > tb.n_inv - 2) j = tb.n_inv - 2;
+  const double u_guess = tb.inv_ek[j] + (s - (double)j) * (tb.inv_ek[j + 1] - tb.inv_ek[j]);
+  double t;
+  const int i = eos_locate(tb, u_guess, &t);
+  double e[4], zz[4], bb[4], qq[4], b4[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* p = tb.pts + (size_t)(i - 1 + k) * kFields;
+    e[k] = p[kLnEk];
+    zz[k] = p[kZ];
+    bb[k] = p[kBeta];
+    qq[k] = p[kQ];
+    b4[k] = p[kBt4];
+  }
+  double w[4], dw[4];
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    lagrange4(t, w, dw);
+    const double val = w[0] * e[0] + w[1] * e[1] + w[2] * e[2] + w[3] * e[3];
+    const double der = dw[0] * e[0] + dw[1] * e[1] + dw[2] * e[2] + dw[3] * e[3];
+    t -= (val - g) / der;
+  }
+  double u = tb.u0 + ((double)i + t) * tb.h;
+  if (!(u >= tb.u_lo)) { u = tb.u_lo; ok = false; t = (u - tb.u0) * tb.inv_h - (double)i; }
+  if (!(u <= tb.u_hi)) { u = tb.u_hi; ok = false; t = (u - tb.u0) * tb.inv_h - (double)i; }
+  lagrange4(t, w, dw);
+  o->T = exp(u);
+  o->M_eq = (w[0] * zz[0] + w[1] * zz[1] + w[2] * zz[2] + w[3] * zz[3]) * o->T;
+  o->beta = w[0] * bb[0] + w[1] * bb[1] + w[2] * bb[2] + w[3] * bb[3];
+  o->q = w[0] * qq[0] + w[1] * qq[1] + w[2] * qq[2] + w[3] * qq[3];
+  o->Bt4 = w[0] * b4[0] + w[1] * b4[1] + w[2] * b4[2] + w[3] * b4[3];
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
 // One Heun stage (Sec. IV.D).  STAGE 0 = predictor, 1 = corrector.
+//
+// A block owns an 8 x TY tile of sites (8 lanes per site).  Phases:
+//  1. every lane loads its phi slice and forms partial moments; the eight
+//     lanes of a site reduce them and one writes them to LDS;
+//  2. the first wave does the per-site FP64 work (Landau matching, EoS
+//     inversion, ln M gradient), one lane per site, while all waves apply
+//     the momentum operators S1, S2 and the transverse streaming, which do
+//     not need the site scalars;
+//  3. after the second barrier: equilibrium, BGK, mass-gradient force, the
+//     mass-evolution sums and the Heun update.
+constexpr int kTX = 8;
+#ifndef LB_TILE_ROWS_F32
+#define LB_TILE_ROWS_F32 4
+#endif
+#ifndef LB_WAVES_PER_EU_F32
+#define LB_WAVES_PER_EU_F32 1
+#endif
+template <typename R> struct TileRows { static constexpr int v = LB_TILE_ROWS_F32; };
+template <> struct TileRows<double> { static constexpr int v = 4; };
+template <typename R> struct MinWaves { static constexpr int v = LB_WAVES_PER_EU_F32; };
+template <> struct MinWaves<double> { static constexpr int v = 1; };
+enum { kSiT = 0, kSiU0, kSiU1, kSiU2, kSiMeq, kSiRate, kSiBeta, kSiGx, kSiGy, kSiM, kSiLnM, kSiN };
+
+// Node planes are read and written as raw buffers: one descriptor per plane
+// (uniform, built with scalar instructions) and a 32-bit byte offset per
+// lane, so no per-load vector address arithmetic.  Out-of-range offsets
+// read 0 and drop writes.
+typedef unsigned lb_v2u __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename R> struct Buf;
+template <> struct Buf<float> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+  }
+};
+template <> struct Buf<double> {
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lb_v2u, v), r, (int)off, 0, 0);
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ R eq_exp2(R a);
+template <>
+__device__ __forceinline__ float eq_exp2<float>(float a) { return __builtin_amdgcn_exp2f(a); }
+template <>
+__device__ __forceinline__ double eq_exp2<double>(double a) { return exp2(a); }
+
 template <typename R, int NXI, int NTH, int STAGE>
-__global__ __launch_bounds__(kBlock) void stage_kernel(
+__global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, MinWaves<R>::v) void stage_kernel(
     const R* __restrict__ Fin, const R* __restrict__ Fbase, R* __restrict__ Fout,
     const double* __restrict__ lnMin, const double* __restrict__ lnMbase, double* __restrict__ lnMout,
     const LatticeConst<R, NXI, NTH> C, const EosTable tb, const StageArgs a, int* __restrict__ err) {
   constexpr int Q = NXI * NTH;
-  const int tid = blockIdx.x * kBlock + threadIdx.x;
-  const int site = tid >> 3;
-  const int l = tid & 7;
-  if (site >= a.n_sites) return;  // whole 8-lane groups leave together
-  const int y = site / a.nx;
-  const int x = site - y * a.nx;
-  const size_t plane = (size_t)a.n_sites * kSl;
-  const size_t me = (size_t)site * kSl + l;
+  constexpr int kTY = TileRows<R>::v;
+  constexpr int kTile = kTX * kTY;
+  __shared__ double s_mom[6][kTile];
+  __shared__ double s_sc[kSiN][kTile];
 
-  // ---- load the slice and accumulate partial moments (eq. (emtnew)) ----
+  const int t = threadIdx.x;
+  const int ts = t >> 3;  // site within the tile
+  const int l = t & 7;    // phi slice
+  const int tiles_x = (a.nx + kTX - 1) / kTX;
+  const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+  const int x0 = bx * kTX + (ts % kTX), y0 = by * kTY + (ts / kTX);
+  const bool valid = (x0 < a.nx) && (y0 < a.ny);
+  const int x = valid ? x0 : 0, y = valid ? y0 : 0;  // out-of-grid lanes compute on site 0, store nothing
+  const int site = y * a.nx + x;
+  const uint32_t plane = (uint32_t)a.n_sites * kSl;
+  const uint32_t pbytes = plane * (uint32_t)sizeof(R);
+  const uint32_t me = ((uint32_t)site * kSl + l) * (uint32_t)sizeof(R);  // byte offset in a plane
+
+  // ---- phase 1: load the slice, partial moments (eq. (emtnew)) ----
   R f[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = Fin[q * plane + me];
+  for (int q = 0; q < Q; ++q) f[q] = Buf<R>::ld(plane_rsrc(Fin + (size_t)q * plane, pbytes), me);
   R p0 = 0, p1 = 0, p2 = 0, p3 = 0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -155,59 +268,65 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(
     p3 += C.w[q] * f[q];
   }
   const R cl = C.cosl[l], sl = C.sinl[l];
-  R m00 = sum8(p0), m01 = sum8(p1 * cl), m02 = sum8(p1 * sl);
-  R m11 = sum8(p2 * cl * cl), m12 = sum8(p2 * cl * sl), m22 = sum8(p2 * sl * sl);
+  {
+    const R m00 = sum8(p0), m01 = sum8(p1 * cl), m02 = sum8(p1 * sl);
+    const R m11 = sum8(p2 * cl * cl), m12 = sum8(p2 * cl * sl), m22 = sum8(p2 * sl * sl);
+    if (l == 0) {
+      s_mom[0][ts] = (double)m00;
+      s_mom[1][ts] = (double)m01;
+      s_mom[2][ts] = (double)m02;
+      s_mom[3][ts] = (double)m11;
+      s_mom[4][ts] = (double)m12;
+      s_mom[5][ts] = (double)m22;
+    }
+  }
   const R wF = sum8(p3);
+  __syncthreads();
 
-  // ---- per-site FP64: Landau matching, EoS, gradient ----
-  const double lnM = lnMin[site];
-  const double M = exp(lnM);
-  const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
-  const double tk[6] = {G * (double)m00, G * (double)m01, G * (double)m02,
-                        G * (double)m11, G * (double)m12, G * (double)m22};
-  bool finite = true;
+  // ---- phase 2a: per-site FP64 work, one lane per site (first wave) ----
+  if (t < kTile) {
+    const int sx = bx * kTX + (t % kTX), sy = by * kTY + (t / kTX);
+    if (sx < a.nx && sy < a.ny) {
+      const int ss = sy * a.nx + sx;
+      const double lnM = lnMin[ss];
+      const double M = exp(lnM);
+      const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
+      double tk[6];
+      bool finite = true;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
-  double lam, u[3];
-  const bool matched = landau3(tk, &lam, u);
-  EosAt E;
-  const bool eos_ok = eos_from_lambda(tb, lam, &E);
-  if (l == 0) {
-    if (!finite) flag(err, kErrNonfinite);
-    else if (!matched) flag(err, kErrMatch);
-    else if (!eos_ok) flag(err, kErrEos);
-  }
-  const double rate = E.T * a.inv_eta_hbarc / E.q;  // 1/tau_R [fm^-1]
-  const int xp = wrap(x + 1, a.nx), xm = wrap(x - 1, a.nx);
-  const int yp = wrap(y + 1, a.ny), ym = wrap(y - 1, a.ny);
-  const double gx = (lnMin[y * a.nx + xp] - lnMin[y * a.nx + xm]) * a.inv2dx;
-  const double gy = (lnMin[yp * a.nx + x] - lnMin[ym * a.nx + x]) * a.inv2dx;
-
-  // ---- node pass: F_eq, BGK, S1, S2, transport, mass-gradient force ----
-  const R ut = (R)u[0], ux = (R)u[1], uy = (R)u[2];
-  const R invT = (R)(1.0 / E.T), Mr = (R)M, Meq = (R)E.M_eq, rr = (R)rate, Zr = (R)a.Z;
-  const R cu = ux * cl + uy * sl;            // u_perp . (cos phi, sin phi)
-  const R Gl = (R)gx * cl + (R)gy * sl;      // grad ln M . (cos phi, sin phi)
-  const R gu = (R)(gx * u[1] + gy * u[2]);   // grad ln M . u_perp
-  const R MinvT = Mr * invT;
-  R Eeq[NXI], iEeq[NXI];
+      for (int i = 0; i < 6; ++i) {
+        tk[i] = G * s_mom[i][t];
+        finite = finite && isfinite(tk[i]);
+      }
+      double lam, u[3];
+      const bool matched = landau3(tk, &lam, u);
+      EosAt E;
+      const bool eos_ok = eos_cell(tb, lam, &E);
+      if (!finite) flag(err, kErrNonfinite);
+      else if (!matched) flag(err, kErrMatch);
+      else if (!eos_ok) flag(err, kErrEos);
+      const int xp = wrap(sx + 1, a.nx), xm = wrap(sx - 1, a.nx);
+      const int yp = wrap(sy + 1, a.ny), ym = wrap(sy - 1, a.ny);
+      s_sc[kSiT][t] = E.T;
+      s_sc[kSiU0][t] = u[0];
+      s_sc[kSiU1][t] = u[1];
+      s_sc[kSiU2][t] = u[2];
+      s_sc[kSiMeq][t] = E.M_eq;
+      s_sc[kSiRate][t] = E.T * a.inv_eta_hbarc / E.q;  // 1/tau_R [fm^-1]
+      s_sc[kSiBeta][t] = E.beta;
+      s_sc[kSiGx][t] = (lnMin[sy * a.nx + xp] - lnMin[sy * a.nx + xm]) * a.inv2dx;
+      s_sc[kSiGy][t] = (lnMin[yp * a.nx + sx] - lnMin[ym * a.nx + sx]) * a.inv2dx;
+      s_sc[kSiM][t] = M;
+      s_sc[kSiLnM][t] = lnM;
+    } else {
 #pragma unroll
-  for (int k = 0; k < NXI; ++k) {
-    Eeq[k] = rsqrt_<R>(Meq * Meq + Mr * Mr * C.sh2[k]);
-    iEeq[k] = (R)1 / Eeq[k];
+      for (int i = 0; i < kSiN; ++i) s_sc[i][t] = 1.0;
+    }
   }
-  // upwind neighbours: along +cos phi take x-1, x-2, etc.
-  const int dxr = (cl > (R)0) ? 1 : ((cl < (R)0) ? -1 : 0);
-  const int dyr = (sl > (R)0) ? 1 : ((sl < (R)0) ? -1 : 0);
-  const size_t sx1 = ((size_t)(y * a.nx + wrap(x - dxr, a.nx))) * kSl + l;
-  const size_t sx2 = ((size_t)(y * a.nx + wrap(x - 2 * dxr, a.nx))) * kSl + l;
-  const size_t sy1 = ((size_t)(wrap(y - dyr, a.ny) * a.nx + x)) * kSl + l;
-  const size_t sy2 = ((size_t)(wrap(y - 2 * dyr, a.ny) * a.nx + x)) * kSl + l;
-  const R ax = (R)(fabs((double)cl) * a.inv2dx), ay = (R)(fabs((double)sl) * a.inv2dx);
-  const R invtau = (R)(1.0 / a.tau);
 
+  // ---- phase 2b: S2 (radial), Milne term S1/tau and streaming ----
   R S2[Q], R0[Q];
-  // S2 (radial) and S1 = mu^2 A1 F - Ath F (stored in R0 for now)
+  const R s1scale = (a.metric == LB_METRIC_MILNE) ? (R)(1.0 / a.tau) : (R)0;
 #pragma unroll
   for (int k = 0; k < NXI; ++k) {
 #pragma unroll
@@ -221,10 +340,55 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(
 #pragma unroll
       for (int jp = 0; jp < NTH; ++jp) s1t += C.Ath[j * NTH + jp] * f[k * NTH + jp];
       S2[k * NTH + j] = s2;
-      R0[k * NTH + j] = C.mu2[j] * s1r - s1t;
+      R0[k * NTH + j] = (C.mu2[j] * s1r - s1t) * s1scale;
     }
   }
+  {
+    // second-order upwind along +(cos phi, sin phi): x-1, x-2 etc., periodic
+    const int dxr = (cl > (R)0) ? 1 : ((cl < (R)0) ? -1 : 0);
+    const int dyr = (sl > (R)0) ? 1 : ((sl < (R)0) ? -1 : 0);
+    constexpr uint32_t es = (uint32_t)sizeof(R);
+    const uint32_t sx1 = ((uint32_t)(y * a.nx + wrap(x - dxr, a.nx)) * kSl + l) * es;
+    const uint32_t sx2 = ((uint32_t)(y * a.nx + wrap(x - 2 * dxr, a.nx)) * kSl + l) * es;
+    const uint32_t sy1 = ((uint32_t)(wrap(y - dyr, a.ny) * a.nx + x) * kSl + l) * es;
+    const uint32_t sy2 = ((uint32_t)(wrap(y - 2 * dyr, a.ny) * a.nx + x) * kSl + l) * es;
+    const R ax = (R)(fabs((double)cl) * a.inv2dx), ay = (R)(fabs((double)sl) * a.inv2dx);
+#pragma unroll
+    for (int k = 0; k < NXI; ++k) {
+#pragma unroll
+      for (int j = 0; j < NTH; ++j) {
+        const int q = k * NTH + j;
+        const __amdgpu_buffer_rsrc_t rq = plane_rsrc(Fin + (size_t)q * plane, pbytes);
+        const R fx1 = Buf<R>::ld(rq, sx1), fx2 = Buf<R>::ld(rq, sx2);
+        const R fy1 = Buf<R>::ld(rq, sy1), fy2 = Buf<R>::ld(rq, sy2);
+        const R tr = ax * ((R)3 * f[q] - (R)4 * fx1 + fx2) + ay * ((R)3 * f[q] - (R)4 * fy1 + fy2);
+        R0[q] -= (C.sig[q] * C.inv_x[k]) * tr;
+      }
+    }
+  }
+  __syncthreads();
 
+  // ---- phase 3: equilibrium, BGK, mass-gradient force, sums, update ----
+  const double Td = s_sc[kSiT][ts], beta = s_sc[kSiBeta][ts], lnM = s_sc[kSiLnM][ts];
+  const double gx = s_sc[kSiGx][ts], gy = s_sc[kSiGy][ts];
+  const double u1d = s_sc[kSiU1][ts], u2d = s_sc[kSiU2][ts];
+  const R ut = (R)s_sc[kSiU0][ts], ux = (R)u1d, uy = (R)u2d;
+  const R Mr = (R)s_sc[kSiM][ts], Meq = (R)s_sc[kSiMeq][ts];
+  const R rr = (R)s_sc[kSiRate][ts], Zr = (R)a.Z;
+  const R MinvT = (R)(s_sc[kSiM][ts] / Td);
+  const R l2invT = (R)(1.4426950408889634 / Td);  // log2(e)/T
+  const R cu = ux * cl + uy * sl;            // u_perp . (cos phi, sin phi)
+  const R Gl = (R)gx * cl + (R)gy * sl;      // grad ln M . (cos phi, sin phi)
+  const R gu = (R)(gx * u1d + gy * u2d);     // grad ln M . u_perp
+  const R Gcu = Gl * cu;
+  const R Mcu2 = Mr * cu * l2invT;
+  R aE[NXI], gA[NXI];
+#pragma unroll
+  for (int k = 0; k < NXI; ++k) {
+    const R Eeq = rsqrt_<R>(Meq * Meq + Mr * Mr * C.sh2[k]);  // sqrt(M_eq^2 + M^2 sinh^2 xi)
+    aE[k] = ut * Eeq * l2invT;
+    gA[k] = Gl * ut * Mr * C.x[k] / Eeq;
+  }
   R nsum = 0, dsum = 0;
 #pragma unroll
   for (int k = 0; k < NXI; ++k) {
@@ -234,21 +398,12 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(
       const R sg = C.sig[q];
       const R ig = C.inv_x[k];
       const R fq = f[q];
-      // equilibrium with E_eq = sqrt(M_eq^2 + M^2 sinh^2 xi)
-      const R feq = Zr * rexp<R>(-(ut * Eeq[k] - Mr * sg * cu) * invT);
-      const R uvg = ut - sg * cu * ig;  // (u.V)/gamma
-      const R coll = uvg * (fq - feq) * rr;
-      // second-order upwind streaming, periodic
-      const R fx1 = Fin[q * plane + sx1], fx2 = Fin[q * plane + sx2];
-      const R fy1 = Fin[q * plane + sy1], fy2 = Fin[q * plane + sy2];
-      const R tr = ax * ((R)3 * fq - (R)4 * fx1 + fx2) + ay * ((R)3 * fq - (R)4 * fy1 + fy2);
-      const R adv = -(sg * ig) * tr;
-      // mass-gradient force applied to F_eq
-      const R grf = -(feq * MinvT) * (Gl * sg * ut * Mr * C.x[k] * iEeq[k] - (Gl * cu * sg * sg + gu) * ig);
-      R r0 = adv + grf - coll;
-      if (a.metric == LB_METRIC_MILNE) r0 += R0[q] * invtau;
-      const R uv = C.x[k] * uvg;
-      const R wuv2 = C.w[q] * uv * uv;
+      const R feq = Zr * eq_exp2<R>(sg * Mcu2 - aE[k]);        // F_eq (Sec. IV.D, with flow)
+      const R uvg = ut - (sg * ig) * cu;                       // (u.V)/gamma
+      const R coll = uvg * (fq - feq) * rr;                    // BGK, eq. (bgk)
+      const R grf = -(feq * MinvT) * (gA[k] * sg - (Gcu * sg * sg + gu) * ig);
+      const R r0 = R0[q] + grf - coll;
+      const R wuv2 = C.wx2[q] * uvg * uvg;                     // w (u.V)^2
       nsum += wuv2 * r0;
       dsum += wuv2 * ((R)4 * fq + S2[q]);
       R0[q] = r0;
@@ -258,27 +413,28 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(
   dsum = sum8(dsum);
 
   // ---- mass evolution (eq. (masschange)), FP64 ----
-  const double beta = E.beta;
   const double X = -beta * (double)nsum / ((double)wF + beta * (double)dsum);
   const R Xr = (R)X;
   const R dt = (R)a.dtau;
 
-  if (STAGE == 0) {
+  if (valid) {
+    if (STAGE == 0) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) Fout[q * plane + me] = f[q] + dt * (R0[q] + Xr * S2[q]);
-    if (l == 0) lnMout[site] = lnM + a.dtau * X;
-  } else {
-    const R hdt = (R)(0.5 * a.dtau);
+      for (int q = 0; q < Q; ++q)
+        Buf<R>::st(plane_rsrc(Fout + (size_t)q * plane, pbytes), me, f[q] + dt * (R0[q] + Xr * S2[q]));
+      if (l == 0) lnMout[site] = lnM + a.dtau * X;
+    } else {
+      const R hdt = (R)(0.5 * a.dtau);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const R fb = Fbase[q * plane + me];
-      Fout[q * plane + me] = (R)0.5 * (fb + f[q]) + hdt * (R0[q] + Xr * S2[q]);
+      for (int q = 0; q < Q; ++q) {
+        const R fb = Buf<R>::ld(plane_rsrc(Fbase + (size_t)q * plane, pbytes), me);
+        Buf<R>::st(plane_rsrc(Fout + (size_t)q * plane, pbytes), me, (R)0.5 * (fb + f[q]) + hdt * (R0[q] + Xr * S2[q]));
+      }
+      if (l == 0) lnMout[site] = 0.5 * (lnMbase[site] + lnM) + 0.5 * a.dtau * X;
     }
-    if (l == 0) lnMout[site] = 0.5 * (lnMbase[site] + lnM) + 0.5 * a.dtau * X;
   }
 }
 
-// ---------------------------------------------------------------------------
 // Initial local equilibrium (Sec. IV.D): T0 from eps_EoS(T0) = e0.
 template <typename R, int NXI, int NTH>
 __global__ __launch_bounds__(kBlock) void init_kernel(const double* __restrict__ e0,
@@ -422,7 +578,9 @@ inline dim3 grid_for(int n_sites) { return dim3((unsigned)(((size_t)n_sites * kS
 hipError_t launch_stage(int precision, int stage, const void* Fin, const void* Fbase, void* Fout,
                         const double* lnMin, const double* lnMbase, double* lnMout, const void* lc,
                         const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
-  const dim3 g = grid_for(a.n_sites), b(kBlock);
+  const int ty = precision == LB_FP32_FP64MATCH ? TileRows<float>::v : TileRows<double>::v;
+  const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
+  const dim3 g(tiles), b(kTX * ty * kSl);
   if (precision == LB_FP32_FP64MATCH) {
     const auto& C = *static_cast<const LatticeConst<float, 5, 5>*>(lc);
     if (stage == 0)

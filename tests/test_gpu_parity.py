@@ -179,7 +179,7 @@ def test_prec_workload_sampled_parity(lat, eos):
     dtau = (w["tau1"] - w["tau0"]) / w["steps"]
     prm = st.Params(dx=w["dx"], eta_over_s=w["eta_over_s"])
     c = make_ctx(w["nx"], w["ny"], w["dx"], e0, precision=lb.LB_FP32_FP64MATCH, eta_over_s=w["eta_over_s"])
-    c.step(5, dtau)
+    c.step(200, dtau)   # tau = 2 fm/c, where the FP32/FP64 difference peaks
     F0, l0, tau = c.get_state()
     F0, l0 = cpu(F0), cpu(l0)
     c.step(1, dtau)
