@@ -18,6 +18,7 @@ struct StageArgs {
   double dtau;           // step [fm]
   double inv_eta_hbarc;  // 1/((eta/s) hbar c), 0 for eta/s = inf
   double Z;
+  double log2Z;          // log2(Z)
 };
 
 // One Heun stage.  stage 0: F* = F + dtau K(F); stage 1:

@@ -125,6 +125,8 @@ void fill_const(const HostLattice& L, LatticeConst<R, 5, 5>* C) {
       const double sig = sh * sth, vY = sh * L.mu[j];
       const double w = std::exp(L.z0 * L.x[k]) * L.wxi[k] * L.wth[j] / (4.0 * L.nphi);
       C->sig[q] = (R)sig;
+      C->sigi[q] = (R)(sig / L.x[k]);
+      C->sig2[q] = (R)(sig * sig);
       C->vY[q] = (R)vY;
       C->w[q] = (R)w;
       C->wx2[q] = (R)(w * L.x[k] * L.x[k]);
@@ -156,6 +158,7 @@ StageArgs stage_args(const lb_ctx* c, double tau, double dtau) {
   a.dtau = dtau;
   a.inv_eta_hbarc = std::isinf(c->p.eta_over_s) ? 0.0 : 1.0 / (c->p.eta_over_s * kHbarC);
   a.Z = c->p.Z;
+  a.log2Z = std::log2(c->p.Z);
   return a;
 }
 

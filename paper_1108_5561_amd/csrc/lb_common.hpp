@@ -96,6 +96,8 @@ struct LatticeConst {
   R inv_x[NXI];      // 1/gamma_k
   R sh2[NXI];        // sinh^2 xi_k
   R sig[NXI * NTH];  // |v_perp| = sinh xi_k sin theta_j
+  R sigi[NXI * NTH]; // |v_perp| / gamma
+  R sig2[NXI * NTH]; // |v_perp|^2
   R vY[NXI * NTH];   // v^Y = sinh xi_k cos theta_j
   R mu2[NTH];        // cos^2 theta_j
   R w[NXI * NTH];    // w_n (the same on every phi slice)

@@ -186,6 +186,7 @@ __device__ inline bool eos_cell(const EosTable& tb, double lam, EosAt* o) {
 //  3. after the second barrier: equilibrium, BGK, mass-gradient force, the
 //     mass-evolution sums and the Heun update.
 constexpr int kTX = 8;
+constexpr int kXcds = 8;  // accelerator complex dies of the MI355X
 #ifndef LB_TILE_ROWS_F32
 #define LB_TILE_ROWS_F32 4
 #endif
@@ -246,7 +247,15 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, MinWaves<R>::v) void st
   const int ts = t >> 3;  // site within the tile
   const int l = t & 7;    // phi slice
   const int tiles_x = (a.nx + kTX - 1) / kTX;
-  const int bx = blockIdx.x % tiles_x, by = blockIdx.x / tiles_x;
+  const int n_tiles = tiles_x * ((a.ny + kTY - 1) / kTY);
+  // XCD-aware order: workgroups go round-robin over the eight XCDs, so XCD
+  // (blockIdx % 8) is given the contiguous band of row-major tiles
+  // [xcd * per, (xcd + 1) * per) and sweeps it in dispatch order; the x and
+  // y neighbours of a tile then sit in the same L2.
+  const int per = (n_tiles + kXcds - 1) / kXcds;
+  const int tile = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  if (tile >= n_tiles) return;  // whole block
+  const int bx = tile % tiles_x, by = tile / tiles_x;
   const int x0 = bx * kTX + (ts % kTX), y0 = by * kTY + (ts / kTX);
   const bool valid = (x0 < a.nx) && (y0 < a.ny);
   const int x = valid ? x0 : 0, y = valid ? y0 : 0;  // out-of-grid lanes compute on site 0, store nothing
@@ -352,7 +361,9 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, MinWaves<R>::v) void st
     const uint32_t sx2 = ((uint32_t)(y * a.nx + wrap(x - 2 * dxr, a.nx)) * kSl + l) * es;
     const uint32_t sy1 = ((uint32_t)(wrap(y - dyr, a.ny) * a.nx + x) * kSl + l) * es;
     const uint32_t sy2 = ((uint32_t)(wrap(y - 2 * dyr, a.ny) * a.nx + x) * kSl + l) * es;
+    // (3 F_i - 4 F_{i-1} + F_{i-2}) |cos phi|/(2 dx) + the same along y
     const R ax = (R)(fabs((double)cl) * a.inv2dx), ay = (R)(fabs((double)sl) * a.inv2dx);
+    const R c0 = (R)3 * (ax + ay), c1 = (R)(-4) * ax, c2 = (R)(-4) * ay;
 #pragma unroll
     for (int k = 0; k < NXI; ++k) {
 #pragma unroll
@@ -361,33 +372,42 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, MinWaves<R>::v) void st
         const __amdgpu_buffer_rsrc_t rq = plane_rsrc(Fin + (size_t)q * plane, pbytes);
         const R fx1 = Buf<R>::ld(rq, sx1), fx2 = Buf<R>::ld(rq, sx2);
         const R fy1 = Buf<R>::ld(rq, sy1), fy2 = Buf<R>::ld(rq, sy2);
-        const R tr = ax * ((R)3 * f[q] - (R)4 * fx1 + fx2) + ay * ((R)3 * f[q] - (R)4 * fy1 + fy2);
-        R0[q] -= (C.sig[q] * C.inv_x[k]) * tr;
+        const R tr = c0 * f[q] + c1 * fx1 + ax * fx2 + c2 * fy1 + ay * fy2;
+        R0[q] -= C.sigi[q] * tr;  // -(|v_perp|/gamma) along (cos, sin)
       }
     }
   }
   __syncthreads();
-
-  // ---- phase 3: equilibrium, BGK, mass-gradient force, sums, update ----
   const double Td = s_sc[kSiT][ts], beta = s_sc[kSiBeta][ts], lnM = s_sc[kSiLnM][ts];
   const double gx = s_sc[kSiGx][ts], gy = s_sc[kSiGy][ts];
   const double u1d = s_sc[kSiU1][ts], u2d = s_sc[kSiU2][ts];
-  const R ut = (R)s_sc[kSiU0][ts], ux = (R)u1d, uy = (R)u2d;
-  const R Mr = (R)s_sc[kSiM][ts], Meq = (R)s_sc[kSiMeq][ts];
-  const R rr = (R)s_sc[kSiRate][ts], Zr = (R)a.Z;
-  const R MinvT = (R)(s_sc[kSiM][ts] / Td);
+  const double u0d = s_sc[kSiU0][ts], Md = s_sc[kSiM][ts], Meqd = s_sc[kSiMeq][ts];
+  const double rated = s_sc[kSiRate][ts];
+
+  // ---- phase 3: equilibrium, BGK, mass-gradient force, sums, update ----
+  const R ut = (R)u0d, ux = (R)u1d, uy = (R)u2d;
+  const R Mr = (R)Md, Meq = (R)Meqd;
+  const R rr = (R)rated;
+  const R MinvT = (R)(Md / Td);
   const R l2invT = (R)(1.4426950408889634 / Td);  // log2(e)/T
   const R cu = ux * cl + uy * sl;            // u_perp . (cos phi, sin phi)
   const R Gl = (R)gx * cl + (R)gy * sl;      // grad ln M . (cos phi, sin phi)
   const R gu = (R)(gx * u1d + gy * u2d);     // grad ln M . u_perp
-  const R Gcu = Gl * cu;
+  // Per node, with s = |v_perp| and gamma = cosh xi:
+  //   F_eq = Z exp(-[u^tau E_eq - M s (u.phi)]/T) = exp2(s Mcu2 + aE_k),
+  //   BGK  = r (u.V/gamma) (F - F_eq), r = 1/tau_R,
+  //   mass-gradient force on F_eq = -F_eq (al_k s - be_k s^2 - ga_k),
+  // so r0 = R0 + F_eq (r u.V/gamma - poly) - r (u.V/gamma) F.
   const R Mcu2 = Mr * cu * l2invT;
-  R aE[NXI], gA[NXI];
+  const R log2Z = (R)a.log2Z;
+  R aE[NXI], al[NXI], be[NXI], ga[NXI];
 #pragma unroll
   for (int k = 0; k < NXI; ++k) {
     const R Eeq = rsqrt_<R>(Meq * Meq + Mr * Mr * C.sh2[k]);  // sqrt(M_eq^2 + M^2 sinh^2 xi)
-    aE[k] = ut * Eeq * l2invT;
-    gA[k] = Gl * ut * Mr * C.x[k] / Eeq;
+    aE[k] = log2Z - ut * Eeq * l2invT;
+    al[k] = MinvT * Gl * ut * Mr * C.x[k] / Eeq;
+    be[k] = MinvT * Gl * cu * C.inv_x[k];
+    ga[k] = MinvT * gu * C.inv_x[k];
   }
   R nsum = 0, dsum = 0;
 #pragma unroll
@@ -396,13 +416,13 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, MinWaves<R>::v) void st
     for (int j = 0; j < NTH; ++j) {
       const int q = k * NTH + j;
       const R sg = C.sig[q];
-      const R ig = C.inv_x[k];
       const R fq = f[q];
-      const R feq = Zr * eq_exp2<R>(sg * Mcu2 - aE[k]);        // F_eq (Sec. IV.D, with flow)
-      const R uvg = ut - (sg * ig) * cu;                       // (u.V)/gamma
-      const R coll = uvg * (fq - feq) * rr;                    // BGK, eq. (bgk)
-      const R grf = -(feq * MinvT) * (gA[k] * sg - (Gcu * sg * sg + gu) * ig);
-      const R r0 = R0[q] + grf - coll;
+      const R feq = eq_exp2<R>(sg * Mcu2 + aE[k]);             // F_eq (Sec. IV.D, with flow)
+      const R uvg = ut - C.sigi[q] * cu;                       // (u.V)/gamma
+      const R ru = rr * uvg;
+      const R poly = al[k] * sg - be[k] * C.sig2[q] - ga[k];
+      R r0 = R0[q] + feq * (ru - poly);
+      r0 -= ru * fq;                                           // BGK, eq. (bgk)
       const R wuv2 = C.wx2[q] * uvg * uvg;                     // w (u.V)^2
       nsum += wuv2 * r0;
       dsum += wuv2 * ((R)4 * fq + S2[q]);
@@ -580,7 +600,8 @@ hipError_t launch_stage(int precision, int stage, const void* Fin, const void* F
                         const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
   const int ty = precision == LB_FP32_FP64MATCH ? TileRows<float>::v : TileRows<double>::v;
   const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
-  const dim3 g(tiles), b(kTX * ty * kSl);
+  const unsigned per = (tiles + kXcds - 1) / kXcds;
+  const dim3 g(per * kXcds), b(kTX * ty * kSl);
   if (precision == LB_FP32_FP64MATCH) {
     const auto& C = *static_cast<const LatticeConst<float, 5, 5>*>(lc);
     if (stage == 0)
