@@ -14,6 +14,7 @@ import argparse
 import json
 import os
 import platform
+import re
 import resource
 import sys
 import time
@@ -33,6 +34,33 @@ def site_bytes(precision, stage):
     elt = 4 if precision == "fp32" else 8
     f = N_NODES * elt
     return (2 * f + 16) if stage == 0 else (3 * f + 24)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_prec256_hbm_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1108_5561_amd", "csrc", "lb_device.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, each scaled by what the counter reads for a
+    plain copy of known size; None if the kernel source changed since."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"lb_device.hip sha256: ([0-9a-f]{64})", txt)
+    if not m or m.group(1) != src:
+        return None
+    c = re.search(r"^calibration fetch_kib (\S+) write_kib (\S+) bytes (\d+)", txt, re.M)
+    k = re.search(r"^traffic %s fetch_kib (\S+) write_kib (\S+)" % re.escape(kernel), txt, re.M)
+    if not c or not k:
+        return None
+    nbytes = float(c.group(3))
+    f_scale = nbytes / (float(c.group(1)) * 1024.0)
+    w_scale = nbytes / (float(c.group(2)) * 1024.0)
+    return float(k.group(1)) * 1024.0 * f_scale + float(k.group(2)) * 1024.0 * w_scale
 
 
 def run_gpu(lb, wl, torch, precision, steps, warmup):
@@ -179,6 +207,8 @@ def main():
     bytes_launch = site_bytes("fp32", stage) * n
     achieved = bytes_launch / (kms / 1e3) / 1e9
     step_bytes = (site_bytes("fp32", 0) + site_bytes("fp32", 1)) * n
+    kname = "stage_kernel<float,5,5,%d>" % stage
+    traffic = measured_traffic(kname)
 
     parity = parity_fp32_vs_fp64(lb, wl, torch)
 
@@ -205,8 +235,10 @@ def main():
         "fp32_vs_fp64_tmunu_rel_err": parity,
         "kernels_ms": {"pred": r32["pred_ms"], "corr": r32["corr_ms"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "stage_kernel<float,5,5,%d>" % stage},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": bytes_launch, "kernel": kname,
+                     "kernel_avg_us": kms * 1e3},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, r32["e0"], r32["dtau"])
