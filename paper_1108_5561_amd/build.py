@@ -24,9 +24,10 @@ def build(verbose=False, arch="gfx950"):
     for src in SOURCES:
         obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", "-Wno-unused-value",
-               f"--offload-arch={arch}", "-c", os.path.join(CSRC, src), "-o", obj]
+               f"--offload-arch={arch}", "-c"]
         if src.endswith(".hip"):
-            cmd += ["-x", "hip"] + HIP_FLAGS
+            cmd += HIP_FLAGS + ["-x", "hip"]
+        cmd += [os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -21,6 +21,8 @@ struct lb_ctx {
   size_t ws_bytes = 0;
   void* F[3] = {nullptr, nullptr, nullptr};
   double* lnM[3] = {nullptr, nullptr, nullptr};
+  double* sc[3] = {nullptr, nullptr, nullptr};  // site scalars of each state
+  void* cst = nullptr;                          // device copy of the stage constants
   int cur = 0;  // index of the current state
   int* err = nullptr;
   EosTable tb{};
@@ -50,7 +52,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t F[3], lnM[3], pts, inv_ek, inv_ee, err, total;
+  size_t F[3], lnM[3], sc[3], cst, pts, inv_ek, inv_ee, err, total;
 };
 
 std::string validate(const lb_params* p) {
@@ -96,6 +98,12 @@ Layout layout(const lb_params* p) {
     L.lnM[i] = off;
     off = align_up(off + sites * 8);
   }
+  for (int i = 0; i < 3; ++i) {
+    L.sc[i] = off;
+    off = align_up(off + site_scalar_bytes(sites, elt));
+  }
+  L.cst = off;
+  off = align_up(off + sizeof(StageConst<double>));
   L.pts = off;
   off = align_up(off + (size_t)kTablePoints * kFields * 8);
   L.inv_ek = off;
@@ -146,6 +154,84 @@ void fill_const(const HostLattice& L, LatticeConst<R, 5, 5>* C) {
   }
 }
 
+// Stage constants (mirror-pair form, see StageConst) with S1 unscaled.
+template <typename R>
+void fill_stage_const(const HostLattice& L, StageConst<R>* S) {
+  const int nxi = 5, nth = 5;
+  for (int k = 0; k < nxi; ++k) {
+    S->x[k] = (R)L.x[k];
+    S->inv_x[k] = (R)(1.0 / L.x[k]);
+    S->sh2[k] = (R)(L.x[k] * L.x[k] - 1.0);
+  }
+  for (int pr = 0; pr < 2; ++pr) S->mu2[pr] = (R)(L.mu[pr] * L.mu[pr]);
+  for (int k = 0; k < nxi; ++k)
+    for (int pr = 0; pr < 3; ++pr) {
+      const int i = k * 3 + pr;
+      const double sh = std::sqrt(L.x[k] * L.x[k] - 1.0);
+      const double sig = sh * std::sqrt(1.0 - L.mu[pr] * L.mu[pr]);
+      const double w = std::exp(L.z0 * L.x[k]) * L.wxi[k] * L.wth[pr] / (4.0 * L.nphi);
+      S->sig[i] = (R)sig;
+      S->sigi[i] = (R)(sig / L.x[k]);
+      S->sig2[i] = (R)(sig * sig);
+      S->w[i] = (R)w;
+      S->wx2[i] = (R)(w * L.x[k] * L.x[k]);
+      S->wxs[i] = (R)(w * L.x[k] * sig);
+      S->ws2[i] = (R)(w * sig * sig);
+    }
+  for (int i = 0; i < nxi * nxi; ++i) {
+    S->A1[i] = (R)L.A1[i];
+    S->A2[i] = (R)L.A2[i];
+  }
+  // -Ath split by the mirror j -> 4 - j (Ath is mirror symmetric):
+  // (Ath f)_j +- (Ath f)_{4-j} = sum_j' Ath_{jj'} (f_j' +- f_{4-j'}).
+  const auto A = [&](int j, int jp) { return L.Ath[j * nth + jp]; };
+  for (int pr = 0; pr < 2; ++pr) {
+    S->Ev[pr][0] = (R)(-0.5 * (A(pr, 0) + A(pr, 4)));
+    S->Ev[pr][1] = (R)(-0.5 * (A(pr, 1) + A(pr, 3)));
+    S->Ev[pr][2] = (R)(-A(pr, 2));
+    S->Od[pr][0] = (R)(-0.5 * (A(pr, 0) - A(pr, 4)));
+    S->Od[pr][1] = (R)(-0.5 * (A(pr, 1) - A(pr, 3)));
+  }
+  S->Mid[0] = (R)(-A(2, 0));
+  S->Mid[1] = (R)(-A(2, 1));
+  S->Mid[2] = (R)(-A(2, 2));
+  for (int l = 0; l < 8; ++l) {
+    S->cosl[l] = (R)L.cosl[l];
+    S->sinl[l] = (R)L.sinl[l];
+  }
+}
+
+// The stage constants of a context: as built for the Milne metric (the
+// kernel supplies the 1/tau of S1), with the S1 parts zero for Minkowski.
+template <typename R>
+StageConst<R> metric_stage_const(const StageConst<R>& base, int metric) {
+  StageConst<R> S = base;
+  if (metric == LB_METRIC_MILNE) return S;
+  for (int i = 0; i < 25; ++i) S.A1[i] = 0;
+  for (int pr = 0; pr < 2; ++pr) {
+    for (int i = 0; i < 3; ++i) S.Ev[pr][i] = 0;
+    for (int i = 0; i < 2; ++i) S.Od[pr][i] = 0;
+  }
+  for (int i = 0; i < 3; ++i) S.Mid[i] = 0;
+  return S;
+}
+
+StageArgs stage_args(const lb_ctx* c, double tau, double dtau);
+
+// Site scalars of the current state (after lb_init / lb_set_state).
+hipError_t prime_site_scalars(lb_ctx* c) {
+  const StageArgs a = stage_args(c, c->tau, 0.0);
+  const int cur = c->cur;
+  return launch_site(c->p.precision, c->F[cur], c->lnM[cur], c->sc[cur], c->cst, c->tb, a, c->err, c->stream);
+}
+
+// Time of a stage; tau_s = tau multiplies the S1-free terms of a Milne stage.
+void set_tau(StageArgs* a, const lb_ctx* c, double tau) {
+  a->tau = tau;
+  a->tau_s = c->p.metric == LB_METRIC_MILNE ? tau : 1.0;
+  a->inv_tau_s = 1.0 / a->tau_s;
+}
+
 StageArgs stage_args(const lb_ctx* c, double tau, double dtau) {
   StageArgs a;
   a.nx = c->p.nx;
@@ -154,8 +240,8 @@ StageArgs stage_args(const lb_ctx* c, double tau, double dtau) {
   a.metric = c->p.metric;
   a.inv2dx = 0.5 / c->p.dx_fm;
   a.inv_dx = 1.0 / c->p.dx_fm;
-  a.tau = tau;
   a.dtau = dtau;
+  set_tau(&a, c, tau);
   a.inv_eta_hbarc = std::isinf(c->p.eta_over_s) ? 0.0 : 1.0 / (c->p.eta_over_s * kHbarC);
   a.Z = c->p.Z;
   a.log2Z = std::log2(c->p.Z);
@@ -232,7 +318,9 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
   for (int i = 0; i < 3; ++i) {
     c->F[i] = c->ws + L.F[i];
     c->lnM[i] = (double*)(c->ws + L.lnM[i]);
+    c->sc[i] = (double*)(c->ws + L.sc[i]);
   }
+  c->cst = c->ws + L.cst;
   double* d_pts = (double*)(c->ws + L.pts);
   double* d_iek = (double*)(c->ws + L.inv_ek);
   double* d_iee = (double*)(c->ws + L.inv_ee);
@@ -251,6 +339,23 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
     delete c;
     return hip_fail(e, "upload of EoS tables");
   }
+  {
+    StageConst<float> sf;
+    StageConst<double> sd;
+    if (p->precision == LB_FP32_FP64MATCH) {
+      fill_stage_const(c->lat, &sf);
+      sf = metric_stage_const(sf, p->metric);
+      e = hipMemcpy(c->cst, &sf, sizeof(sf), hipMemcpyHostToDevice);
+    } else {
+      fill_stage_const(c->lat, &sd);
+      sd = metric_stage_const(sd, p->metric);
+      e = hipMemcpy(c->cst, &sd, sizeof(sd), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+      delete c;
+      return hip_fail(e, "upload of stage constants");
+    }
+  }
   c->tau = p->tau0_fm;
   c->cur = 0;
   StageArgs a = stage_args(c, c->tau, 0.0);
@@ -258,6 +363,10 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
                        c->stream)) != hipSuccess) {
     delete c;
     return hip_fail(e, "init kernel launch");
+  }
+  if ((e = prime_site_scalars(c)) != hipSuccess) {
+    delete c;
+    return hip_fail(e, "site kernel launch");
   }
   int rc = read_err(c);
   if (rc != LB_OK) {
@@ -277,7 +386,6 @@ int lb_step(lb_ctx* c, int32_t n_steps, double dtau) {
   if (cfl > 0.5)
     return fail(LB_E_ARG, "CFL number " + std::to_string(cfl) + " > 0.5 (reduce dtau or increase dx)");
   const int prec = c->p.precision;
-  const void* lc = lat_const(c);
   for (int s = 0; s < n_steps; ++s) {
     const int i0 = c->cur, i1 = (c->cur + 1) % 3, i2 = (c->cur + 2) % 3;
     hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
@@ -294,12 +402,14 @@ int lb_step(lb_ctx* c, int32_t n_steps, double dtau) {
       hipEventRecord(e0, c->stream);
     }
     StageArgs a = stage_args(c, c->tau, dtau);
-    hipError_t e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], lc,
+    hipError_t e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], c->sc[i0],
+                                c->sc[i1], c->cst,
                                 c->tb, a, c->err, c->stream);
     if (e != hipSuccess) return hip_fail(e, "predictor launch");
     if (c->prof) hipEventRecord(e1, c->stream);
-    a.tau = c->tau + dtau;
-    e = launch_stage(prec, 1, c->F[i1], c->F[i0], c->F[i2], c->lnM[i1], c->lnM[i0], c->lnM[i2], lc, c->tb, a,
+    set_tau(&a, c, c->tau + dtau);
+    e = launch_stage(prec, 1, c->F[i1], c->F[i0], c->F[i2], c->lnM[i1], c->lnM[i0], c->lnM[i2], c->sc[i1],
+                     c->sc[i2], c->cst, c->tb, a,
                      c->err, c->stream);
     if (e != hipSuccess) return hip_fail(e, "corrector launch");
     if (c->prof) hipEventRecord(e2, c->stream);
@@ -345,6 +455,7 @@ int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_f
   e = hipMemcpyAsync(c->lnM[c->cur], d_lnM, (size_t)n_sites * 8, hipMemcpyDeviceToDevice, c->stream);
   if (e != hipSuccess) return hip_fail(e, "copy of ln M");
   c->tau = tau_fm;
+  if ((e = prime_site_scalars(c)) != hipSuccess) return hip_fail(e, "site kernel launch");
   return LB_OK;
 }
 

@@ -112,4 +112,29 @@ struct LatticeConst {
   R cosl[8], sinl[8];
 };
 
+// Constants of one stage-kernel launch (5 x 5 nodes per phi slice).  The
+// polar nodes are mirror pairs, mu_{4-j} = -mu_j, and every per-node
+// quantity the stage needs (weights, |v_perp|, gamma) is even under the
+// mirror, so it is stored once per (k, p): pair p = 0 holds j = 0, 4, p = 1
+// holds j = 1, 3 and p = 2 is j = 2 (mu = 0).  The Milne factor 1/tau of S1
+// is folded into A1 and the polar blocks (0 for the Minkowski metric).
+template <typename R>
+struct StageConst {
+  static constexpr int NXI = 5, NP = 3;
+  R x[NXI], inv_x[NXI], sh2[NXI];
+  R sig[NXI * NP];   // |v_perp|
+  R sigi[NXI * NP];  // |v_perp| / gamma
+  R sig2[NXI * NP];  // |v_perp|^2
+  R w[NXI * NP], wx2[NXI * NP], wxs[NXI * NP], ws2[NXI * NP];  // w, w gamma^2, w gamma |v_perp|, w |v_perp|^2
+  R mu2[2];          // mu_j^2 of pairs 0 and 1
+  R A1[NXI * NXI];   // radial part of S1, times 1/tau
+  R A2[NXI * NXI];   // S2 (radial)
+  // Polar part of S1, -Ath/tau, split by the mirror: for output pair p < 2,
+  // Ev[p] acts on (f_0 + f_4, f_1 + f_3, f_2) and Od[p] on (f_0 - f_4,
+  // f_1 - f_3), each with the factor 1/2 of the recombination; Mid acts on
+  // (f_0 + f_4, f_1 + f_3, f_2) for j = 2.
+  R Ev[2][3], Od[2][2], Mid[3];
+  R cosl[8], sinl[8];
+};
+
 }  // namespace lbmi

@@ -35,20 +35,6 @@ __device__ __forceinline__ R sum8(R v) {
   return v;
 }
 
-template <typename R>
-__device__ __forceinline__ R rexp(R x);
-template <>
-__device__ __forceinline__ float rexp<float>(float x) { return expf(x); }
-template <>
-__device__ __forceinline__ double rexp<double>(double x) { return exp(x); }
-
-template <typename R>
-__device__ __forceinline__ R rsqrt_(R x);
-template <>
-__device__ __forceinline__ float rsqrt_<float>(float x) { return sqrtf(x); }
-template <>
-__device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
-
 __device__ __forceinline__ void flag(int* err, int bit) { atomicOr(err, bit); }
 
 // Landau matching (eq. (sanity)) of the 3x3 (tau, x, y) block.  t = {Ttt, Ttx,
@@ -176,28 +162,44 @@ __device__ inline bool eos_cell(const EosTable& tb, double lam, EosAt* o) {
 // ---------------------------------------------------------------------------
 // One Heun stage (Sec. IV.D).  STAGE 0 = predictor, 1 = corrector.
 //
-// A block owns an 8 x TY tile of sites (8 lanes per site).  Phases:
-//  1. every lane loads its phi slice and forms partial moments; the eight
-//     lanes of a site reduce them and one writes them to LDS;
-//  2. the first wave does the per-site FP64 work (Landau matching, EoS
-//     inversion, ln M gradient), one lane per site, while all waves apply
-//     the momentum operators S1, S2 and the transverse streaming, which do
-//     not need the site scalars;
-//  3. after the second barrier: equilibrium, BGK, mass-gradient force, the
-//     mass-evolution sums and the Heun update.
+// A block owns an 8 x TY tile of sites (8 lanes per site, lane l owning the
+// phi_l slice).  The per-site FP64 work of a state (Landau matching of
+// eq. (sanity), EoS inversion) is done once, at the end of the kernel that
+// produced the state, and handed to the next stage as per-site scalars.  A
+// stage therefore has no wait on it:
+//  1. load the site scalars of the input state, the slice and its upwind
+//     neighbours; streaming, Milne term S1/tau, S2;
+//  2. equilibrium, BGK, mass-gradient force, the mass-evolution sums, X and
+//     the Heun update, stored;
+//  3. moments of the new state (eq. (emtnew)), reduced over the eight slices;
+//     one barrier; the first wave matches them (one lane per site, FP64) and
+//     writes the site scalars of the new state.
+//
+// Polar mirror pairs: the node set is symmetric under theta -> pi - theta
+// (j -> 4 - j), and the equilibrium, |v_perp|, gamma and the weights are
+// even under it, so per slice those are evaluated on 15 (k, pair) values
+// and shared by the two nodes of a pair; the polar part of S1 is applied in
+// the mirror-even / mirror-odd basis.
 constexpr int kTX = 8;
 constexpr int kXcds = 8;  // accelerator complex dies of the MI355X
 #ifndef LB_TILE_ROWS_F32
 #define LB_TILE_ROWS_F32 4
 #endif
 #ifndef LB_WAVES_PER_EU_F32
-#define LB_WAVES_PER_EU_F32 1
+#define LB_WAVES_PER_EU_F32 4
+#endif
+#ifndef LB_WAVES_PER_EU_F64
+#define LB_WAVES_PER_EU_F64 2
 #endif
 template <typename R> struct TileRows { static constexpr int v = LB_TILE_ROWS_F32; };
 template <> struct TileRows<double> { static constexpr int v = 4; };
-template <typename R> struct MinWaves { static constexpr int v = LB_WAVES_PER_EU_F32; };
-template <> struct MinWaves<double> { static constexpr int v = 1; };
-enum { kSiT = 0, kSiU0, kSiU1, kSiU2, kSiMeq, kSiRate, kSiBeta, kSiGx, kSiGy, kSiM, kSiLnM, kSiN };
+#ifndef LB_WAVES_PER_EU_F32_CORR
+#define LB_WAVES_PER_EU_F32_CORR LB_WAVES_PER_EU_F32
+#endif
+template <typename R, int STAGE> struct MinWaves {
+  static constexpr int v = STAGE == 0 ? LB_WAVES_PER_EU_F32 : LB_WAVES_PER_EU_F32_CORR;
+};
+template <int STAGE> struct MinWaves<double, STAGE> { static constexpr int v = LB_WAVES_PER_EU_F64; };
 
 // Node planes are read and written as raw buffers: one descriptor per plane
 // (uniform, built with scalar instructions) and a 32-bit byte offset per
@@ -225,132 +227,223 @@ template <> struct Buf<double> {
   }
 };
 
-template <typename R>
-__device__ __forceinline__ R eq_exp2(R a);
-template <>
-__device__ __forceinline__ float eq_exp2<float>(float a) { return __builtin_amdgcn_exp2f(a); }
-template <>
-__device__ __forceinline__ double eq_exp2<double>(double a) { return exp2(a); }
+// Node arithmetic helpers: hardware exp2 / sqrt / reciprocal in FP32 (about
+// 1 ulp), the correctly rounded library functions in FP64.
+template <typename R> __device__ __forceinline__ R eq_exp2(R a);
+template <> __device__ __forceinline__ float eq_exp2<float>(float a) { return __builtin_amdgcn_exp2f(a); }
+template <> __device__ __forceinline__ double eq_exp2<double>(double a) { return exp2(a); }
+template <typename R> __device__ __forceinline__ R nsqrt(R a);
+template <> __device__ __forceinline__ float nsqrt<float>(float a) { return __builtin_amdgcn_sqrtf(a); }
+template <> __device__ __forceinline__ double nsqrt<double>(double a) { return sqrt(a); }
+template <typename R> __device__ __forceinline__ R nrcp(R a);
+template <> __device__ __forceinline__ float nrcp<float>(float a) { return __builtin_amdgcn_rcpf(a); }
+template <> __device__ __forceinline__ double nrcp<double>(double a) { return 1.0 / a; }
 
-template <typename R, int NXI, int NTH, int STAGE>
-__global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, MinWaves<R>::v) void stage_kernel(
+// Stage constants live in device memory and are read with scalar loads
+// through a constant-address-space pointer; const_ptr hides the pointer's
+// value from the optimiser at the point of use, so a loop re-reads them
+// instead of holding all of them in registers across iterations.
+template <typename R>
+using CPtr = const __attribute__((address_space(4))) StageConst<R>*;
+template <typename R>
+__device__ __forceinline__ CPtr<R> const_ptr(const StageConst<R>* p) {
+  uint64_t v = (uint64_t)p;
+  asm volatile("" : "+s"(v));
+  return (CPtr<R>)v;
+}
+// Site scalars of a state (kernels.hpp: kScN planes of R after an FP64 beta
+// plane): what the node arithmetic of a stage needs from Landau matching and
+// the EoS.
+template <typename R>
+__device__ __forceinline__ R* sc_planes(double* sc, int n_sites) { return reinterpret_cast<R*>(sc + n_sites); }
+template <typename R>
+__device__ __forceinline__ const R* sc_planes(const double* sc, int n_sites) {
+  return reinterpret_cast<const R*>(sc + n_sites);
+}
+
+// Partial moments of one slice over the mirror pairs: w gamma^2, w gamma
+// |v_perp|, w |v_perp|^2 and w, summed over the 25 nodes (eq. (emtnew)).
+template <typename R>
+__device__ __forceinline__ void slice_moments(const R f[25], CPtr<R> C, R* p0, R* p1, R* p2, R* p3) {
+  R a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr) {
+      const R fs = pr < 2 ? f[k * 5 + pr] + f[k * 5 + 4 - pr] : f[k * 5 + 2];
+      const int i = k * 3 + pr;
+      a0 += C->wx2[i] * fs;
+      a1 += C->wxs[i] * fs;
+      a2 += C->ws2[i] * fs;
+      a3 += C->w[i] * fs;
+    }
+  }
+  *p0 = a0;
+  *p1 = a1;
+  *p2 = a2;
+  *p3 = a3;
+}
+
+// Landau matching (eq. (sanity)) and EoS inversion of a tile's state from
+// the slices in registers, writing the site scalars.  Every thread of the
+// block calls it (one barrier inside); lane l of site ts holds slice l and
+// lnM = ln M of its site.  s_mom is the block's LDS scratch [7][tile sites].
+template <typename R, int kTY>
+__device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM, int t, int bx,
+                                           int by, const EosTable& tb, const StageArgs& a,
+                                           double* __restrict__ sc, int* __restrict__ err,
+                                           double (*s_mom)[kTX * kTY]) {
+  constexpr int kTile = kTX * kTY;
+  const int ts = t >> 3, l = t & 7;
+  R p0, p1, p2, p3;
+  slice_moments(f, C, &p0, &p1, &p2, &p3);
+  (void)p3;
+  const R cl = C->cosl[l], sl = C->sinl[l];
+  const R m00 = sum8(p0), m01 = sum8(p1 * cl), m02 = sum8(p1 * sl);
+  const R m11 = sum8(p2 * cl * cl), m12 = sum8(p2 * cl * sl), m22 = sum8(p2 * sl * sl);
+  if (l == 0) {
+    s_mom[0][ts] = (double)m00;
+    s_mom[1][ts] = (double)m01;
+    s_mom[2][ts] = (double)m02;
+    s_mom[3][ts] = (double)m11;
+    s_mom[4][ts] = (double)m12;
+    s_mom[5][ts] = (double)m22;
+    s_mom[6][ts] = lnM;
+  }
+  __syncthreads();
+  if (t >= kTile) return;
+  const int sx = bx * kTX + (t % kTX), sy = by * kTY + (t / kTX);
+  if (sx >= a.nx || sy >= a.ny) return;
+  const int ss = sy * a.nx + sx;
+  const double M = exp(s_mom[6][t]);
+  const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
+  double tk[6];
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    tk[i] = G * s_mom[i][t];
+    finite = finite && isfinite(tk[i]);
+  }
+  double lam, u[3];
+  const bool matched = landau3(tk, &lam, u);
+  EosAt E;
+  const bool eos_ok = eos_cell(tb, lam, &E);
+  if (!finite) flag(err, kErrNonfinite);
+  else if (!matched) flag(err, kErrMatch);
+  else if (!eos_ok) flag(err, kErrEos);
+  const double invT = 1.0 / E.T;
+  R* P = sc_planes<R>(sc, a.n_sites);
+  const size_t n = (size_t)a.n_sites;
+  sc[ss] = E.beta;
+  P[kScUt * n + ss] = (R)u[0];
+  P[kScUx * n + ss] = (R)u[1];
+  P[kScUy * n + ss] = (R)u[2];
+  P[kScM * n + ss] = (R)M;
+  P[kScMeq * n + ss] = (R)E.M_eq;
+  P[kScRate * n + ss] = (R)(E.T * a.inv_eta_hbarc / E.q);  // 1/tau_R [fm^-1]
+  P[kScMinvT * n + ss] = (R)(M * invT);
+  P[kScL2invT * n + ss] = (R)(1.4426950408889634 * invT);  // log2(e)/T
+}
+
+// Tile of a block in the XCD-aware order: workgroups go round-robin over the
+// eight XCDs, so XCD (blockIdx % 8) is given the contiguous band of
+// row-major tiles [xcd * per, (xcd + 1) * per) and sweeps it in dispatch
+// order; the x and y neighbours of a tile then sit in the same L2.
+__device__ __forceinline__ int xcd_tile(int n_tiles) {
+  const int per = (n_tiles + kXcds - 1) / kXcds;
+  return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+
+// Geometry of one lane in a tile: site (x, y) (site 0 for lanes outside the
+// grid, which compute but store nothing) and its byte offset in a plane.
+struct LaneSite {
+  int bx, by, x, y, site;
+  bool valid;
+  uint32_t me;
+};
+template <typename R, int kTY>
+__device__ __forceinline__ LaneSite lane_site(int tile, int tiles_x, int ts, int l, const StageArgs& a) {
+  LaneSite g;
+  g.bx = tile % tiles_x;
+  g.by = tile / tiles_x;
+  const int x0 = g.bx * kTX + (ts % kTX), y0 = g.by * kTY + (ts / kTX);
+  g.valid = (x0 < a.nx) && (y0 < a.ny);
+  g.x = g.valid ? x0 : 0;
+  g.y = g.valid ? y0 : 0;
+  g.site = g.y * a.nx + g.x;
+  g.me = ((uint32_t)g.site * kSl + l) * (uint32_t)sizeof(R);
+  return g;
+}
+
+// Stage kernel: one block per 8 x TY tile, blocks in the XCD-aware tile
+// order of xcd_tile.
+template <typename R, int STAGE>
+__global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, (MinWaves<R, STAGE>::v)) void stage_kernel(
     const R* __restrict__ Fin, const R* __restrict__ Fbase, R* __restrict__ Fout,
     const double* __restrict__ lnMin, const double* __restrict__ lnMbase, double* __restrict__ lnMout,
-    const LatticeConst<R, NXI, NTH> C, const EosTable tb, const StageArgs a, int* __restrict__ err) {
-  constexpr int Q = NXI * NTH;
+    const double* __restrict__ scin, double* __restrict__ scout, const StageConst<R>* __restrict__ Cg,
+    const EosTable tb, const StageArgs a, int* __restrict__ err) {
+  constexpr int NXI = 5, NTH = 5, Q = NXI * NTH;
   constexpr int kTY = TileRows<R>::v;
-  constexpr int kTile = kTX * kTY;
-  __shared__ double s_mom[6][kTile];
-  __shared__ double s_sc[kSiN][kTile];
+  __shared__ double s_mom[7][kTX * kTY];
 
   const int t = threadIdx.x;
   const int ts = t >> 3;  // site within the tile
   const int l = t & 7;    // phi slice
   const int tiles_x = (a.nx + kTX - 1) / kTX;
   const int n_tiles = tiles_x * ((a.ny + kTY - 1) / kTY);
-  // XCD-aware order: workgroups go round-robin over the eight XCDs, so XCD
-  // (blockIdx % 8) is given the contiguous band of row-major tiles
-  // [xcd * per, (xcd + 1) * per) and sweeps it in dispatch order; the x and
-  // y neighbours of a tile then sit in the same L2.
-  const int per = (n_tiles + kXcds - 1) / kXcds;
-  const int tile = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  const int tile = xcd_tile(n_tiles);
   if (tile >= n_tiles) return;  // whole block
-  const int bx = tile % tiles_x, by = tile / tiles_x;
-  const int x0 = bx * kTX + (ts % kTX), y0 = by * kTY + (ts / kTX);
-  const bool valid = (x0 < a.nx) && (y0 < a.ny);
-  const int x = valid ? x0 : 0, y = valid ? y0 : 0;  // out-of-grid lanes compute on site 0, store nothing
-  const int site = y * a.nx + x;
+  const CPtr<R> C = const_ptr(Cg);
+  const LaneSite g = lane_site<R, kTY>(tile, tiles_x, ts, l, a);
+  const int bx = g.bx, by = g.by, x = g.x, y = g.y, site = g.site;
+  const bool valid = g.valid;
+  const uint32_t me = g.me;
   const uint32_t plane = (uint32_t)a.n_sites * kSl;
   const uint32_t pbytes = plane * (uint32_t)sizeof(R);
-  const uint32_t me = ((uint32_t)site * kSl + l) * (uint32_t)sizeof(R);  // byte offset in a plane
+  const size_t n = (size_t)a.n_sites;
 
-  // ---- phase 1: load the slice, partial moments (eq. (emtnew)) ----
+  // ---- site scalars of the input state; ln M and its centred gradient ----
+  const R* P = sc_planes<R>(scin, a.n_sites);
+  const double beta = scin[site];
+  const R ut = P[kScUt * n + site], ux = P[kScUx * n + site], uy = P[kScUy * n + site];
+  const R Mr = P[kScM * n + site], Meq = P[kScMeq * n + site], rr = P[kScRate * n + site];
+  const R MinvT = P[kScMinvT * n + site], l2invT = P[kScL2invT * n + site];
+  const double lnM = lnMin[site];
+  const R gx = (R)((lnMin[y * a.nx + wrap(x + 1, a.nx)] - lnMin[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx);
+  const R gy = (R)((lnMin[wrap(y + 1, a.ny) * a.nx + x] - lnMin[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx);
+
+  // ---- 1: the slice; S2 (radial), Milne term S1/tau and streaming ----
   R f[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) f[q] = Buf<R>::ld(plane_rsrc(Fin + (size_t)q * plane, pbytes), me);
-  R p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    p0 += C.wx2[q] * f[q];
-    p1 += C.wxs[q] * f[q];
-    p2 += C.ws2[q] * f[q];
-    p3 += C.w[q] * f[q];
-  }
-  const R cl = C.cosl[l], sl = C.sinl[l];
-  {
-    const R m00 = sum8(p0), m01 = sum8(p1 * cl), m02 = sum8(p1 * sl);
-    const R m11 = sum8(p2 * cl * cl), m12 = sum8(p2 * cl * sl), m22 = sum8(p2 * sl * sl);
-    if (l == 0) {
-      s_mom[0][ts] = (double)m00;
-      s_mom[1][ts] = (double)m01;
-      s_mom[2][ts] = (double)m02;
-      s_mom[3][ts] = (double)m11;
-      s_mom[4][ts] = (double)m12;
-      s_mom[5][ts] = (double)m22;
-    }
-  }
-  const R wF = sum8(p3);
-  __syncthreads();
-
-  // ---- phase 2a: per-site FP64 work, one lane per site (first wave) ----
-  if (t < kTile) {
-    const int sx = bx * kTX + (t % kTX), sy = by * kTY + (t / kTX);
-    if (sx < a.nx && sy < a.ny) {
-      const int ss = sy * a.nx + sx;
-      const double lnM = lnMin[ss];
-      const double M = exp(lnM);
-      const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
-      double tk[6];
-      bool finite = true;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        tk[i] = G * s_mom[i][t];
-        finite = finite && isfinite(tk[i]);
-      }
-      double lam, u[3];
-      const bool matched = landau3(tk, &lam, u);
-      EosAt E;
-      const bool eos_ok = eos_cell(tb, lam, &E);
-      if (!finite) flag(err, kErrNonfinite);
-      else if (!matched) flag(err, kErrMatch);
-      else if (!eos_ok) flag(err, kErrEos);
-      const int xp = wrap(sx + 1, a.nx), xm = wrap(sx - 1, a.nx);
-      const int yp = wrap(sy + 1, a.ny), ym = wrap(sy - 1, a.ny);
-      s_sc[kSiT][t] = E.T;
-      s_sc[kSiU0][t] = u[0];
-      s_sc[kSiU1][t] = u[1];
-      s_sc[kSiU2][t] = u[2];
-      s_sc[kSiMeq][t] = E.M_eq;
-      s_sc[kSiRate][t] = E.T * a.inv_eta_hbarc / E.q;  // 1/tau_R [fm^-1]
-      s_sc[kSiBeta][t] = E.beta;
-      s_sc[kSiGx][t] = (lnMin[sy * a.nx + xp] - lnMin[sy * a.nx + xm]) * a.inv2dx;
-      s_sc[kSiGy][t] = (lnMin[yp * a.nx + sx] - lnMin[ym * a.nx + sx]) * a.inv2dx;
-      s_sc[kSiM][t] = M;
-      s_sc[kSiLnM][t] = lnM;
-    } else {
-#pragma unroll
-      for (int i = 0; i < kSiN; ++i) s_sc[i][t] = 1.0;
-    }
-  }
-
-  // ---- phase 2b: S2 (radial), Milne term S1/tau and streaming ----
+  const R cl = C->cosl[l], sl = C->sinl[l];
   R S2[Q], R0[Q];
-  const R s1scale = (a.metric == LB_METRIC_MILNE) ? (R)(1.0 / a.tau) : (R)0;
 #pragma unroll
   for (int k = 0; k < NXI; ++k) {
 #pragma unroll
     for (int j = 0; j < NTH; ++j) {
-      R s2 = 0, s1r = 0, s1t = 0;
+      R s2 = 0;
+#pragma unroll
+      for (int kp = 0; kp < NXI; ++kp) s2 += C->A2[k * NXI + kp] * f[kp * NTH + j];
+      S2[k * NTH + j] = s2;
+    }
+    const R* fk = &f[k * NTH];
+    const R e0 = fk[0] + fk[4], e1 = fk[1] + fk[3], o0 = fk[0] - fk[4], o1 = fk[1] - fk[3], c2 = fk[2];
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+      const R ev = C->Ev[pr][0] * e0 + C->Ev[pr][1] * e1 + C->Ev[pr][2] * c2;
+      const R od = C->Od[pr][0] * o0 + C->Od[pr][1] * o1;
+      R sa = 0, sb = 0;
 #pragma unroll
       for (int kp = 0; kp < NXI; ++kp) {
-        s2 += C.A2[k * NXI + kp] * f[kp * NTH + j];
-        s1r += C.A1[k * NXI + kp] * f[kp * NTH + j];
+        sa += C->A1[k * NXI + kp] * f[kp * NTH + pr];
+        sb += C->A1[k * NXI + kp] * f[kp * NTH + 4 - pr];
       }
-#pragma unroll
-      for (int jp = 0; jp < NTH; ++jp) s1t += C.Ath[j * NTH + jp] * f[k * NTH + jp];
-      S2[k * NTH + j] = s2;
-      R0[k * NTH + j] = (C.mu2[j] * s1r - s1t) * s1scale;
+      R0[k * NTH + pr] = C->mu2[pr] * sa + (ev + od);
+      R0[k * NTH + 4 - pr] = C->mu2[pr] * sb + (ev - od);
     }
+    R0[k * NTH + 2] = C->Mid[0] * e0 + C->Mid[1] * e1 + C->Mid[2] * c2;  // mu = 0: no radial part
   }
   {
     // second-order upwind along +(cos phi, sin phi): x-1, x-2 etc., periodic
@@ -361,98 +454,142 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, MinWaves<R>::v) void st
     const uint32_t sx2 = ((uint32_t)(y * a.nx + wrap(x - 2 * dxr, a.nx)) * kSl + l) * es;
     const uint32_t sy1 = ((uint32_t)(wrap(y - dyr, a.ny) * a.nx + x) * kSl + l) * es;
     const uint32_t sy2 = ((uint32_t)(wrap(y - 2 * dyr, a.ny) * a.nx + x) * kSl + l) * es;
-    // (3 F_i - 4 F_{i-1} + F_{i-2}) |cos phi|/(2 dx) + the same along y
-    const R ax = (R)(fabs((double)cl) * a.inv2dx), ay = (R)(fabs((double)sl) * a.inv2dx);
+    // (3 F_i - 4 F_{i-1} + F_{i-2}) |cos phi|/(2 dx) + the same along y, times
+    // tau_s (the stage works with R0' = tau_s R0, see below)
+    const R ax = (R)(fabs((double)cl) * a.inv2dx * a.tau_s), ay = (R)(fabs((double)sl) * a.inv2dx * a.tau_s);
     const R c0 = (R)3 * (ax + ay), c1 = (R)(-4) * ax, c2 = (R)(-4) * ay;
 #pragma unroll
     for (int k = 0; k < NXI; ++k) {
 #pragma unroll
       for (int j = 0; j < NTH; ++j) {
         const int q = k * NTH + j;
+        const int i = k * 3 + (j < 3 ? j : 4 - j);
         const __amdgpu_buffer_rsrc_t rq = plane_rsrc(Fin + (size_t)q * plane, pbytes);
         const R fx1 = Buf<R>::ld(rq, sx1), fx2 = Buf<R>::ld(rq, sx2);
         const R fy1 = Buf<R>::ld(rq, sy1), fy2 = Buf<R>::ld(rq, sy2);
         const R tr = c0 * f[q] + c1 * fx1 + ax * fx2 + c2 * fy1 + ay * fy2;
-        R0[q] -= C.sigi[q] * tr;  // -(|v_perp|/gamma) along (cos, sin)
+        R0[q] -= C->sigi[i] * tr;  // -(|v_perp|/gamma) along (cos, sin)
       }
     }
   }
-  __syncthreads();
-  const double Td = s_sc[kSiT][ts], beta = s_sc[kSiBeta][ts], lnM = s_sc[kSiLnM][ts];
-  const double gx = s_sc[kSiGx][ts], gy = s_sc[kSiGy][ts];
-  const double u1d = s_sc[kSiU1][ts], u2d = s_sc[kSiU2][ts];
-  const double u0d = s_sc[kSiU0][ts], Md = s_sc[kSiM][ts], Meqd = s_sc[kSiMeq][ts];
-  const double rated = s_sc[kSiRate][ts];
 
-  // ---- phase 3: equilibrium, BGK, mass-gradient force, sums, update ----
-  const R ut = (R)u0d, ux = (R)u1d, uy = (R)u2d;
-  const R Mr = (R)Md, Meq = (R)Meqd;
-  const R rr = (R)rated;
-  const R MinvT = (R)(Md / Td);
-  const R l2invT = (R)(1.4426950408889634 / Td);  // log2(e)/T
+  // ---- 2: equilibrium, BGK, mass-gradient force, sums, update ----
   const R cu = ux * cl + uy * sl;            // u_perp . (cos phi, sin phi)
-  const R Gl = (R)gx * cl + (R)gy * sl;      // grad ln M . (cos phi, sin phi)
-  const R gu = (R)(gx * u1d + gy * u2d);     // grad ln M . u_perp
+  const R Gl = gx * cl + gy * sl;            // grad ln M . (cos phi, sin phi)
+  const R gu = gx * ux + gy * uy;            // grad ln M . u_perp
   // Per node, with s = |v_perp| and gamma = cosh xi:
   //   F_eq = Z exp(-[u^tau E_eq - M s (u.phi)]/T) = exp2(s Mcu2 + aE_k),
   //   BGK  = r (u.V/gamma) (F - F_eq), r = 1/tau_R,
   //   mass-gradient force on F_eq = -F_eq (al_k s - be_k s^2 - ga_k),
   // so r0 = R0 + F_eq (r u.V/gamma - poly) - r (u.V/gamma) F.
+  // The Milne factor 1/tau of S1 is not in the constants: every term of r0
+  // is carried times tau_s (tau for Milne, 1 for Minkowski, where the S1
+  // constants are zero), r0' = tau_s r0, and divided out in X and the update.
   const R Mcu2 = Mr * cu * l2invT;
   const R log2Z = (R)a.log2Z;
+  const R ts_ = (R)a.tau_s;
+  const R rrt = rr * ts_;
+  const R utl2 = ut * l2invT, alc = MinvT * Gl * ut * Mr * ts_, bec = MinvT * Gl * cu * ts_, gac = MinvT * gu * ts_;
   R aE[NXI], al[NXI], be[NXI], ga[NXI];
 #pragma unroll
   for (int k = 0; k < NXI; ++k) {
-    const R Eeq = rsqrt_<R>(Meq * Meq + Mr * Mr * C.sh2[k]);  // sqrt(M_eq^2 + M^2 sinh^2 xi)
-    aE[k] = log2Z - ut * Eeq * l2invT;
-    al[k] = MinvT * Gl * ut * Mr * C.x[k] / Eeq;
-    be[k] = MinvT * Gl * cu * C.inv_x[k];
-    ga[k] = MinvT * gu * C.inv_x[k];
+    const R Eeq = nsqrt<R>(Meq * Meq + Mr * Mr * C->sh2[k]);  // sqrt(M_eq^2 + M^2 sinh^2 xi)
+    aE[k] = log2Z - utl2 * Eeq;
+    al[k] = alc * C->x[k] * nrcp<R>(Eeq);
+    be[k] = bec * C->inv_x[k];
+    ga[k] = gac * C->inv_x[k];
   }
-  R nsum = 0, dsum = 0;
+  R nsum = 0, dsum = 0, wsum = 0;
 #pragma unroll
   for (int k = 0; k < NXI; ++k) {
 #pragma unroll
-    for (int j = 0; j < NTH; ++j) {
-      const int q = k * NTH + j;
-      const R sg = C.sig[q];
-      const R fq = f[q];
+    for (int pr = 0; pr < 3; ++pr) {
+      const int i = k * 3 + pr;
+      const R sg = C->sig[i];
       const R feq = eq_exp2<R>(sg * Mcu2 + aE[k]);             // F_eq (Sec. IV.D, with flow)
-      const R uvg = ut - C.sigi[q] * cu;                       // (u.V)/gamma
-      const R ru = rr * uvg;
-      const R poly = al[k] * sg - be[k] * C.sig2[q] - ga[k];
-      R r0 = R0[q] + feq * (ru - poly);
-      r0 -= ru * fq;                                           // BGK, eq. (bgk)
-      const R wuv2 = C.wx2[q] * uvg * uvg;                     // w (u.V)^2
-      nsum += wuv2 * r0;
-      dsum += wuv2 * ((R)4 * fq + S2[q]);
-      R0[q] = r0;
+      const R uvg = ut - C->sigi[i] * cu;                       // (u.V)/gamma
+      const R ru = rrt * uvg;
+      const R poly = al[k] * sg - be[k] * C->sig2[i] - ga[k];
+      const R fd = feq * (ru - poly);
+      const R wuv2 = C->wx2[i] * uvg * uvg;                     // w gamma^2 ((u.V)/gamma)^2
+      if (pr < 2) {
+        const int qa = k * NTH + pr, qb = k * NTH + 4 - pr;
+        const R ra = (R0[qa] + fd) - ru * f[qa];               // BGK, eq. (bgk)
+        const R rb = (R0[qb] + fd) - ru * f[qb];
+        R0[qa] = ra;
+        R0[qb] = rb;
+        const R fs = f[qa] + f[qb];
+        nsum += wuv2 * (ra + rb);
+        dsum += wuv2 * ((R)4 * fs + (S2[qa] + S2[qb]));
+        wsum += C->w[i] * fs;
+      } else {
+        const int q = k * NTH + 2;
+        const R r = (R0[q] + fd) - ru * f[q];
+        R0[q] = r;
+        nsum += wuv2 * r;
+        dsum += wuv2 * ((R)4 * f[q] + S2[q]);
+        wsum += C->w[i] * f[q];
+      }
     }
   }
   nsum = sum8(nsum);
   dsum = sum8(dsum);
+  wsum = sum8(wsum);
 
-  // ---- mass evolution (eq. (masschange)), FP64 ----
-  const double X = -beta * (double)nsum / ((double)wF + beta * (double)dsum);
-  const R Xr = (R)X;
-  const R dt = (R)a.dtau;
-
-  if (valid) {
-    if (STAGE == 0) {
+  // mass evolution (eq. (masschange)), FP64
+  const double X = -beta * ((double)nsum * a.inv_tau_s) / ((double)wsum + beta * (double)dsum);
+  const R Xr = (R)(X * a.tau_s);
+  double lnM_new;
+  if (STAGE == 0) {
+    const R dt = (R)(a.dtau * a.inv_tau_s);
 #pragma unroll
-      for (int q = 0; q < Q; ++q)
-        Buf<R>::st(plane_rsrc(Fout + (size_t)q * plane, pbytes), me, f[q] + dt * (R0[q] + Xr * S2[q]));
-      if (l == 0) lnMout[site] = lnM + a.dtau * X;
-    } else {
-      const R hdt = (R)(0.5 * a.dtau);
+    for (int q = 0; q < Q; ++q) f[q] = f[q] + dt * (R0[q] + Xr * S2[q]);
+    lnM_new = lnM + a.dtau * X;
+  } else {
+    const R hdt = (R)(0.5 * a.dtau * a.inv_tau_s);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const R fb = Buf<R>::ld(plane_rsrc(Fbase + (size_t)q * plane, pbytes), me);
-        Buf<R>::st(plane_rsrc(Fout + (size_t)q * plane, pbytes), me, (R)0.5 * (fb + f[q]) + hdt * (R0[q] + Xr * S2[q]));
-      }
-      if (l == 0) lnMout[site] = 0.5 * (lnMbase[site] + lnM) + 0.5 * a.dtau * X;
+    for (int q = 0; q < Q; ++q) {
+      const R fb = Buf<R>::ld(plane_rsrc(Fbase + (size_t)q * plane, pbytes), me);
+      f[q] = (R)0.5 * (fb + f[q]) + hdt * (R0[q] + Xr * S2[q]);
     }
+    lnM_new = 0.5 * (lnMbase[site] + lnM) + 0.5 * a.dtau * X;
   }
+  if (valid) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) Buf<R>::st(plane_rsrc(Fout + (size_t)q * plane, pbytes), me, f[q]);
+    if (l == 0) lnMout[site] = lnM_new;
+  }
+
+  // ---- 3: matching of the new state for the next stage ----
+  match_tile<R, kTY>(f, C, lnM_new, t, bx, by, tb, a, scout, err, s_mom);
+}
+
+// Site scalars of a state that no stage produced (after lb_init or
+// lb_set_state): the matching phase of the stage kernel on its own.
+template <typename R>
+__global__ __launch_bounds__(kTX * TileRows<R>::v * kSl) void site_kernel(
+    const R* __restrict__ F, const double* __restrict__ lnMv, double* __restrict__ sc,
+    const StageConst<R>* __restrict__ Cg, const EosTable tb, const StageArgs a, int* __restrict__ err) {
+  const CPtr<R> C = const_ptr(Cg);
+  constexpr int kTY = TileRows<R>::v;
+  __shared__ double s_mom[7][kTX * kTY];
+  const int t = threadIdx.x;
+  const int ts = t >> 3, l = t & 7;
+  const int tiles_x = (a.nx + kTX - 1) / kTX;
+  const int n_tiles = tiles_x * ((a.ny + kTY - 1) / kTY);
+  const int tile = xcd_tile(n_tiles);
+  if (tile >= n_tiles) return;
+  const int bx = tile % tiles_x, by = tile / tiles_x;
+  const int x0 = bx * kTX + (ts % kTX), y0 = by * kTY + (ts / kTX);
+  const bool valid = (x0 < a.nx) && (y0 < a.ny);
+  const int site = valid ? y0 * a.nx + x0 : 0;
+  const uint32_t plane = (uint32_t)a.n_sites * kSl;
+  const uint32_t pbytes = plane * (uint32_t)sizeof(R);
+  const uint32_t me = ((uint32_t)site * kSl + l) * (uint32_t)sizeof(R);
+  R f[25];
+#pragma unroll
+  for (int q = 0; q < 25; ++q) f[q] = Buf<R>::ld(plane_rsrc(F + (size_t)q * plane, pbytes), me);
+  match_tile<R, kTY>(f, C, lnMv[site], t, bx, by, tb, a, sc, err, s_mom);
 }
 
 // Initial local equilibrium (Sec. IV.D): T0 from eps_EoS(T0) = e0.
@@ -596,29 +733,45 @@ inline dim3 grid_for(int n_sites) { return dim3((unsigned)(((size_t)n_sites * kS
 }  // namespace
 
 hipError_t launch_stage(int precision, int stage, const void* Fin, const void* Fbase, void* Fout,
-                        const double* lnMin, const double* lnMbase, double* lnMout, const void* lc,
-                        const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
+                        const double* lnMin, const double* lnMbase, double* lnMout, const double* scin,
+                        double* scout, const void* sc, const EosTable& tb, const StageArgs& a, int* err,
+                        hipStream_t s) {
   const int ty = precision == LB_FP32_FP64MATCH ? TileRows<float>::v : TileRows<double>::v;
   const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
   const unsigned per = (tiles + kXcds - 1) / kXcds;
   const dim3 g(per * kXcds), b(kTX * ty * kSl);
   if (precision == LB_FP32_FP64MATCH) {
-    const auto& C = *static_cast<const LatticeConst<float, 5, 5>*>(lc);
+    const auto* C = static_cast<const StageConst<float>*>(sc);
     if (stage == 0)
-      hipLaunchKernelGGL((stage_kernel<float, 5, 5, 0>), g, b, 0, s, (const float*)Fin, (const float*)Fbase,
-                         (float*)Fout, lnMin, lnMbase, lnMout, C, tb, a, err);
+      hipLaunchKernelGGL((stage_kernel<float, 0>), g, b, 0, s, (const float*)Fin, (const float*)Fbase,
+                         (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
     else
-      hipLaunchKernelGGL((stage_kernel<float, 5, 5, 1>), g, b, 0, s, (const float*)Fin, (const float*)Fbase,
-                         (float*)Fout, lnMin, lnMbase, lnMout, C, tb, a, err);
+      hipLaunchKernelGGL((stage_kernel<float, 1>), g, b, 0, s, (const float*)Fin, (const float*)Fbase,
+                         (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
   } else {
-    const auto& C = *static_cast<const LatticeConst<double, 5, 5>*>(lc);
+    const auto* C = static_cast<const StageConst<double>*>(sc);
     if (stage == 0)
-      hipLaunchKernelGGL((stage_kernel<double, 5, 5, 0>), g, b, 0, s, (const double*)Fin,
-                         (const double*)Fbase, (double*)Fout, lnMin, lnMbase, lnMout, C, tb, a, err);
+      hipLaunchKernelGGL((stage_kernel<double, 0>), g, b, 0, s, (const double*)Fin, (const double*)Fbase,
+                         (double*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
     else
-      hipLaunchKernelGGL((stage_kernel<double, 5, 5, 1>), g, b, 0, s, (const double*)Fin,
-                         (const double*)Fbase, (double*)Fout, lnMin, lnMbase, lnMout, C, tb, a, err);
+      hipLaunchKernelGGL((stage_kernel<double, 1>), g, b, 0, s, (const double*)Fin, (const double*)Fbase,
+                         (double*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_site(int precision, const void* F, const double* lnM, double* scout, const void* sc,
+                       const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
+  const int ty = precision == LB_FP32_FP64MATCH ? TileRows<float>::v : TileRows<double>::v;
+  const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
+  const unsigned per = (tiles + kXcds - 1) / kXcds;
+  const dim3 g(per * kXcds), b(kTX * ty * kSl);
+  if (precision == LB_FP32_FP64MATCH)
+    hipLaunchKernelGGL(site_kernel<float>, g, b, 0, s, (const float*)F, lnM, scout,
+                       static_cast<const StageConst<float>*>(sc), tb, a, err);
+  else
+    hipLaunchKernelGGL(site_kernel<double>, g, b, 0, s, (const double*)F, lnM, scout,
+                       static_cast<const StageConst<double>*>(sc), tb, a, err);
   return hipGetLastError();
 }
 
