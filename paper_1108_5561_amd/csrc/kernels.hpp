@@ -9,11 +9,12 @@ namespace lbmi {
 
 enum : int { kErrNonfinite = 1, kErrMatch = 2, kErrEos = 4 };
 
-// Site scalars of a state (Landau matching and EoS of it), one buffer per
-// state: beta [n_sites] in FP64, then kScN planes [n_sites] of the node type:
-// u^tau, u^x, u^y, M, M_eq = M(T), 1/tau_R [fm^-1], M/T, log2(e)/T.
+// Site scalars of a state (Landau matching and EoS of it): one record per
+// site, 16-byte aligned: kScN values of the node type (u^tau, u^x, u^y, M,
+// M_eq = M(T), 1/tau_R [fm^-1], M/T, log2(e)/T), then beta and ln M in FP64.
 enum : int { kScUt = 0, kScUx, kScUy, kScM, kScMeq, kScRate, kScMinvT, kScL2invT, kScN };
-inline size_t site_scalar_bytes(size_t n_sites, size_t elt) { return n_sites * (8 + kScN * elt); }
+inline size_t site_record_bytes(size_t elt) { return kScN * elt + 16; }
+inline size_t site_scalar_bytes(size_t n_sites, size_t elt) { return n_sites * site_record_bytes(elt); }
 
 struct StageArgs {
   int32_t nx, ny, n_sites;
@@ -51,7 +52,7 @@ hipError_t launch_moments(int precision, const void* F, const double* lnM, doubl
                           const void* latconst, const EosTable& tb, const StageArgs& a, int* err,
                           hipStream_t s);
 
-// Canonical [N][sites] FP64 <-> internal [q][sites][8] (precision).
+// Canonical [N][sites] FP64 <-> internal node layout (precision).
 hipError_t launch_get_state(int precision, const void* F, double* Fc, int n_q, int n_sites,
                             hipStream_t s);
 hipError_t launch_set_state(int precision, const double* Fc, void* F, int n_q, int n_sites,

@@ -64,6 +64,13 @@ std::string validate(const lb_params* p) {
   if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
   // a node plane (8 slices x sites, FP64) must be addressable with 32-bit byte offsets
   if ((int64_t)p->nx * p->ny >= ((int64_t)1 << 26)) return "grid too large (nx*ny must be below 2^26 sites)";
+  {
+    // the kernels address one distribution buffer with 32-bit byte offsets
+    const int64_t elt = p->precision == LB_FP64 ? 8 : 4;
+    const int64_t nodes = (int64_t)p->n_xi * p->n_theta * 2 * p->n_phi;
+    if ((int64_t)p->nx * p->ny * nodes * elt > (int64_t)0xFFFFFFFF)
+      return "grid too large: one distribution buffer (nx*ny*N values) must stay below 4 GiB";
+  }
   if (!(p->dx_fm > 0) || !std::isfinite(p->dx_fm)) return "dx_fm must be finite and > 0";
   if (!std::isfinite(p->tau0_fm)) return "tau0_fm must be finite";
   if (p->metric == LB_METRIC_MILNE && !(p->tau0_fm > 0)) return "tau0_fm must be > 0 for the Milne metric";

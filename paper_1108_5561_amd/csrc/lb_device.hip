@@ -22,16 +22,39 @@ namespace lbmi {
 constexpr int kSl = 8;        // phi slices (n_phi = 4)
 constexpr int kBlock = 256;   // 32 sites per block
 
+// Periodic index for i within two of [0, n), n >= 1 (two corrections on
+// each side cover n = 1); compare-and-select, no integer division.
 __device__ __forceinline__ int wrap(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
+  i = i < 0 ? i + n : i;
+  i = i < 0 ? i + n : i;
+  i = i >= n ? i - n : i;
+  i = i >= n ? i - n : i;
+  return i;
 }
 
-template <typename R>
-__device__ __forceinline__ R sum8(R v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
+// Sum over the eight lanes of a site (lanes 8s .. 8s + 7) with DPP moves:
+// swap neighbours, swap pairs, then mirror within the eight.  Every lane
+// ends with the same bits (each step adds two equal-rank partial sums, and
+// floating-point addition is commutative).
+__device__ __forceinline__ int dpp8(int x, int step) {
+  switch (step) {
+    case 0: return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    default: return __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false); // row_half_mirror
+  }
+}
+__device__ __forceinline__ float sum8(float v) {
+#pragma unroll
+  for (int st = 0; st < 3; ++st) v += __int_as_float(dpp8(__float_as_int(v), st));
+  return v;
+}
+__device__ __forceinline__ double sum8(double v) {
+#pragma unroll
+  for (int st = 0; st < 3; ++st) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)dpp8((int)(uint32_t)b, st), hi = (uint32_t)dpp8((int)(uint32_t)(b >> 32), st);
+    v += __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  }
   return v;
 }
 
@@ -201,31 +224,136 @@ template <typename R, int STAGE> struct MinWaves {
 };
 template <int STAGE> struct MinWaves<double, STAGE> { static constexpr int v = LB_WAVES_PER_EU_F64; };
 
-// Node planes are read and written as raw buffers: one descriptor per plane
-// (uniform, built with scalar instructions) and a 32-bit byte offset per
-// lane, so no per-load vector address arithmetic.  Out-of-range offsets
-// read 0 and drop writes.
+// A distribution buffer is read and written as one raw buffer: one
+// descriptor (uniform, scalar registers), the plane offset q * plane bytes
+// as the scalar offset and a 32-bit byte offset per lane, so no per-load
+// vector address arithmetic.  Out-of-range offsets read 0 and drop writes;
+// the host keeps a buffer below 4 GiB.
 typedef unsigned lb_v2u __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, uint32_t bytes) {
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
 }
 template <typename R> struct Buf;
 template <> struct Buf<float> {
-  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
   }
-  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, (int)soff, 0);
   }
 };
 template <> struct Buf<double> {
-  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0));
   }
-  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lb_v2u, v), r, (int)off, 0, 0);
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(lb_v2u, v), r, (int)off, (int)soff, 0);
   }
 };
+
+// 16-byte vector access (dwordx4): one instruction moves V = 16 / sizeof(R)
+// values of a lane.
+typedef unsigned lb_v4u __attribute__((ext_vector_type(4)));
+template <typename R>
+__device__ __forceinline__ void ld_vec(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, R* out) {
+  // the whole vector is reinterpreted at once (a bit cast of a single
+  // vector element is not used: it does not survive the load narrowing)
+  typedef R lb_vr __attribute__((ext_vector_type(16 / sizeof(R))));
+  const lb_vr v = __builtin_bit_cast(lb_vr, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)soff, 0));
+#pragma unroll
+  for (int i = 0; i < (int)(16 / sizeof(R)); ++i) out[i] = v[i];
+}
+template <typename R>
+__device__ __forceinline__ void st_vec(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, const R* in) {
+  typedef R lb_vr __attribute__((ext_vector_type(16 / sizeof(R))));
+  lb_vr v;
+#pragma unroll
+  for (int i = 0; i < (int)(16 / sizeof(R)); ++i) v[i] = in[i];
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(lb_v4u, v), r, (int)off, (int)soff, 0);
+}
+
+// Distribution layout in HBM.  The 25 nodes q = k N_theta + j of a slice
+// (site, l) are stored in groups of V = 16 / sizeof(R) consecutive nodes,
+// group g = q / V in plane g as [site][l][V]; the last node (q = 24) in a
+// plane of its own, [site][l].  A lane moves its slice with 24 / V + 1
+// instructions, a wavefront (8 sites x 8 slices) 1 KB per group.
+template <typename R>
+struct NodeLayout {
+  static constexpr int V = 16 / (int)sizeof(R);
+  static constexpr int NG = 24 / V;  // full groups
+  // bytes of one group plane
+  static __device__ __host__ uint32_t gbytes(int n_sites) { return (uint32_t)n_sites * kSl * 16u; }
+  // byte offset of node q of slice (site, l)
+  static __device__ __host__ size_t offset(int q, int site, int l, int n_sites) {
+    const size_t lane = (size_t)site * kSl + l;
+    if (q < NG * V) return (size_t)(q / V) * gbytes(n_sites) + (lane * V + (size_t)(q % V)) * sizeof(R);
+    return (size_t)NG * gbytes(n_sites) + lane * sizeof(R);
+  }
+};
+
+// Slice of lane index lane = site * 8 + l: load / store all 25 nodes.
+template <typename R>
+__device__ __forceinline__ void load_slice(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t gb, R f[25]) {
+  using L = NodeLayout<R>;
+#pragma unroll
+  for (int g = 0; g < L::NG; ++g) ld_vec<R>(r, lane * 16u, g * gb, &f[g * L::V]);
+  f[24] = Buf<R>::ld(r, lane * (uint32_t)sizeof(R), L::NG * gb);
+}
+template <typename R>
+__device__ __forceinline__ void store_slice(__amdgpu_buffer_rsrc_t r, uint32_t lane, uint32_t gb, const R f[25]) {
+  using L = NodeLayout<R>;
+#pragma unroll
+  for (int g = 0; g < L::NG; ++g) st_vec<R>(r, lane * 16u, g * gb, &f[g * L::V]);
+  Buf<R>::st(r, lane * (uint32_t)sizeof(R), L::NG * gb, f[24]);
+}
+
+// Site record (kernels.hpp): kScN values of R, then beta and ln M (FP64).
+template <typename R>
+struct SiteRecord {
+  static constexpr uint32_t kBytes = kScN * (uint32_t)sizeof(R) + 16u;
+  static constexpr int kVecs = (int)(kBytes / 16u);
+  R v[kScN];
+  double beta, lnM;
+};
+template <typename R>
+__device__ __forceinline__ SiteRecord<R> load_record(__amdgpu_buffer_rsrc_t r, int site) {
+  SiteRecord<R> rec;
+  R w[SiteRecord<R>::kVecs * NodeLayout<R>::V];
+#pragma unroll
+  for (int i = 0; i < SiteRecord<R>::kVecs; ++i)
+    ld_vec<R>(r, (uint32_t)site * SiteRecord<R>::kBytes + 16u * i, 0, &w[i * NodeLayout<R>::V]);
+#pragma unroll
+  for (int i = 0; i < kScN; ++i) rec.v[i] = w[i];
+  if constexpr (sizeof(R) == 4) {
+    rec.beta = __builtin_bit_cast(double, (uint64_t)__builtin_bit_cast(unsigned, w[kScN]) |
+                                              ((uint64_t)__builtin_bit_cast(unsigned, w[kScN + 1]) << 32));
+    rec.lnM = __builtin_bit_cast(double, (uint64_t)__builtin_bit_cast(unsigned, w[kScN + 2]) |
+                                             ((uint64_t)__builtin_bit_cast(unsigned, w[kScN + 3]) << 32));
+  } else {
+    rec.beta = (double)w[kScN];
+    rec.lnM = (double)w[kScN + 1];
+  }
+  return rec;
+}
+template <typename R>
+__device__ __forceinline__ void store_record(__amdgpu_buffer_rsrc_t r, int site, const SiteRecord<R>& rec) {
+  R w[SiteRecord<R>::kVecs * NodeLayout<R>::V];
+#pragma unroll
+  for (int i = 0; i < kScN; ++i) w[i] = rec.v[i];
+  if constexpr (sizeof(R) == 4) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, rec.beta), m = __builtin_bit_cast(uint64_t, rec.lnM);
+    w[kScN] = __builtin_bit_cast(R, (unsigned)b);
+    w[kScN + 1] = __builtin_bit_cast(R, (unsigned)(b >> 32));
+    w[kScN + 2] = __builtin_bit_cast(R, (unsigned)m);
+    w[kScN + 3] = __builtin_bit_cast(R, (unsigned)(m >> 32));
+  } else {
+    w[kScN] = rec.beta;
+    w[kScN + 1] = rec.lnM;
+  }
+#pragma unroll
+  for (int i = 0; i < SiteRecord<R>::kVecs; ++i)
+    st_vec<R>(r, (uint32_t)site * SiteRecord<R>::kBytes + 16u * i, 0, &w[i * NodeLayout<R>::V]);
+}
 
 // Node arithmetic helpers: hardware exp2 / sqrt / reciprocal in FP32 (about
 // 1 ulp), the correctly rounded library functions in FP64.
@@ -251,16 +379,6 @@ __device__ __forceinline__ CPtr<R> const_ptr(const StageConst<R>* p) {
   asm volatile("" : "+s"(v));
   return (CPtr<R>)v;
 }
-// Site scalars of a state (kernels.hpp: kScN planes of R after an FP64 beta
-// plane): what the node arithmetic of a stage needs from Landau matching and
-// the EoS.
-template <typename R>
-__device__ __forceinline__ R* sc_planes(double* sc, int n_sites) { return reinterpret_cast<R*>(sc + n_sites); }
-template <typename R>
-__device__ __forceinline__ const R* sc_planes(const double* sc, int n_sites) {
-  return reinterpret_cast<const R*>(sc + n_sites);
-}
-
 // Partial moments of one slice over the mirror pairs: w gamma^2, w gamma
 // |v_perp|, w |v_perp|^2 and w, summed over the 25 nodes (eq. (emtnew)).
 template <typename R>
@@ -332,17 +450,18 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   else if (!matched) flag(err, kErrMatch);
   else if (!eos_ok) flag(err, kErrEos);
   const double invT = 1.0 / E.T;
-  R* P = sc_planes<R>(sc, a.n_sites);
-  const size_t n = (size_t)a.n_sites;
-  sc[ss] = E.beta;
-  P[kScUt * n + ss] = (R)u[0];
-  P[kScUx * n + ss] = (R)u[1];
-  P[kScUy * n + ss] = (R)u[2];
-  P[kScM * n + ss] = (R)M;
-  P[kScMeq * n + ss] = (R)E.M_eq;
-  P[kScRate * n + ss] = (R)(E.T * a.inv_eta_hbarc / E.q);  // 1/tau_R [fm^-1]
-  P[kScMinvT * n + ss] = (R)(M * invT);
-  P[kScL2invT * n + ss] = (R)(1.4426950408889634 * invT);  // log2(e)/T
+  SiteRecord<R> rec;
+  rec.v[kScUt] = (R)u[0];
+  rec.v[kScUx] = (R)u[1];
+  rec.v[kScUy] = (R)u[2];
+  rec.v[kScM] = (R)M;
+  rec.v[kScMeq] = (R)E.M_eq;
+  rec.v[kScRate] = (R)(E.T * a.inv_eta_hbarc / E.q);  // 1/tau_R [fm^-1]
+  rec.v[kScMinvT] = (R)(M * invT);
+  rec.v[kScL2invT] = (R)(1.4426950408889634 * invT);  // log2(e)/T
+  rec.beta = E.beta;
+  rec.lnM = s_mom[6][t];
+  store_record<R>(buf_rsrc(sc, (uint32_t)a.n_sites * SiteRecord<R>::kBytes), ss, rec);
 }
 
 // Tile of a block in the XCD-aware order: workgroups go round-robin over the
@@ -398,27 +517,72 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, (MinWaves<R, STAGE>::v)
   const LaneSite g = lane_site<R, kTY>(tile, tiles_x, ts, l, a);
   const int bx = g.bx, by = g.by, x = g.x, y = g.y, site = g.site;
   const bool valid = g.valid;
-  const uint32_t me = g.me;
-  const uint32_t plane = (uint32_t)a.n_sites * kSl;
-  const uint32_t pbytes = plane * (uint32_t)sizeof(R);
-  const size_t n = (size_t)a.n_sites;
+  const uint32_t lane = (uint32_t)site * kSl + l;  // slice index in a plane
+  using NL = NodeLayout<R>;
+  const uint32_t gb = NL::gbytes(a.n_sites);
+  const uint32_t fbytes = (uint32_t)a.n_sites * kSl * 25u * (uint32_t)sizeof(R);
 
-  // ---- site scalars of the input state; ln M and its centred gradient ----
-  const R* P = sc_planes<R>(scin, a.n_sites);
-  const double beta = scin[site];
-  const R ut = P[kScUt * n + site], ux = P[kScUx * n + site], uy = P[kScUy * n + site];
-  const R Mr = P[kScM * n + site], Meq = P[kScMeq * n + site], rr = P[kScRate * n + site];
-  const R MinvT = P[kScMinvT * n + site], l2invT = P[kScL2invT * n + site];
-  const double lnM = lnMin[site];
-  const R gx = (R)((lnMin[y * a.nx + wrap(x + 1, a.nx)] - lnMin[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx);
-  const R gy = (R)((lnMin[wrap(y + 1, a.ny) * a.nx + x] - lnMin[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx);
-
-  // ---- 1: the slice; S2 (radial), Milne term S1/tau and streaming ----
+  // ---- 1: the slice; streaming (its loads right behind the slice's); the
+  // site scalars of the input state; S2 (radial) and the Milne term S1/tau ----
+  const __amdgpu_buffer_rsrc_t rin = buf_rsrc(Fin, fbytes);
   R f[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) f[q] = Buf<R>::ld(plane_rsrc(Fin + (size_t)q * plane, pbytes), me);
+  load_slice<R>(rin, lane, gb, f);
+  __builtin_amdgcn_sched_barrier(0);
   const R cl = C->cosl[l], sl = C->sinl[l];
   R S2[Q], R0[Q];
+  {
+    // second-order upwind along +(cos phi, sin phi): x-1, x-2 etc., periodic
+    const int dxr = (cl > (R)0) ? 1 : ((cl < (R)0) ? -1 : 0);
+    const int dyr = (sl > (R)0) ? 1 : ((sl < (R)0) ? -1 : 0);
+    // slice indices of the upwind neighbours
+    const uint32_t nx1 = (uint32_t)(y * a.nx + wrap(x - dxr, a.nx)) * kSl + l;
+    const uint32_t nx2 = (uint32_t)(y * a.nx + wrap(x - 2 * dxr, a.nx)) * kSl + l;
+    const uint32_t ny1 = (uint32_t)(wrap(y - dyr, a.ny) * a.nx + x) * kSl + l;
+    const uint32_t ny2 = (uint32_t)(wrap(y - 2 * dyr, a.ny) * a.nx + x) * kSl + l;
+    // (3 F_i - 4 F_{i-1} + F_{i-2}) |cos phi|/(2 dx) + the same along y, times
+    // tau_s (the stage works with R0' = tau_s R0, see below)
+    const R ax = (R)(fabs((double)cl) * a.inv2dx * a.tau_s), ay = (R)(fabs((double)sl) * a.inv2dx * a.tau_s);
+    const R c0 = (R)3 * (ax + ay), c1 = (R)(-4) * ax, c2 = (R)(-4) * ay;
+    constexpr int V = NL::V;
+#pragma unroll
+    for (int g = 0; g <= NL::NG; ++g) {
+      R h1[V], h2[V], h3[V], h4[V];
+      const int nq = g < NL::NG ? V : 1;  // the last group is node 24 alone
+      if (g < NL::NG) {
+        ld_vec<R>(rin, nx1 * 16u, g * gb, h1);
+        ld_vec<R>(rin, nx2 * 16u, g * gb, h2);
+        ld_vec<R>(rin, ny1 * 16u, g * gb, h3);
+        ld_vec<R>(rin, ny2 * 16u, g * gb, h4);
+      } else {
+        constexpr uint32_t es = (uint32_t)sizeof(R);
+        h1[0] = Buf<R>::ld(rin, nx1 * es, g * gb);
+        h2[0] = Buf<R>::ld(rin, nx2 * es, g * gb);
+        h3[0] = Buf<R>::ld(rin, ny1 * es, g * gb);
+        h4[0] = Buf<R>::ld(rin, ny2 * es, g * gb);
+      }
+#pragma unroll
+      for (int c = 0; c < nq; ++c) {
+        const int q = g * V + c;
+        const int j = q % NTH;
+        const int i = (q / NTH) * 3 + (j < 3 ? j : 4 - j);
+        const R tr = c0 * f[q] + c1 * h1[c] + ax * h2[c] + c2 * h3[c] + ay * h4[c];
+        R0[q] = -C->sigi[i] * tr;  // -(|v_perp|/gamma) along (cos, sin)
+      }
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+
+  // site record of the input state; ln M at the four neighbours
+  const uint32_t ns = (uint32_t)a.n_sites;
+  const SiteRecord<R> rec = load_record<R>(buf_rsrc(scin, ns * SiteRecord<R>::kBytes), site);
+  const double beta = rec.beta, lnM = rec.lnM;
+  const R ut = rec.v[kScUt], ux = rec.v[kScUx], uy = rec.v[kScUy], Mr = rec.v[kScM];
+  const R Meq = rec.v[kScMeq], rr = rec.v[kScRate], MinvT = rec.v[kScMinvT], l2invT = rec.v[kScL2invT];
+  const __amdgpu_buffer_rsrc_t rl = buf_rsrc(lnMin, ns * 8u);
+  const double lnMxp = Buf<double>::ld(rl, (uint32_t)(y * a.nx + wrap(x + 1, a.nx)) * 8u, 0);
+  const double lnMxm = Buf<double>::ld(rl, (uint32_t)(y * a.nx + wrap(x - 1, a.nx)) * 8u, 0);
+  const double lnMyp = Buf<double>::ld(rl, (uint32_t)(wrap(y + 1, a.ny) * a.nx + x) * 8u, 0);
+  const double lnMym = Buf<double>::ld(rl, (uint32_t)(wrap(y - 1, a.ny) * a.nx + x) * 8u, 0);
 #pragma unroll
   for (int k = 0; k < NXI; ++k) {
 #pragma unroll
@@ -440,38 +604,14 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, (MinWaves<R, STAGE>::v)
         sa += C->A1[k * NXI + kp] * f[kp * NTH + pr];
         sb += C->A1[k * NXI + kp] * f[kp * NTH + 4 - pr];
       }
-      R0[k * NTH + pr] = C->mu2[pr] * sa + (ev + od);
-      R0[k * NTH + 4 - pr] = C->mu2[pr] * sb + (ev - od);
+      R0[k * NTH + pr] += C->mu2[pr] * sa + (ev + od);
+      R0[k * NTH + 4 - pr] += C->mu2[pr] * sb + (ev - od);
     }
-    R0[k * NTH + 2] = C->Mid[0] * e0 + C->Mid[1] * e1 + C->Mid[2] * c2;  // mu = 0: no radial part
+    R0[k * NTH + 2] += C->Mid[0] * e0 + C->Mid[1] * e1 + C->Mid[2] * c2;  // mu = 0: no radial part
   }
-  {
-    // second-order upwind along +(cos phi, sin phi): x-1, x-2 etc., periodic
-    const int dxr = (cl > (R)0) ? 1 : ((cl < (R)0) ? -1 : 0);
-    const int dyr = (sl > (R)0) ? 1 : ((sl < (R)0) ? -1 : 0);
-    constexpr uint32_t es = (uint32_t)sizeof(R);
-    const uint32_t sx1 = ((uint32_t)(y * a.nx + wrap(x - dxr, a.nx)) * kSl + l) * es;
-    const uint32_t sx2 = ((uint32_t)(y * a.nx + wrap(x - 2 * dxr, a.nx)) * kSl + l) * es;
-    const uint32_t sy1 = ((uint32_t)(wrap(y - dyr, a.ny) * a.nx + x) * kSl + l) * es;
-    const uint32_t sy2 = ((uint32_t)(wrap(y - 2 * dyr, a.ny) * a.nx + x) * kSl + l) * es;
-    // (3 F_i - 4 F_{i-1} + F_{i-2}) |cos phi|/(2 dx) + the same along y, times
-    // tau_s (the stage works with R0' = tau_s R0, see below)
-    const R ax = (R)(fabs((double)cl) * a.inv2dx * a.tau_s), ay = (R)(fabs((double)sl) * a.inv2dx * a.tau_s);
-    const R c0 = (R)3 * (ax + ay), c1 = (R)(-4) * ax, c2 = (R)(-4) * ay;
-#pragma unroll
-    for (int k = 0; k < NXI; ++k) {
-#pragma unroll
-      for (int j = 0; j < NTH; ++j) {
-        const int q = k * NTH + j;
-        const int i = k * 3 + (j < 3 ? j : 4 - j);
-        const __amdgpu_buffer_rsrc_t rq = plane_rsrc(Fin + (size_t)q * plane, pbytes);
-        const R fx1 = Buf<R>::ld(rq, sx1), fx2 = Buf<R>::ld(rq, sx2);
-        const R fy1 = Buf<R>::ld(rq, sy1), fy2 = Buf<R>::ld(rq, sy2);
-        const R tr = c0 * f[q] + c1 * fx1 + ax * fx2 + c2 * fy1 + ay * fy2;
-        R0[q] -= C->sigi[i] * tr;  // -(|v_perp|/gamma) along (cos, sin)
-      }
-    }
-  }
+  // centred gradient of ln M
+  const R gx = (R)((lnMxp - lnMxm) * a.inv2dx);
+  const R gy = (R)((lnMyp - lnMym) * a.inv2dx);
 
   // ---- 2: equilibrium, BGK, mass-gradient force, sums, update ----
   const R cu = ux * cl + uy * sl;            // u_perp . (cos phi, sin phi)
@@ -547,16 +687,14 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, (MinWaves<R, STAGE>::v)
     lnM_new = lnM + a.dtau * X;
   } else {
     const R hdt = (R)(0.5 * a.dtau * a.inv_tau_s);
+    R fb[Q];
+    load_slice<R>(buf_rsrc(Fbase, fbytes), lane, gb, fb);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const R fb = Buf<R>::ld(plane_rsrc(Fbase + (size_t)q * plane, pbytes), me);
-      f[q] = (R)0.5 * (fb + f[q]) + hdt * (R0[q] + Xr * S2[q]);
-    }
+    for (int q = 0; q < Q; ++q) f[q] = (R)0.5 * (fb[q] + f[q]) + hdt * (R0[q] + Xr * S2[q]);
     lnM_new = 0.5 * (lnMbase[site] + lnM) + 0.5 * a.dtau * X;
   }
   if (valid) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) Buf<R>::st(plane_rsrc(Fout + (size_t)q * plane, pbytes), me, f[q]);
+    store_slice<R>(buf_rsrc(Fout, fbytes), lane, gb, f);
     if (l == 0) lnMout[site] = lnM_new;
   }
 
@@ -583,12 +721,9 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl) void site_kernel(
   const int x0 = bx * kTX + (ts % kTX), y0 = by * kTY + (ts / kTX);
   const bool valid = (x0 < a.nx) && (y0 < a.ny);
   const int site = valid ? y0 * a.nx + x0 : 0;
-  const uint32_t plane = (uint32_t)a.n_sites * kSl;
-  const uint32_t pbytes = plane * (uint32_t)sizeof(R);
-  const uint32_t me = ((uint32_t)site * kSl + l) * (uint32_t)sizeof(R);
   R f[25];
-#pragma unroll
-  for (int q = 0; q < 25; ++q) f[q] = Buf<R>::ld(plane_rsrc(F + (size_t)q * plane, pbytes), me);
+  load_slice<R>(buf_rsrc(F, (uint32_t)a.n_sites * kSl * 25u * (uint32_t)sizeof(R)), (uint32_t)site * kSl + l,
+                NodeLayout<R>::gbytes(a.n_sites), f);
   match_tile<R, kTY>(f, C, lnMv[site], t, bx, by, tb, a, sc, err, s_mom);
 }
 
@@ -621,13 +756,11 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const double* __restrict__
   const double M = eos_field(tb, i, w, kZ) * T0;
   const double ut = sqrt(1.0 + vx * vx + vy * vy);
   const double cu = vx * (double)C.cosl[l] + vy * (double)C.sinl[l];
-  const size_t plane = (size_t)a.n_sites * kSl;
-  const size_t me = (size_t)site * kSl + l;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int k = q / NTH;
     const double uP = M * (ut * (double)C.x[k] - cu * (double)C.sig[q]);
-    F[q * plane + me] = (R)(a.Z * exp(-uP / T0));
+    F[NodeLayout<R>::offset(q, site, l, a.n_sites) / sizeof(R)] = (R)(a.Z * exp(-uP / T0));
   }
   if (l == 0) {
     lnM[site] = log(M);
@@ -649,12 +782,10 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const R* __restrict__ F
   const int site = tid >> 3;
   const int l = tid & 7;
   if (site >= a.n_sites) return;
-  const size_t plane = (size_t)a.n_sites * kSl;
-  const size_t me = (size_t)site * kSl + l;
   double p0 = 0, p1 = 0, p2 = 0, p3 = 0, p4 = 0, p5 = 0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const double fq = (double)F[q * plane + me];
+    const double fq = (double)F[NodeLayout<R>::offset(q, site, l, a.n_sites) / sizeof(R)];
     p0 += (double)C.wx2[q] * fq;
     p1 += (double)C.wxs[q] * fq;
     p2 += (double)C.ws2[q] * fq;
@@ -707,12 +838,12 @@ __global__ void get_state_kernel(const R* __restrict__ F, double* __restrict__ F
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)n_q * n_sites * kSl;
   if (i >= total) return;
-  // internal index i = (q * n_sites + site) * 8 + l
+  // thread i = (q * n_sites + site) * 8 + l
   const int l = (int)(i % kSl);
   const size_t rest = i / kSl;
   const int site = (int)(rest % n_sites);
   const int q = (int)(rest / n_sites);
-  Fc[((size_t)q * kSl + l) * n_sites + site] = (double)F[i];
+  Fc[((size_t)q * kSl + l) * n_sites + site] = (double)F[NodeLayout<R>::offset(q, site, l, n_sites) / sizeof(R)];
 }
 
 template <typename R>
@@ -724,7 +855,7 @@ __global__ void set_state_kernel(const double* __restrict__ Fc, R* __restrict__ 
   const size_t rest = i / kSl;
   const int site = (int)(rest % n_sites);
   const int q = (int)(rest / n_sites);
-  F[i] = (R)Fc[((size_t)q * kSl + l) * n_sites + site];
+  F[NodeLayout<R>::offset(q, site, l, n_sites) / sizeof(R)] = (R)Fc[((size_t)q * kSl + l) * n_sites + site];
 }
 
 // ---------------------------------------------------------------------------
