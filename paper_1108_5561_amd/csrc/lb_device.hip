@@ -570,7 +570,9 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, (MinWaves<R, STAGE>::v)
       }
     }
   }
-  __builtin_amdgcn_sched_barrier(0);
+  // FP32: the streaming loads may overlap the operator arithmetic below;
+  // FP64 (twice the registers per value) schedules better without
+  if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
 
   // site record of the input state; ln M at the four neighbours
   const uint32_t ns = (uint32_t)a.n_sites;
