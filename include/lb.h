@@ -210,6 +210,14 @@ int lb_eos_eval(const lb_params* p, int64_t n, const double* T_GeV, double* out,
 int lb_profile(lb_ctx* c, int32_t enable);
 int lb_profile_read(lb_ctx* c, double* ms_out, int64_t* count_out);
 
+/* Mean duration in milliseconds of one launch of the predictor (stage 0) or
+ * corrector (stage 1) kernel, from HIP events around n >= 1 back-to-back
+ * launches on the context's stream (after one untimed predictor).  The
+ * launches read the current state and write only the two spare state
+ * buffers, so the state, the time and the next lb_step are unchanged.
+ * Synchronises the stream; returns the device error word like lb_status. */
+int lb_profile_stage(lb_ctx* c, int32_t stage, int32_t n, double dtau_fm, double* ms_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,7 +4,7 @@ quasiparticle lattice-Boltzmann step (see include/lb.h for the contract).
 Argument marshalling only: every step of the method runs in the library's HIP
 kernels.  PyTorch provides device memory and the stream.  Importing this
 module fails loudly if the library has not been built
-(``python -m paper_1108_5561_amd.build``).
+(``python paper_1108_5561_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -51,7 +51,7 @@ class lb_params(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1108_5561_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1108_5561_amd/build.py`")
     # torch bundles its own HIP runtime under the same soname
     # (libamdhip64.so.7).  Loading torch first makes the dynamic loader bind
     # the library to that copy, so one HIP runtime serves the process and
@@ -75,6 +75,7 @@ def _load():
         "lb_eos_eval": (ctypes.c_int, [P, i64, dp, dp, i32]),
         "lb_profile": (ctypes.c_int, [vp, i32]),
         "lb_profile_read": (ctypes.c_int, [vp, dp, ctypes.POINTER(i64)]),
+        "lb_profile_stage": (ctypes.c_int, [vp, i32, i32, ctypes.c_double, dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -226,6 +227,13 @@ class Context:
         cnt = (ctypes.c_int64 * 2)()
         check(lib.lb_profile_read(self._ctx, ms, cnt))
         return (ms[0], ms[1]), (cnt[0], cnt[1])
+
+    def profile_stage(self, stage, n, dtau_fm):
+        """Mean milliseconds of one predictor (0) or corrector (1) launch over
+        n back-to-back launches; the state is left unchanged."""
+        ms = ctypes.c_double()
+        check(lib.lb_profile_stage(self._ctx, int(stage), int(n), float(dtau_fm), ctypes.byref(ms)))
+        return ms.value
 
     def adjoint_step(self, *args):
         return lib.lb_adjoint_step(self._ctx, 0, None, None, None, None)

@@ -1,6 +1,7 @@
 """Build the C-ABI shared library liblbmi.so for gfx950 with hipcc, in-tree.
 
-Usage: python -m paper_1108_5561_amd.build   (or call build()).
+Usage: python paper_1108_5561_amd/build.py   (or call build()); run as a
+script, not as a module of the package, whose import loads the library.
 """
 import os
 import subprocess

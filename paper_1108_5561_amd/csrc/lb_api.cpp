@@ -520,6 +520,41 @@ int lb_profile_read(lb_ctx* c, double* ms_out, int64_t* count_out) {
   return LB_OK;
 }
 
+int lb_profile_stage(lb_ctx* c, int32_t stage, int32_t n, double dtau_fm, double* ms_out) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  if ((stage != 0 && stage != 1) || n < 1 || !ms_out) return fail(LB_E_ARG, "need stage 0 or 1, n >= 1, ms_out");
+  if (!(dtau_fm > 0) || !std::isfinite(dtau_fm)) return fail(LB_E_ARG, "dtau must be finite and > 0");
+  const int prec = c->p.precision;
+  const int i0 = c->cur, i1 = (c->cur + 1) % 3, i2 = (c->cur + 2) % 3;
+  StageArgs a = stage_args(c, c->tau, dtau_fm);
+  // the corrector needs a predictor output to read: one untimed predictor
+  hipError_t e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], c->sc[i0],
+                              c->sc[i1], c->cst, c->tb, a, c->err, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "predictor launch");
+  if (stage == 1) set_tau(&a, c, c->tau + dtau_fm);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& x : ev)
+    if ((e = hipEventCreate(&x)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  hipEventRecord(ev[0], c->stream);
+  for (int k = 0; k < n && e == hipSuccess; ++k) {
+    if (stage == 0)
+      e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], c->sc[i0], c->sc[i1],
+                       c->cst, c->tb, a, c->err, c->stream);
+    else
+      e = launch_stage(prec, 1, c->F[i1], c->F[i0], c->F[i2], c->lnM[i1], c->lnM[i0], c->lnM[i2], c->sc[i1],
+                       c->sc[i2], c->cst, c->tb, a, c->err, c->stream);
+  }
+  hipEventRecord(ev[1], c->stream);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return hip_fail(e, "stage timing");
+  *ms_out = (double)ms / n;
+  return read_err(c);
+}
+
 int64_t lb_lattice_info(const lb_params* p, double* out, int64_t n_out) {
   if (!p) return fail(LB_E_ARG, "params is NULL");
   if (p->n_xi < 1 || p->n_theta < 1 || p->n_phi < 1 || !(p->z0 > 0))

@@ -221,6 +221,29 @@ def test_deterministic(eos):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("precision", [lb.LB_FP64, lb.LB_FP32_FP64MATCH])
+def test_profile_stage_leaves_state(eos, precision):
+    """Timing launches of one stage write only the spare buffers: the state,
+    the time and the following step are as without them."""
+    e0 = gaussian_e0(eos, 24, 16, 0.2)
+    a = make_ctx(24, 16, 0.2, e0, precision=precision)
+    b = make_ctx(24, 16, 0.2, e0, precision=precision)
+    a.step(3, 0.01)
+    b.step(3, 0.01)
+    F0, l0, t0 = b.get_state()
+    for stage in (0, 1):
+        ms = b.profile_stage(stage, 5, 0.01)
+        assert ms > 0
+    F1, l1, t1 = b.get_state()
+    assert t1 == t0 and torch.equal(F0, F1) and torch.equal(l0, l1)
+    a.step(2, 0.01)
+    b.step(2, 0.01)
+    Fa, la, _ = a.get_state()
+    Fb, lb_, _ = b.get_state()
+    assert torch.equal(Fa, Fb) and torch.equal(la, lb_)
+    assert b.status() == lb.LB_OK
+
+
 def test_error_paths(eos):
     e0 = gaussian_e0(eos, 8, 8, 0.2)
     bad = e0.copy()
