@@ -218,6 +218,68 @@ int lb_profile_read(lb_ctx* c, double* ms_out, int64_t* count_out);
  * Synchronises the stream; returns the device error word like lb_status. */
 int lb_profile_stage(lb_ctx* c, int32_t stage, int32_t n, double dtau_fm, double* ms_out);
 
+/* ---- batched form: many events advanced together ----
+ *
+ * A batch advances n_events independent events (boost-invariant initial
+ * conditions, e.g. fluctuating ones, on their own periodic transverse grids)
+ * of one species, lattice and EoS, with one kernel launch per Heun stage
+ * covering the tiles of all events; the library keeps one context-wide
+ * state per event exactly as lb_step would (an event's result does not
+ * depend on the batch it is in).  Runs of 48 steps that start at the first
+ * buffer rotation are replayed from a captured HIP graph; the tile shape and
+ * occupancy of the batched kernel are chosen by timing the candidates on the
+ * batch itself (lb_batch_tune, or automatically at the first lb_batch_step).
+ */
+typedef struct lb_batch lb_batch; /* opaque, host memory owned by the library */
+
+typedef struct lb_event {
+  int32_t nx, ny;      /* periodic transverse lattice of the event, >= 1 each */
+  double dx_fm;        /* its spacing (> 0) */
+  double eta_over_s;   /* its eta/s (> 0, +INFINITY for free streaming) */
+} lb_event;
+
+/* Workspace bytes for the batch (0 on invalid input; message in
+ * lb_last_error).  p gives everything but the per-event grid, spacing and
+ * eta/s, whose fields in p are ignored. */
+size_t lb_batch_workspace_bytes(const lb_params* p, const lb_event* events, int32_t n_events);
+
+/* Create a batch: as lb_init for every event, with zero initial flow.
+ * d_e0 is a host array of n_events device pointers, each [ny][nx] FP64
+ * energy density in GeV/fm^3 of that event (read during the call).  The
+ * library allocates 2 x 48 stage-time records of pinned host memory
+ * (hipHostMalloc) for the graph replays; device memory is the caller's
+ * workspace only.  Errors as lb_init. */
+int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, int32_t n_events,
+                  void* d_workspace, size_t ws_bytes, const double* const* d_e0, void* hip_stream);
+
+/* Time every variant of the batched stage kernel (tile rows 2, 4, 8; in
+ * FP32 with 4 or 3 waves per SIMD as occupancy target) on the batch's own
+ * events for a few steps of size dtau_fm, on the spare state buffers (the
+ * state is unchanged), and keep the fastest.  variant_out (may be NULL)
+ * receives its index; ms_out (may be NULL) the mean milliseconds per step
+ * of each variant ([6] in FP32, [3] in FP64).  Synchronous. */
+int lb_batch_tune(lb_batch* b, double dtau_fm, int32_t* variant_out, double* ms_out);
+
+/* Use kernel variant `variant` (0..5 in FP32, 0..2 in FP64, numbered as in
+ * lb_batch_tune) without timing: pins a tuned choice. */
+int lb_batch_set_variant(lb_batch* b, int32_t variant);
+
+/* Advance every event n_steps Heun steps of dtau_fm (as lb_step; LB_E_ARG
+ * if the CFL limit is exceeded in any event).  Tunes first if not tuned. */
+int lb_batch_step(lb_batch* b, int32_t n_steps, double dtau_fm);
+
+/* Observables of one event into d_out [14][ny][nx] (as lb_moments). */
+int lb_batch_moments(lb_batch* b, int32_t event, double* d_out);
+
+/* State of one event in canonical order (as lb_get_state). */
+int lb_batch_get_state(lb_batch* b, int32_t event, double* d_F, double* d_lnM, double* tau_fm);
+
+/* Synchronise and return the sticky device error of the batch. */
+int lb_batch_status(lb_batch* b);
+
+/* Release the batch (the workspace stays the caller's). */
+int lb_batch_destroy(lb_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

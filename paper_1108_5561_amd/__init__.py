@@ -49,6 +49,12 @@ class lb_params(ctypes.Structure):
     ]
 
 
+class lb_event(ctypes.Structure):
+    """One event of a batch (include/lb.h)."""
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx_fm", ctypes.c_double),
+                ("eta_over_s", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1108_5561_amd/build.py`")
@@ -76,6 +82,16 @@ def _load():
         "lb_profile": (ctypes.c_int, [vp, i32]),
         "lb_profile_read": (ctypes.c_int, [vp, dp, ctypes.POINTER(i64)]),
         "lb_profile_stage": (ctypes.c_int, [vp, i32, i32, ctypes.c_double, dp]),
+        "lb_batch_workspace_bytes": (sz, [P, ctypes.POINTER(lb_event), i32]),
+        "lb_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), P, ctypes.POINTER(lb_event), i32, vp, sz,
+                                         ctypes.POINTER(vp), vp]),
+        "lb_batch_tune": (ctypes.c_int, [vp, ctypes.c_double, ctypes.POINTER(i32), dp]),
+        "lb_batch_step": (ctypes.c_int, [vp, i32, ctypes.c_double]),
+        "lb_batch_set_variant": (ctypes.c_int, [vp, i32]),
+        "lb_batch_moments": (ctypes.c_int, [vp, i32, vp]),
+        "lb_batch_get_state": (ctypes.c_int, [vp, i32, vp, vp, dp]),
+        "lb_batch_status": (ctypes.c_int, [vp]),
+        "lb_batch_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -242,6 +258,86 @@ class Context:
         if self._ctx:
             lib.lb_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many events advanced together (lb_batch_init .. lb_batch_destroy):
+    events is a list of (nx, ny, dx_fm, eta_over_s), e0s the matching list
+    of contiguous float64 [ny, nx] GPU tensors; params gives the shared
+    lattice, EoS, precision, metric and tau0."""
+
+    def __init__(self, params, events, e0s):
+        import torch
+        self.torch = torch
+        self.params = params
+        if len(events) != len(e0s) or not events:
+            raise LbError(LB_E_ARG, "need one e0 per event")
+        dev = e0s[0].device
+        for (nx, ny, _, _), t in zip(events, e0s):
+            if t.dtype != torch.float64 or tuple(t.shape) != (ny, nx) or not t.is_contiguous() or t.device != dev:
+                raise LbError(LB_E_ARG, "each e0 must be a contiguous float64 [ny, nx] GPU tensor")
+        self.device = dev
+        self.events = [tuple(e) for e in events]
+        n = len(events)
+        self._ev = (lb_event * n)(*[lb_event(int(a), int(b), float(c), float(d)) for a, b, c, d in events])
+        nbytes = lib.lb_batch_workspace_bytes(ctypes.byref(params), self._ev, n)
+        if nbytes == 0:
+            raise LbError(LB_E_ARG, last_error())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in e0s])
+        self._b = ctypes.c_void_p()
+        check(lib.lb_batch_init(ctypes.byref(self._b), ctypes.byref(params), self._ev, n, self.workspace.data_ptr(),
+                                nbytes, ptrs, self.stream.cuda_stream))
+        self.N = params.n_xi * params.n_theta * 2 * params.n_phi
+
+    def tune(self, dtau_fm):
+        """Time the kernel variants, keep the fastest; returns (variant, ms per step of each)."""
+        nv = 6 if self.params.precision == LB_FP32_FP64MATCH else 3
+        ms = (ctypes.c_double * nv)()
+        v = ctypes.c_int32()
+        check(lib.lb_batch_tune(self._b, float(dtau_fm), ctypes.byref(v), ms))
+        return v.value, list(ms)
+
+    def set_variant(self, variant):
+        check(lib.lb_batch_set_variant(self._b, int(variant)))
+
+    def step(self, n_steps, dtau_fm):
+        check(lib.lb_batch_step(self._b, int(n_steps), float(dtau_fm)))
+
+    def _grid(self, event):
+        if not 0 <= int(event) < len(self.events):
+            raise LbError(LB_E_ARG, f"no event {event} in a batch of {len(self.events)}")
+        return self.events[int(event)][:2]
+
+    def moments(self, event):
+        nx, ny = self._grid(event)
+        out = self.torch.empty((N_OBS, ny, nx), dtype=self.torch.float64, device=self.device)
+        check(lib.lb_batch_moments(self._b, int(event), out.data_ptr()))
+        return out
+
+    def get_state(self, event):
+        nx, ny = self._grid(event)
+        torch = self.torch
+        F = torch.empty((self.N, ny, nx), dtype=torch.float64, device=self.device)
+        lnM = torch.empty((ny, nx), dtype=torch.float64, device=self.device)
+        tau = ctypes.c_double()
+        check(lib.lb_batch_get_state(self._b, int(event), F.data_ptr(), lnM.data_ptr(), ctypes.byref(tau)))
+        return F, lnM, tau.value
+
+    def status(self):
+        return lib.lb_batch_status(self._b)
+
+    def close(self):
+        if self._b:
+            lib.lb_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

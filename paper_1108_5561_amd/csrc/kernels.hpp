@@ -32,17 +32,49 @@ struct StageArgs {
 
 // One Heun stage.  stage 0: F* = F + dtau K(F); stage 1:
 // F_new = (F + F*)/2 + dtau/2 K(F*).  precision 0 = FP64, 1 = FP32;
-// scin / scout are the site scalars of the input and output states;
+// scin / scout are the site records of the input and output states; d_tb
+// is the device copy of the EoS table descriptor;
 // stageconst is a device pointer to the context's StageConst<double> or
 // StageConst<float>.
 hipError_t launch_stage(int precision, int stage, const void* Fin, const void* Fbase, void* Fout,
                         const double* lnMin, const double* lnMbase, double* lnMout, const double* scin,
-                        double* scout, const void* stageconst, const EosTable& tb, const StageArgs& a,
+                        double* scout, const void* stageconst, const EosTable* d_tb, const StageArgs& a,
                         int* err, hipStream_t s);
+
+// ---- batched form: many events (own grid, spacing, eta/s, state) advanced
+// by one launch per stage ----
+struct BatchEvent {
+  int32_t nx, ny, n_sites, tile0;  // tile0: first tile of the event in the launch
+  double inv2dx, inv_eta_hbarc;
+  void* F[3];
+  double* lnM[3];
+  double* sc[3];
+};
+// Time of one stage: tau, and tau_s / 1/tau_s of StageArgs.
+struct StageTime {
+  double tau, tau_s, inv_tau_s;
+};
+// Variants of the batched stage kernel (the tuning choices): variant v has
+// kBatchTileRows[v % 3] tile rows (tiles are 8 sites wide) and, in FP32,
+// 4 (v < 3) or 3 (v >= 3) waves per SIMD as occupancy target; FP64 has
+// variants 0..2 at 2 waves per SIMD.
+constexpr int kBatchTileRows[3] = {2, 4, 8};
+inline int batch_variants(int precision) { return precision == 1 ? 6 : 3; }
+inline int batch_tile_rows(int variant) { return kBatchTileRows[variant % 3]; }
+inline int batch_tiles(int nx, int ny, int tile_rows) { return ((nx + 7) / 8) * ((ny + tile_rows - 1) / tile_rows); }
+
+// One stage of every event.  ev [n_events], tile_event [n_tiles] (event of
+// each tile, in the launch's tile numbering); the stage time is `time` or,
+// if times != NULL, times[time_idx] (read by the kernel: graph replays
+// refresh it); buffers i_in, i_base, i_out of each event.
+hipError_t launch_batch_stage(int precision, int stage, int variant, const BatchEvent* ev,
+                              const int32_t* tile_event, int n_tiles, StageTime time, const StageTime* times,
+                              int time_idx, int i_in, int i_base, int i_out, const void* stageconst,
+                              const EosTable* d_tb, const StageArgs& shared, int* err, hipStream_t s);
 
 // Site scalars of the state (F, lnM) into scout.
 hipError_t launch_site(int precision, const void* F, const double* lnM, double* scout, const void* stageconst,
-                       const EosTable& tb, const StageArgs& a, int* err, hipStream_t s);
+                       const EosTable* d_tb, const StageArgs& a, int* err, hipStream_t s);
 
 hipError_t launch_init(int precision, const double* e0, const double* ux0, const double* uy0, void* F,
                        double* lnM, const void* latconst, const EosTable& tb, const StageArgs& a,

@@ -2,6 +2,7 @@
 // carving, host setup upload, kernel launches (declarations in include/lb.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -23,6 +24,7 @@ struct lb_ctx {
   double* lnM[3] = {nullptr, nullptr, nullptr};
   double* sc[3] = {nullptr, nullptr, nullptr};  // site scalars of each state
   void* cst = nullptr;                          // device copy of the stage constants
+  EosTable* tbd = nullptr;                      // device copy of the EoS table descriptor
   int cur = 0;  // index of the current state
   int* err = nullptr;
   EosTable tb{};
@@ -52,7 +54,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t F[3], lnM[3], sc[3], cst, pts, inv_ek, inv_ee, err, total;
+  size_t F[3], lnM[3], sc[3], cst, tbd, pts, inv_ek, inv_ee, err, total;
 };
 
 std::string validate(const lb_params* p) {
@@ -111,6 +113,8 @@ Layout layout(const lb_params* p) {
   }
   L.cst = off;
   off = align_up(off + sizeof(StageConst<double>));
+  L.tbd = off;
+  off = align_up(off + sizeof(EosTable));
   L.pts = off;
   off = align_up(off + (size_t)kTablePoints * kFields * 8);
   L.inv_ek = off;
@@ -229,7 +233,7 @@ StageArgs stage_args(const lb_ctx* c, double tau, double dtau);
 hipError_t prime_site_scalars(lb_ctx* c) {
   const StageArgs a = stage_args(c, c->tau, 0.0);
   const int cur = c->cur;
-  return launch_site(c->p.precision, c->F[cur], c->lnM[cur], c->sc[cur], c->cst, c->tb, a, c->err, c->stream);
+  return launch_site(c->p.precision, c->F[cur], c->lnM[cur], c->sc[cur], c->cst, c->tbd, a, c->err, c->stream);
 }
 
 // Time of a stage; tau_s = tau multiplies the S1-free terms of a Milne stage.
@@ -239,21 +243,25 @@ void set_tau(StageArgs* a, const lb_ctx* c, double tau) {
   a->inv_tau_s = 1.0 / a->tau_s;
 }
 
-StageArgs stage_args(const lb_ctx* c, double tau, double dtau) {
+StageArgs params_args(const lb_params& p, double tau, double dtau) {
   StageArgs a;
-  a.nx = c->p.nx;
-  a.ny = c->p.ny;
-  a.n_sites = c->p.nx * c->p.ny;
-  a.metric = c->p.metric;
-  a.inv2dx = 0.5 / c->p.dx_fm;
-  a.inv_dx = 1.0 / c->p.dx_fm;
+  a.nx = p.nx;
+  a.ny = p.ny;
+  a.n_sites = p.nx * p.ny;
+  a.metric = p.metric;
+  a.inv2dx = 0.5 / p.dx_fm;
+  a.inv_dx = 1.0 / p.dx_fm;
   a.dtau = dtau;
-  set_tau(&a, c, tau);
-  a.inv_eta_hbarc = std::isinf(c->p.eta_over_s) ? 0.0 : 1.0 / (c->p.eta_over_s * kHbarC);
-  a.Z = c->p.Z;
-  a.log2Z = std::log2(c->p.Z);
+  a.tau = tau;
+  a.tau_s = p.metric == LB_METRIC_MILNE ? tau : 1.0;
+  a.inv_tau_s = 1.0 / a.tau_s;
+  a.inv_eta_hbarc = std::isinf(p.eta_over_s) ? 0.0 : 1.0 / (p.eta_over_s * kHbarC);
+  a.Z = p.Z;
+  a.log2Z = std::log2(p.Z);
   return a;
 }
+
+StageArgs stage_args(const lb_ctx* c, double tau, double dtau) { return params_args(c->p, tau, dtau); }
 
 const void* lat_const(const lb_ctx* c) {
   return c->p.precision == LB_FP64 ? (const void*)&c->cd : (const void*)&c->cf;
@@ -263,17 +271,19 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(LB_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int read_err(lb_ctx* c) {
+int read_err_word(int* d_err, hipStream_t stream) {
   int h = 0;
-  hipError_t e = hipMemcpyAsync(&h, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(error word)");
-  e = hipStreamSynchronize(c->stream);
+  e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   if (h & kErrNonfinite) return fail(LB_E_NONFINITE, "device: non-finite value in the state or input");
   if (h & kErrMatch) return fail(LB_E_MATCH, "device: Landau matching found no timelike eigenvector");
   if (h & kErrEos) return fail(LB_E_EOS, "device: temperature or energy density outside the EoS table");
   return LB_OK;
 }
+
+int read_err(lb_ctx* c) { return read_err_word(c->err, c->stream); }
 
 }  // namespace
 
@@ -328,6 +338,7 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
     c->sc[i] = (double*)(c->ws + L.sc[i]);
   }
   c->cst = c->ws + L.cst;
+  c->tbd = (EosTable*)(c->ws + L.tbd);
   double* d_pts = (double*)(c->ws + L.pts);
   double* d_iek = (double*)(c->ws + L.inv_ek);
   double* d_iee = (double*)(c->ws + L.inv_ee);
@@ -342,6 +353,7 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
   if ((e = hipMemcpy(d_pts, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_iek, T.inv_ek.data(), T.inv_ek.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_iee, T.inv_ee.data(), T.inv_ee.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->tbd, &c->tb, sizeof(EosTable), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemsetAsync(c->err, 0, sizeof(int), c->stream)) != hipSuccess) {
     delete c;
     return hip_fail(e, "upload of EoS tables");
@@ -410,13 +422,12 @@ int lb_step(lb_ctx* c, int32_t n_steps, double dtau) {
     }
     StageArgs a = stage_args(c, c->tau, dtau);
     hipError_t e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], c->sc[i0],
-                                c->sc[i1], c->cst,
-                                c->tb, a, c->err, c->stream);
+                                c->sc[i1], c->cst, c->tbd, a, c->err, c->stream);
     if (e != hipSuccess) return hip_fail(e, "predictor launch");
     if (c->prof) hipEventRecord(e1, c->stream);
     set_tau(&a, c, c->tau + dtau);
     e = launch_stage(prec, 1, c->F[i1], c->F[i0], c->F[i2], c->lnM[i1], c->lnM[i0], c->lnM[i2], c->sc[i1],
-                     c->sc[i2], c->cst, c->tb, a,
+                     c->sc[i2], c->cst, c->tbd, a,
                      c->err, c->stream);
     if (e != hipSuccess) return hip_fail(e, "corrector launch");
     if (c->prof) hipEventRecord(e2, c->stream);
@@ -529,7 +540,7 @@ int lb_profile_stage(lb_ctx* c, int32_t stage, int32_t n, double dtau_fm, double
   StageArgs a = stage_args(c, c->tau, dtau_fm);
   // the corrector needs a predictor output to read: one untimed predictor
   hipError_t e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], c->sc[i0],
-                              c->sc[i1], c->cst, c->tb, a, c->err, c->stream);
+                              c->sc[i1], c->cst, c->tbd, a, c->err, c->stream);
   if (e != hipSuccess) return hip_fail(e, "predictor launch");
   if (stage == 1) set_tau(&a, c, c->tau + dtau_fm);
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -539,10 +550,10 @@ int lb_profile_stage(lb_ctx* c, int32_t stage, int32_t n, double dtau_fm, double
   for (int k = 0; k < n && e == hipSuccess; ++k) {
     if (stage == 0)
       e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], c->sc[i0], c->sc[i1],
-                       c->cst, c->tb, a, c->err, c->stream);
+                       c->cst, c->tbd, a, c->err, c->stream);
     else
       e = launch_stage(prec, 1, c->F[i1], c->F[i0], c->F[i2], c->lnM[i1], c->lnM[i0], c->lnM[i2], c->sc[i1],
-                       c->sc[i2], c->cst, c->tb, a, c->err, c->stream);
+                       c->sc[i2], c->cst, c->tbd, a, c->err, c->stream);
   }
   hipEventRecord(ev[1], c->stream);
   float ms = 0;
@@ -611,6 +622,509 @@ int lb_eos_eval(const lb_params* p, int64_t n, const double* T, double* out, int
     o[6] = pt.beta;
     o[7] = tauR;
   }
+  return LB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form: many events advanced together (lb_batch_* in lb.h).
+
+struct lb_batch {
+  lb_params p{};                 // shared parameters (grid fields per event)
+  std::vector<lb_event> events;
+  std::vector<BatchEvent> ev;    // host copy of the device event table
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;     // private stream the graphs are captured on
+  char* ws = nullptr;
+  HostLattice lat;
+  EosTable tb{};                 // with device table pointers
+  EosTable* tbd = nullptr;
+  void* cst = nullptr;
+  LatticeConst<float, 5, 5> cf{};
+  LatticeConst<double, 5, 5> cd{};
+  int* err = nullptr;
+  BatchEvent* d_ev = nullptr;
+  int32_t* d_tile_event = nullptr;
+  StageTime* d_times = nullptr;  // [2][2 kBatchGraphSteps]
+  StageTime* h_times = nullptr;  // pinned host staging of the same
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  double vsum_over_dx = 0;       // max over events of max_n (|v^x|+|v^y|)/gamma / dx
+  double tau = 0;
+  int cur = 0;
+  int variant = -1, n_tiles = 0;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  int graph_variant = -1;
+  double graph_dtau = 0;
+  int slot = 0;
+};
+
+namespace {
+
+constexpr int kBatchGraphSteps = 48;  // steps per captured graph (a multiple of 3)
+
+struct BatchLayout {
+  size_t cst, tbd, pts, inv_ek, inv_ee, err, ev, tile_event, times, total;
+  std::vector<size_t> F, lnM, sc;  // [event * 3 + i]
+};
+
+lb_params event_params(const lb_params& p, const lb_event& e) {
+  lb_params q = p;
+  q.nx = e.nx;
+  q.ny = e.ny;
+  q.dx_fm = e.dx_fm;
+  q.eta_over_s = e.eta_over_s;
+  return q;
+}
+
+std::string validate_batch(const lb_params* p, const lb_event* ev, int32_t n) {
+  if (!p) return "params is NULL";
+  if (!ev || n < 1) return "need at least one event";
+  int64_t tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    const lb_params q = event_params(*p, ev[i]);
+    std::string m = validate(&q);
+    if (!m.empty()) return "event " + std::to_string(i) + ": " + m;
+    tiles += batch_tiles(ev[i].nx, ev[i].ny, kBatchTileRows[0]);
+  }
+  if (tiles >= ((int64_t)1 << 30)) return "too many tiles in the batch";
+  return "";
+}
+
+BatchLayout batch_layout(const lb_params* p, const lb_event* ev, int32_t n) {
+  BatchLayout L;
+  const size_t elt = p->precision == LB_FP64 ? 8 : 4;
+  const size_t nodes = (size_t)p->n_xi * p->n_theta * 2 * p->n_phi;
+  size_t off = 0;
+  L.cst = off;
+  off = align_up(off + sizeof(StageConst<double>));
+  L.tbd = off;
+  off = align_up(off + sizeof(EosTable));
+  L.pts = off;
+  off = align_up(off + (size_t)kTablePoints * kFields * 8);
+  L.inv_ek = off;
+  off = align_up(off + (size_t)kInvPoints * 8);
+  L.inv_ee = off;
+  off = align_up(off + (size_t)kInvPoints * 8);
+  L.err = off;
+  off = align_up(off + 256);
+  L.ev = off;
+  off = align_up(off + (size_t)n * sizeof(BatchEvent));
+  size_t max_tiles = 0;
+  for (int r = 0; r < 3; ++r) {
+    size_t t = 0;
+    for (int i = 0; i < n; ++i) t += (size_t)batch_tiles(ev[i].nx, ev[i].ny, kBatchTileRows[r]);
+    max_tiles = std::max(max_tiles, t);
+  }
+  L.tile_event = off;
+  off = align_up(off + max_tiles * 4);
+  L.times = off;
+  off = align_up(off + 2 * 2 * kBatchGraphSteps * sizeof(StageTime));
+  L.F.resize(3 * n);
+  L.lnM.resize(3 * n);
+  L.sc.resize(3 * n);
+  for (int i = 0; i < n; ++i) {
+    const size_t sites = (size_t)ev[i].nx * ev[i].ny;
+    for (int k = 0; k < 3; ++k) {
+      L.F[3 * i + k] = off;
+      off = align_up(off + nodes * sites * elt);
+      L.lnM[3 * i + k] = off;
+      off = align_up(off + sites * 8);
+      L.sc[3 * i + k] = off;
+      off = align_up(off + site_scalar_bytes(sites, elt));
+    }
+  }
+  L.total = off;
+  return L;
+}
+
+// Tile numbering of a kernel variant: event tile offsets and the map from
+// tile to event, uploaded to the device.
+hipError_t set_variant(lb_batch* b, int variant) {
+  const int rows = batch_tile_rows(variant);
+  std::vector<int32_t> te;
+  int t0 = 0;
+  for (size_t i = 0; i < b->ev.size(); ++i) {
+    b->ev[i].tile0 = t0;
+    const int nt = batch_tiles(b->ev[i].nx, b->ev[i].ny, rows);
+    te.insert(te.end(), (size_t)nt, (int32_t)i);
+    t0 += nt;
+  }
+  hipError_t e = hipMemcpyAsync(b->d_ev, b->ev.data(), b->ev.size() * sizeof(BatchEvent), hipMemcpyHostToDevice,
+                                b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_tile_event, te.data(), te.size() * 4, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // te is a local staging vector
+  if (e == hipSuccess) {
+    b->variant = variant;
+    b->n_tiles = t0;
+  }
+  return e;
+}
+
+StageArgs batch_shared_args(const lb_batch* b, double dtau) {
+  StageArgs a = params_args(b->p, b->tau, dtau);  // grid / time fields are set per block
+  return a;
+}
+
+StageTime stage_time(const lb_params& p, double tau) {
+  StageTime t;
+  t.tau = tau;
+  t.tau_s = p.metric == LB_METRIC_MILNE ? tau : 1.0;
+  t.inv_tau_s = 1.0 / t.tau_s;
+  return t;
+}
+
+// One Heun step of every event with the kernel arguments of the stage times
+// given directly (pred at b->tau, corr at b->tau + dtau).
+hipError_t batch_step_direct(lb_batch* b, double dtau) {
+  const int i0 = b->cur, i1 = (b->cur + 1) % 3, i2 = (b->cur + 2) % 3;
+  const StageArgs a = batch_shared_args(b, dtau);
+  hipError_t e = launch_batch_stage(b->p.precision, 0, b->variant, b->d_ev, b->d_tile_event, b->n_tiles,
+                                    stage_time(b->p, b->tau), nullptr, 0, i0, i0, i1, b->cst, b->tbd, a, b->err,
+                                    b->stream);
+  if (e != hipSuccess) return e;
+  e = launch_batch_stage(b->p.precision, 1, b->variant, b->d_ev, b->d_tile_event, b->n_tiles,
+                         stage_time(b->p, b->tau + dtau), nullptr, 0, i1, i0, i2, b->cst, b->tbd, a, b->err,
+                         b->stream);
+  if (e != hipSuccess) return e;
+  b->cur = i2;
+  b->tau += dtau;
+  return hipSuccess;
+}
+
+void drop_graphs(lb_batch* b) {
+  for (auto& g : b->graph)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  b->graph_variant = -1;
+}
+
+// Capture kBatchGraphSteps steps starting from buffer rotation 0, reading
+// the stage times from slot `slot` of the device time table.
+hipError_t capture_graph(lb_batch* b, int slot, double dtau) {
+  // captured on the batch's own stream (the caller's may be the legacy
+  // default stream, which cannot be captured); launched on the caller's
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  const StageArgs a = batch_shared_args(b, dtau);
+  const StageTime* times = b->d_times + (size_t)slot * 2 * kBatchGraphSteps;
+  int cur = 0;
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < kBatchGraphSteps && le == hipSuccess; ++k) {
+    const int i0 = cur, i1 = (cur + 1) % 3, i2 = (cur + 2) % 3;
+    le = launch_batch_stage(b->p.precision, 0, b->variant, b->d_ev, b->d_tile_event, b->n_tiles, StageTime{}, times,
+                            2 * k, i0, i0, i1, b->cst, b->tbd, a, b->err, b->cap);
+    if (le == hipSuccess)
+      le = launch_batch_stage(b->p.precision, 1, b->variant, b->d_ev, b->d_tile_event, b->n_tiles, StageTime{},
+                              times, 2 * k + 1, i1, i0, i2, b->cst, b->tbd, a, b->err, b->cap);
+    cur = i2;
+  }
+  e = hipStreamEndCapture(b->cap, &g);
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->graph[slot], g, nullptr, nullptr, 0);
+  if (g) hipGraphDestroy(g);
+  return e;
+}
+
+// kBatchGraphSteps steps (rotation 0 to 0) as one graph launch.
+hipError_t batch_graph_steps(lb_batch* b, double dtau) {
+  hipError_t e = hipSuccess;
+  if (b->graph_variant != b->variant || b->graph_dtau != dtau) {
+    drop_graphs(b);
+    for (int sl = 0; sl < 2 && e == hipSuccess; ++sl) e = capture_graph(b, sl, dtau);
+    if (e != hipSuccess) {
+      drop_graphs(b);
+      return e;
+    }
+    b->graph_variant = b->variant;
+    b->graph_dtau = dtau;
+  }
+  const int sl = b->slot;
+  // the pinned staging of this slot is free once its previous copy is done
+  if ((e = hipEventSynchronize(b->copied[sl])) != hipSuccess) return e;
+  StageTime* h = b->h_times + (size_t)sl * 2 * kBatchGraphSteps;
+  double tau = b->tau;
+  for (int k = 0; k < kBatchGraphSteps; ++k) {  // the times lb_step would use
+    h[2 * k] = stage_time(b->p, tau);
+    h[2 * k + 1] = stage_time(b->p, tau + dtau);
+    tau += dtau;
+  }
+  e = hipMemcpyAsync(b->d_times + (size_t)sl * 2 * kBatchGraphSteps, h, 2 * kBatchGraphSteps * sizeof(StageTime),
+                     hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->copied[sl], b->stream);
+  if (e == hipSuccess) e = hipGraphLaunch(b->graph[sl], b->stream);
+  if (e != hipSuccess) return e;
+  b->tau = tau;
+  b->slot ^= 1;
+  return hipSuccess;
+}
+
+// Mean milliseconds of one predictor + corrector pair of variant v over n
+// pairs, on the spare buffers (the state is unchanged).
+hipError_t time_variant(lb_batch* b, int v, double dtau, int n, float* ms) {
+  hipError_t e = set_variant(b, v);
+  if (e != hipSuccess) return e;
+  const int i0 = b->cur, i1 = (b->cur + 1) % 3, i2 = (b->cur + 2) % 3;
+  const StageArgs a = batch_shared_args(b, dtau);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  for (auto& x : ev)
+    if ((e = hipEventCreate(&x)) != hipSuccess) return e;
+  for (int k = -1; k < n && e == hipSuccess; ++k) {  // k = -1: untimed warm-up
+    if (k == 0) hipEventRecord(ev[0], b->stream);
+    e = launch_batch_stage(b->p.precision, 0, v, b->d_ev, b->d_tile_event, b->n_tiles, stage_time(b->p, b->tau),
+                           nullptr, 0, i0, i0, i1, b->cst, b->tbd, a, b->err, b->stream);
+    if (e == hipSuccess)
+      e = launch_batch_stage(b->p.precision, 1, v, b->d_ev, b->d_tile_event, b->n_tiles,
+                             stage_time(b->p, b->tau + dtau), nullptr, 0, i1, i0, i2, b->cst, b->tbd, a, b->err,
+                             b->stream);
+  }
+  hipEventRecord(ev[1], b->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+  if (e == hipSuccess) *ms /= n;
+  hipEventDestroy(ev[0]);
+  hipEventDestroy(ev[1]);
+  return e;
+}
+
+int batch_tune(lb_batch* b, double dtau, int32_t* variant_out, double* ms_out) {
+  const int nv = batch_variants(b->p.precision);
+  int best = -1;
+  float best_ms = 0;
+  for (int v = 0; v < nv; ++v) {
+    float ms = 0;
+    hipError_t e = time_variant(b, v, dtau, 5, &ms);
+    if (e != hipSuccess) return hip_fail(e, "batch tuning");
+    if (ms_out) ms_out[v] = ms;
+    if (best < 0 || ms < best_ms) {
+      best = v;
+      best_ms = ms;
+    }
+  }
+  hipError_t e = set_variant(b, best);
+  if (e != hipSuccess) return hip_fail(e, "batch tile map");
+  if (variant_out) *variant_out = best;
+  return read_err_word(b->err, b->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lb_batch_workspace_bytes(const lb_params* p, const lb_event* events, int32_t n_events) {
+  g_err.clear();
+  std::string m = validate_batch(p, events, n_events);
+  if (!m.empty()) {
+    fail(LB_E_ARG, m);
+    return 0;
+  }
+  return batch_layout(p, events, n_events).total;
+}
+
+int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, int32_t n_events, void* d_workspace,
+                  size_t ws_bytes, const double* const* d_e0, void* hip_stream) {
+  g_err.clear();
+  if (!out) return fail(LB_E_ARG, "out is NULL");
+  *out = nullptr;
+  std::string m = validate_batch(p, events, n_events);
+  if (!m.empty()) return fail(LB_E_ARG, m);
+  if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(LB_E_ARG, "workspace NULL or not 256-byte aligned");
+  if (!d_e0) return fail(LB_E_ARG, "e0 pointer array is NULL");
+  for (int i = 0; i < n_events; ++i)
+    if (!d_e0[i]) return fail(LB_E_ARG, "e0 of event " + std::to_string(i) + " is NULL");
+  const BatchLayout L = batch_layout(p, events, n_events);
+  if (ws_bytes < L.total) return fail(LB_E_ARG, "workspace too small: need " + std::to_string(L.total) + " bytes");
+
+  lb_batch* b = new lb_batch();
+  b->p = *p;
+  b->events.assign(events, events + n_events);
+  b->stream = (hipStream_t)hip_stream;
+  b->ws = (char*)d_workspace;
+  m = build_lattice(*p, &b->lat);
+  if (!m.empty()) {
+    delete b;
+    return fail(LB_E_ARG, m);
+  }
+  HostTables T;
+  m = build_tables(*p, &T);
+  if (!m.empty()) {
+    delete b;
+    return fail(LB_E_EOS, m);
+  }
+  fill_const(b->lat, &b->cf);
+  fill_const(b->lat, &b->cd);
+  b->cst = b->ws + L.cst;
+  b->tbd = (EosTable*)(b->ws + L.tbd);
+  b->err = (int*)(b->ws + L.err);
+  b->d_ev = (BatchEvent*)(b->ws + L.ev);
+  b->d_tile_event = (int32_t*)(b->ws + L.tile_event);
+  b->d_times = (StageTime*)(b->ws + L.times);
+  b->tb = T.desc;
+  b->tb.pts = (double*)(b->ws + L.pts);
+  b->tb.inv_ek = (double*)(b->ws + L.inv_ek);
+  b->tb.inv_ee = (double*)(b->ws + L.inv_ee);
+  b->ev.resize(n_events);
+  for (int i = 0; i < n_events; ++i) {
+    BatchEvent& E = b->ev[i];
+    E.nx = events[i].nx;
+    E.ny = events[i].ny;
+    E.n_sites = events[i].nx * events[i].ny;
+    E.tile0 = 0;
+    E.inv2dx = 0.5 / events[i].dx_fm;
+    E.inv_eta_hbarc = std::isinf(events[i].eta_over_s) ? 0.0 : 1.0 / (events[i].eta_over_s * kHbarC);
+    for (int k = 0; k < 3; ++k) {
+      E.F[k] = b->ws + L.F[3 * i + k];
+      E.lnM[k] = (double*)(b->ws + L.lnM[3 * i + k]);
+      E.sc[k] = (double*)(b->ws + L.sc[3 * i + k]);
+    }
+    b->vsum_over_dx = std::max(b->vsum_over_dx, b->lat.vsum_max / events[i].dx_fm);
+  }
+  hipError_t e = hipSuccess;
+  if ((e = hipHostMalloc((void**)&b->h_times, 2 * 2 * kBatchGraphSteps * sizeof(StageTime))) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->copied[0], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->copied[1], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) {
+    lb_batch_destroy(b);
+    return hip_fail(e, "batch host staging");
+  }
+  if ((e = hipMemcpy((void*)b->tb.pts, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy((void*)b->tb.inv_ek, T.inv_ek.data(), T.inv_ek.size() * 8, hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy((void*)b->tb.inv_ee, T.inv_ee.data(), T.inv_ee.size() * 8, hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(b->tbd, &b->tb, sizeof(EosTable), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemsetAsync(b->err, 0, sizeof(int), b->stream)) != hipSuccess) {
+    lb_batch_destroy(b);
+    return hip_fail(e, "upload of EoS tables");
+  }
+  if (p->precision == LB_FP32_FP64MATCH) {
+    StageConst<float> sf;
+    fill_stage_const(b->lat, &sf);
+    sf = metric_stage_const(sf, p->metric);
+    e = hipMemcpy(b->cst, &sf, sizeof(sf), hipMemcpyHostToDevice);
+  } else {
+    StageConst<double> sd;
+    fill_stage_const(b->lat, &sd);
+    sd = metric_stage_const(sd, p->metric);
+    e = hipMemcpy(b->cst, &sd, sizeof(sd), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    lb_batch_destroy(b);
+    return hip_fail(e, "upload of stage constants");
+  }
+  b->tau = p->tau0_fm;
+  b->cur = 0;
+  const void* lc = p->precision == LB_FP64 ? (const void*)&b->cd : (const void*)&b->cf;
+  for (int i = 0; i < n_events && e == hipSuccess; ++i) {
+    const StageArgs a = params_args(event_params(*p, events[i]), b->tau, 0.0);
+    e = launch_init(p->precision, d_e0[i], nullptr, nullptr, b->ev[i].F[0], b->ev[i].lnM[0], lc, b->tb, a, b->err,
+                    b->stream);
+    if (e == hipSuccess)
+      e = launch_site(p->precision, b->ev[i].F[0], b->ev[i].lnM[0], b->ev[i].sc[0], b->cst, b->tbd, a, b->err,
+                      b->stream);
+  }
+  if (e == hipSuccess) e = set_variant(b, p->precision == LB_FP32_FP64MATCH ? 1 : 1);  // until tuned
+  if (e != hipSuccess) {
+    lb_batch_destroy(b);
+    return hip_fail(e, "batch initial state");
+  }
+  b->variant = -1;  // not tuned yet (the tile map above is variant 1)
+  int rc = read_err_word(b->err, b->stream);
+  if (rc != LB_OK) {
+    lb_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return LB_OK;
+}
+
+int lb_batch_tune(lb_batch* b, double dtau_fm, int32_t* variant_out, double* ms_out) {
+  if (!b) return fail(LB_E_STATE, "batch not initialised");
+  if (!(dtau_fm > 0) || !std::isfinite(dtau_fm)) return fail(LB_E_ARG, "dtau must be finite and > 0");
+  return batch_tune(b, dtau_fm, variant_out, ms_out);
+}
+
+int lb_batch_set_variant(lb_batch* b, int32_t variant) {
+  if (!b) return fail(LB_E_STATE, "batch not initialised");
+  if (variant < 0 || variant >= batch_variants(b->p.precision)) return fail(LB_E_ARG, "no such kernel variant");
+  hipError_t e = set_variant(b, variant);
+  if (e != hipSuccess) return hip_fail(e, "batch tile map");
+  return LB_OK;
+}
+
+int lb_batch_step(lb_batch* b, int32_t n_steps, double dtau_fm) {
+  if (!b) return fail(LB_E_STATE, "batch not initialised");
+  if (n_steps < 0) return fail(LB_E_ARG, "n_steps must be >= 0");
+  if (!(dtau_fm > 0) || !std::isfinite(dtau_fm)) return fail(LB_E_ARG, "dtau must be finite and > 0");
+  const double cfl = b->vsum_over_dx * dtau_fm;
+  if (cfl > 0.5)
+    return fail(LB_E_ARG, "CFL number " + std::to_string(cfl) + " > 0.5 in some event (reduce dtau)");
+  if (n_steps == 0) return LB_OK;
+  if (b->variant < 0) {
+    int rc = batch_tune(b, dtau_fm, nullptr, nullptr);
+    if (rc != LB_OK) return rc;
+  }
+  int left = n_steps;
+  while (left > 0) {
+    hipError_t e;
+    if (b->cur == 0 && left >= kBatchGraphSteps) {
+      e = batch_graph_steps(b, dtau_fm);
+      left -= kBatchGraphSteps;
+    } else {
+      e = batch_step_direct(b, dtau_fm);
+      left -= 1;
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch step");
+  }
+  return LB_OK;
+}
+
+int lb_batch_moments(lb_batch* b, int32_t event, double* d_out) {
+  if (!b) return fail(LB_E_STATE, "batch not initialised");
+  if (event < 0 || event >= (int)b->ev.size() || !d_out) return fail(LB_E_ARG, "bad event index or out is NULL");
+  const StageArgs a = params_args(event_params(b->p, b->events[event]), b->tau, 0.0);
+  const void* lc = b->p.precision == LB_FP64 ? (const void*)&b->cd : (const void*)&b->cf;
+  hipError_t e = launch_moments(b->p.precision, b->ev[event].F[b->cur], b->ev[event].lnM[b->cur], d_out, lc, b->tb,
+                                a, b->err, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "moments launch");
+  return LB_OK;
+}
+
+int lb_batch_get_state(lb_batch* b, int32_t event, double* d_F, double* d_lnM, double* tau_fm) {
+  if (!b) return fail(LB_E_STATE, "batch not initialised");
+  if (event < 0 || event >= (int)b->ev.size()) return fail(LB_E_ARG, "bad event index");
+  const int n_sites = b->ev[event].n_sites, n_q = b->p.n_xi * b->p.n_theta;
+  if (d_F) {
+    hipError_t e = launch_get_state(b->p.precision, b->ev[event].F[b->cur], d_F, n_q, n_sites, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "get_state launch");
+  }
+  if (d_lnM) {
+    hipError_t e = hipMemcpyAsync(d_lnM, b->ev[event].lnM[b->cur], (size_t)n_sites * 8, hipMemcpyDeviceToDevice,
+                                  b->stream);
+    if (e != hipSuccess) return hip_fail(e, "copy of ln M");
+  }
+  if (tau_fm) *tau_fm = b->tau;
+  return LB_OK;
+}
+
+int lb_batch_status(lb_batch* b) {
+  if (!b) return fail(LB_E_STATE, "batch not initialised");
+  return read_err_word(b->err, b->stream);
+}
+
+int lb_batch_destroy(lb_batch* b) {
+  if (!b) return LB_OK;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  drop_graphs(b);
+  for (auto& x : b->copied)
+    if (x) hipEventDestroy(x);
+  if (b->h_times) hipHostFree(b->h_times);
+  if (b->cap) hipStreamDestroy(b->cap);
+  delete b;
   return LB_OK;
 }
 

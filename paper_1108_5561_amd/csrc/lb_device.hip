@@ -379,6 +379,31 @@ __device__ __forceinline__ CPtr<R> const_ptr(const StageConst<R>* p) {
   asm volatile("" : "+s"(v));
   return (CPtr<R>)v;
 }
+// The EoS table descriptor from its device copy, with scalar loads at the
+// point of use.
+__device__ __forceinline__ EosTable load_table(const EosTable* p) {
+  uint64_t v = (uint64_t)p;
+  asm volatile("" : "+s"(v));
+  const __attribute__((address_space(4))) EosTable* q = (const __attribute__((address_space(4))) EosTable*)v;
+  EosTable t;
+  t.pts = q->pts;
+  t.inv_ek = q->inv_ek;
+  t.inv_ee = q->inv_ee;
+  t.n = q->n;
+  t.n_inv = q->n_inv;
+  t.u0 = q->u0;
+  t.h = q->h;
+  t.inv_h = q->inv_h;
+  t.gk0 = q->gk0;
+  t.gk_h = q->gk_h;
+  t.gk_inv_h = q->gk_inv_h;
+  t.ge0 = q->ge0;
+  t.ge_h = q->ge_h;
+  t.ge_inv_h = q->ge_inv_h;
+  t.u_lo = q->u_lo;
+  t.u_hi = q->u_hi;
+  return t;
+}
 // Partial moments of one slice over the mirror pairs: w gamma^2, w gamma
 // |v_perp|, w |v_perp|^2 and w, summed over the 25 nodes (eq. (emtnew)).
 template <typename R>
@@ -408,7 +433,7 @@ __device__ __forceinline__ void slice_moments(const R f[25], CPtr<R> C, R* p0, R
 // lnM = ln M of its site.  s_mom is the block's LDS scratch [7][tile sites].
 template <typename R, int kTY>
 __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM, int t, int bx,
-                                           int by, const EosTable& tb, const StageArgs& a,
+                                           int by, const EosTable* __restrict__ tbg, const StageArgs& a,
                                            double* __restrict__ sc, int* __restrict__ err,
                                            double (*s_mom)[kTX * kTY]) {
   constexpr int kTile = kTX * kTY;
@@ -445,6 +470,7 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   double lam, u[3];
   const bool matched = landau3(tk, &lam, u);
   EosAt E;
+  const EosTable tb = load_table(tbg);  // read here, where it is used
   const bool eos_ok = eos_cell(tb, lam, &E);
   if (!finite) flag(err, kErrNonfinite);
   else if (!matched) flag(err, kErrMatch);
@@ -494,214 +520,78 @@ __device__ __forceinline__ LaneSite lane_site(int tile, int tiles_x, int ts, int
   return g;
 }
 
-// Stage kernel: one block per 8 x TY tile, blocks in the XCD-aware tile
-// order of xcd_tile.
+
+// Stage kernel of one event: one block per 8 x TY tile, blocks in the
+// XCD-aware tile order of xcd_tile.
 template <typename R, int STAGE>
 __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, (MinWaves<R, STAGE>::v)) void stage_kernel(
     const R* __restrict__ Fin, const R* __restrict__ Fbase, R* __restrict__ Fout,
     const double* __restrict__ lnMin, const double* __restrict__ lnMbase, double* __restrict__ lnMout,
     const double* __restrict__ scin, double* __restrict__ scout, const StageConst<R>* __restrict__ Cg,
-    const EosTable tb, const StageArgs a, int* __restrict__ err) {
-  constexpr int NXI = 5, NTH = 5, Q = NXI * NTH;
+    const EosTable* __restrict__ tbg, const StageArgs a, int* __restrict__ err) {
   constexpr int kTY = TileRows<R>::v;
   __shared__ double s_mom[7][kTX * kTY];
-
-  const int t = threadIdx.x;
-  const int ts = t >> 3;  // site within the tile
-  const int l = t & 7;    // phi slice
-  const int tiles_x = (a.nx + kTX - 1) / kTX;
-  const int n_tiles = tiles_x * ((a.ny + kTY - 1) / kTY);
+  const int n_tiles = ((a.nx + kTX - 1) / kTX) * ((a.ny + kTY - 1) / kTY);
   const int tile = xcd_tile(n_tiles);
   if (tile >= n_tiles) return;  // whole block
-  const CPtr<R> C = const_ptr(Cg);
-  const LaneSite g = lane_site<R, kTY>(tile, tiles_x, ts, l, a);
-  const int bx = g.bx, by = g.by, x = g.x, y = g.y, site = g.site;
-  const bool valid = g.valid;
-  const uint32_t lane = (uint32_t)site * kSl + l;  // slice index in a plane
-  using NL = NodeLayout<R>;
-  const uint32_t gb = NL::gbytes(a.n_sites);
-  const uint32_t fbytes = (uint32_t)a.n_sites * kSl * 25u * (uint32_t)sizeof(R);
+#include "stage_body.inc"
+}
 
-  // ---- 1: the slice; streaming (its loads right behind the slice's); the
-  // site scalars of the input state; S2 (radial) and the Milne term S1/tau ----
-  const __amdgpu_buffer_rsrc_t rin = buf_rsrc(Fin, fbytes);
-  R f[Q];
-  load_slice<R>(rin, lane, gb, f);
-  __builtin_amdgcn_sched_barrier(0);
-  const R cl = C->cosl[l], sl = C->sinl[l];
-  R S2[Q], R0[Q];
+// Batched stage: the launch's tiles are the tiles of all events in turn
+// (event e owns tiles [tile0_e, tile0_e + tiles_e)), taken in the XCD-aware
+// order; each block looks up its event and runs the single-event tile code,
+// so an event's result does not depend on the batch it is in.
+template <typename R, int STAGE, int kTY, int kW>
+__global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
+    const BatchEvent* __restrict__ ev, const int32_t* __restrict__ tile_event, int n_tiles, StageTime time,
+    const StageTime* __restrict__ times, int time_idx, int i_in, int i_base, int i_out,
+    const StageConst<R>* __restrict__ Cg, const EosTable* __restrict__ tbg, StageArgs a,
+    int* __restrict__ err) {
+  __shared__ double s_mom[7][kTX * kTY];
+  const int tile = xcd_tile(n_tiles);
+  if (tile >= n_tiles) return;  // whole block
+  // the event, its buffers and the stage time through constant-address
+  // pointers: uniform values, read with scalar loads
+  typedef const __attribute__((address_space(4))) BatchEvent* EvP;
+  typedef const __attribute__((address_space(4))) int32_t* TeP;
+  typedef const __attribute__((address_space(4))) StageTime* TmP;
+  const int e = ((TeP)(uint64_t)tile_event)[tile];
+  const EvP ep = (EvP)(uint64_t)ev + e;
+  struct {
+    int32_t tile0;
+  } E;
+  E.tile0 = ep->tile0;
+  if (times) {
+    const TmP tp = (TmP)(uint64_t)times + time_idx;
+    time.tau = tp->tau;
+    time.tau_s = tp->tau_s;
+    time.inv_tau_s = tp->inv_tau_s;
+  }
+  a.nx = ep->nx;
+  a.ny = ep->ny;
+  a.n_sites = ep->n_sites;
+  a.inv2dx = ep->inv2dx;
+  a.inv_dx = 2.0 * a.inv2dx;
+  a.inv_eta_hbarc = ep->inv_eta_hbarc;
+  a.tau = time.tau;
+  a.tau_s = time.tau_s;
+  a.inv_tau_s = time.inv_tau_s;
+  // only the buffers this stage touches (scalar loads at uniform offsets)
+  const R* __restrict__ Fin = (const R*)ep->F[i_in];
+  const R* __restrict__ Fbase = (const R*)ep->F[i_base];
+  R* __restrict__ Fout = (R*)ep->F[i_out];
+  const double* __restrict__ lnMin = ep->lnM[i_in];
+  const double* __restrict__ lnMbase = ep->lnM[i_base];
+  double* __restrict__ lnMout = ep->lnM[i_out];
+  const double* __restrict__ scin = ep->sc[i_in];
+  double* __restrict__ scout = ep->sc[i_out];
   {
-    // second-order upwind along +(cos phi, sin phi): x-1, x-2 etc., periodic
-    const int dxr = (cl > (R)0) ? 1 : ((cl < (R)0) ? -1 : 0);
-    const int dyr = (sl > (R)0) ? 1 : ((sl < (R)0) ? -1 : 0);
-    // slice indices of the upwind neighbours
-    const uint32_t nx1 = (uint32_t)(y * a.nx + wrap(x - dxr, a.nx)) * kSl + l;
-    const uint32_t nx2 = (uint32_t)(y * a.nx + wrap(x - 2 * dxr, a.nx)) * kSl + l;
-    const uint32_t ny1 = (uint32_t)(wrap(y - dyr, a.ny) * a.nx + x) * kSl + l;
-    const uint32_t ny2 = (uint32_t)(wrap(y - 2 * dyr, a.ny) * a.nx + x) * kSl + l;
-    // (3 F_i - 4 F_{i-1} + F_{i-2}) |cos phi|/(2 dx) + the same along y, times
-    // tau_s (the stage works with R0' = tau_s R0, see below)
-    const R ax = (R)(fabs((double)cl) * a.inv2dx * a.tau_s), ay = (R)(fabs((double)sl) * a.inv2dx * a.tau_s);
-    const R c0 = (R)3 * (ax + ay), c1 = (R)(-4) * ax, c2 = (R)(-4) * ay;
-    constexpr int V = NL::V;
-#pragma unroll
-    for (int g = 0; g <= NL::NG; ++g) {
-      R h1[V], h2[V], h3[V], h4[V];
-      const int nq = g < NL::NG ? V : 1;  // the last group is node 24 alone
-      if (g < NL::NG) {
-        ld_vec<R>(rin, nx1 * 16u, g * gb, h1);
-        ld_vec<R>(rin, nx2 * 16u, g * gb, h2);
-        ld_vec<R>(rin, ny1 * 16u, g * gb, h3);
-        ld_vec<R>(rin, ny2 * 16u, g * gb, h4);
-      } else {
-        constexpr uint32_t es = (uint32_t)sizeof(R);
-        h1[0] = Buf<R>::ld(rin, nx1 * es, g * gb);
-        h2[0] = Buf<R>::ld(rin, nx2 * es, g * gb);
-        h3[0] = Buf<R>::ld(rin, ny1 * es, g * gb);
-        h4[0] = Buf<R>::ld(rin, ny2 * es, g * gb);
-      }
-#pragma unroll
-      for (int c = 0; c < nq; ++c) {
-        const int q = g * V + c;
-        const int j = q % NTH;
-        const int i = (q / NTH) * 3 + (j < 3 ? j : 4 - j);
-        const R tr = c0 * f[q] + c1 * h1[c] + ax * h2[c] + c2 * h3[c] + ay * h4[c];
-        R0[q] = -C->sigi[i] * tr;  // -(|v_perp|/gamma) along (cos, sin)
-      }
+    const int tile_g = tile;
+    {
+      const int tile = tile_g - E.tile0;  // within the event
+#include "stage_body.inc"
     }
   }
-  // FP32: the streaming loads may overlap the operator arithmetic below;
-  // FP64 (twice the registers per value) schedules better without
-  if constexpr (sizeof(R) == 8) __builtin_amdgcn_sched_barrier(0);
-
-  // site record of the input state; ln M at the four neighbours
-  const uint32_t ns = (uint32_t)a.n_sites;
-  const SiteRecord<R> rec = load_record<R>(buf_rsrc(scin, ns * SiteRecord<R>::kBytes), site);
-  const double beta = rec.beta, lnM = rec.lnM;
-  const R ut = rec.v[kScUt], ux = rec.v[kScUx], uy = rec.v[kScUy], Mr = rec.v[kScM];
-  const R Meq = rec.v[kScMeq], rr = rec.v[kScRate], MinvT = rec.v[kScMinvT], l2invT = rec.v[kScL2invT];
-  const __amdgpu_buffer_rsrc_t rl = buf_rsrc(lnMin, ns * 8u);
-  const double lnMxp = Buf<double>::ld(rl, (uint32_t)(y * a.nx + wrap(x + 1, a.nx)) * 8u, 0);
-  const double lnMxm = Buf<double>::ld(rl, (uint32_t)(y * a.nx + wrap(x - 1, a.nx)) * 8u, 0);
-  const double lnMyp = Buf<double>::ld(rl, (uint32_t)(wrap(y + 1, a.ny) * a.nx + x) * 8u, 0);
-  const double lnMym = Buf<double>::ld(rl, (uint32_t)(wrap(y - 1, a.ny) * a.nx + x) * 8u, 0);
-#pragma unroll
-  for (int k = 0; k < NXI; ++k) {
-#pragma unroll
-    for (int j = 0; j < NTH; ++j) {
-      R s2 = 0;
-#pragma unroll
-      for (int kp = 0; kp < NXI; ++kp) s2 += C->A2[k * NXI + kp] * f[kp * NTH + j];
-      S2[k * NTH + j] = s2;
-    }
-    const R* fk = &f[k * NTH];
-    const R e0 = fk[0] + fk[4], e1 = fk[1] + fk[3], o0 = fk[0] - fk[4], o1 = fk[1] - fk[3], c2 = fk[2];
-#pragma unroll
-    for (int pr = 0; pr < 2; ++pr) {
-      const R ev = C->Ev[pr][0] * e0 + C->Ev[pr][1] * e1 + C->Ev[pr][2] * c2;
-      const R od = C->Od[pr][0] * o0 + C->Od[pr][1] * o1;
-      R sa = 0, sb = 0;
-#pragma unroll
-      for (int kp = 0; kp < NXI; ++kp) {
-        sa += C->A1[k * NXI + kp] * f[kp * NTH + pr];
-        sb += C->A1[k * NXI + kp] * f[kp * NTH + 4 - pr];
-      }
-      R0[k * NTH + pr] += C->mu2[pr] * sa + (ev + od);
-      R0[k * NTH + 4 - pr] += C->mu2[pr] * sb + (ev - od);
-    }
-    R0[k * NTH + 2] += C->Mid[0] * e0 + C->Mid[1] * e1 + C->Mid[2] * c2;  // mu = 0: no radial part
-  }
-  // centred gradient of ln M
-  const R gx = (R)((lnMxp - lnMxm) * a.inv2dx);
-  const R gy = (R)((lnMyp - lnMym) * a.inv2dx);
-
-  // ---- 2: equilibrium, BGK, mass-gradient force, sums, update ----
-  const R cu = ux * cl + uy * sl;            // u_perp . (cos phi, sin phi)
-  const R Gl = gx * cl + gy * sl;            // grad ln M . (cos phi, sin phi)
-  const R gu = gx * ux + gy * uy;            // grad ln M . u_perp
-  // Per node, with s = |v_perp| and gamma = cosh xi:
-  //   F_eq = Z exp(-[u^tau E_eq - M s (u.phi)]/T) = exp2(s Mcu2 + aE_k),
-  //   BGK  = r (u.V/gamma) (F - F_eq), r = 1/tau_R,
-  //   mass-gradient force on F_eq = -F_eq (al_k s - be_k s^2 - ga_k),
-  // so r0 = R0 + F_eq (r u.V/gamma - poly) - r (u.V/gamma) F.
-  // The Milne factor 1/tau of S1 is not in the constants: every term of r0
-  // is carried times tau_s (tau for Milne, 1 for Minkowski, where the S1
-  // constants are zero), r0' = tau_s r0, and divided out in X and the update.
-  const R Mcu2 = Mr * cu * l2invT;
-  const R log2Z = (R)a.log2Z;
-  const R ts_ = (R)a.tau_s;
-  const R rrt = rr * ts_;
-  const R utl2 = ut * l2invT, alc = MinvT * Gl * ut * Mr * ts_, bec = MinvT * Gl * cu * ts_, gac = MinvT * gu * ts_;
-  R aE[NXI], al[NXI], be[NXI], ga[NXI];
-#pragma unroll
-  for (int k = 0; k < NXI; ++k) {
-    const R Eeq = nsqrt<R>(Meq * Meq + Mr * Mr * C->sh2[k]);  // sqrt(M_eq^2 + M^2 sinh^2 xi)
-    aE[k] = log2Z - utl2 * Eeq;
-    al[k] = alc * C->x[k] * nrcp<R>(Eeq);
-    be[k] = bec * C->inv_x[k];
-    ga[k] = gac * C->inv_x[k];
-  }
-  R nsum = 0, dsum = 0, wsum = 0;
-#pragma unroll
-  for (int k = 0; k < NXI; ++k) {
-#pragma unroll
-    for (int pr = 0; pr < 3; ++pr) {
-      const int i = k * 3 + pr;
-      const R sg = C->sig[i];
-      const R feq = eq_exp2<R>(sg * Mcu2 + aE[k]);             // F_eq (Sec. IV.D, with flow)
-      const R uvg = ut - C->sigi[i] * cu;                       // (u.V)/gamma
-      const R ru = rrt * uvg;
-      const R poly = al[k] * sg - be[k] * C->sig2[i] - ga[k];
-      const R fd = feq * (ru - poly);
-      const R wuv2 = C->wx2[i] * uvg * uvg;                     // w gamma^2 ((u.V)/gamma)^2
-      if (pr < 2) {
-        const int qa = k * NTH + pr, qb = k * NTH + 4 - pr;
-        const R ra = (R0[qa] + fd) - ru * f[qa];               // BGK, eq. (bgk)
-        const R rb = (R0[qb] + fd) - ru * f[qb];
-        R0[qa] = ra;
-        R0[qb] = rb;
-        const R fs = f[qa] + f[qb];
-        nsum += wuv2 * (ra + rb);
-        dsum += wuv2 * ((R)4 * fs + (S2[qa] + S2[qb]));
-        wsum += C->w[i] * fs;
-      } else {
-        const int q = k * NTH + 2;
-        const R r = (R0[q] + fd) - ru * f[q];
-        R0[q] = r;
-        nsum += wuv2 * r;
-        dsum += wuv2 * ((R)4 * f[q] + S2[q]);
-        wsum += C->w[i] * f[q];
-      }
-    }
-  }
-  nsum = sum8(nsum);
-  dsum = sum8(dsum);
-  wsum = sum8(wsum);
-
-  // mass evolution (eq. (masschange)), FP64
-  const double X = -beta * ((double)nsum * a.inv_tau_s) / ((double)wsum + beta * (double)dsum);
-  const R Xr = (R)(X * a.tau_s);
-  double lnM_new;
-  if (STAGE == 0) {
-    const R dt = (R)(a.dtau * a.inv_tau_s);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = f[q] + dt * (R0[q] + Xr * S2[q]);
-    lnM_new = lnM + a.dtau * X;
-  } else {
-    const R hdt = (R)(0.5 * a.dtau * a.inv_tau_s);
-    R fb[Q];
-    load_slice<R>(buf_rsrc(Fbase, fbytes), lane, gb, fb);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) f[q] = (R)0.5 * (fb[q] + f[q]) + hdt * (R0[q] + Xr * S2[q]);
-    lnM_new = 0.5 * (lnMbase[site] + lnM) + 0.5 * a.dtau * X;
-  }
-  if (valid) {
-    store_slice<R>(buf_rsrc(Fout, fbytes), lane, gb, f);
-    if (l == 0) lnMout[site] = lnM_new;
-  }
-
-  // ---- 3: matching of the new state for the next stage ----
-  match_tile<R, kTY>(f, C, lnM_new, t, bx, by, tb, a, scout, err, s_mom);
 }
 
 // Site scalars of a state that no stage produced (after lb_init or
@@ -709,7 +599,8 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl, (MinWaves<R, STAGE>::v)
 template <typename R>
 __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl) void site_kernel(
     const R* __restrict__ F, const double* __restrict__ lnMv, double* __restrict__ sc,
-    const StageConst<R>* __restrict__ Cg, const EosTable tb, const StageArgs a, int* __restrict__ err) {
+    const StageConst<R>* __restrict__ Cg, const EosTable* __restrict__ tbg, const StageArgs a,
+    int* __restrict__ err) {
   const CPtr<R> C = const_ptr(Cg);
   constexpr int kTY = TileRows<R>::v;
   __shared__ double s_mom[7][kTX * kTY];
@@ -726,7 +617,7 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl) void site_kernel(
   R f[25];
   load_slice<R>(buf_rsrc(F, (uint32_t)a.n_sites * kSl * 25u * (uint32_t)sizeof(R)), (uint32_t)site * kSl + l,
                 NodeLayout<R>::gbytes(a.n_sites), f);
-  match_tile<R, kTY>(f, C, lnMv[site], t, bx, by, tb, a, sc, err, s_mom);
+  match_tile<R, kTY>(f, C, lnMv[site], t, bx, by, tbg, a, sc, err, s_mom);
 }
 
 // Initial local equilibrium (Sec. IV.D): T0 from eps_EoS(T0) = e0.
@@ -867,7 +758,7 @@ inline dim3 grid_for(int n_sites) { return dim3((unsigned)(((size_t)n_sites * kS
 
 hipError_t launch_stage(int precision, int stage, const void* Fin, const void* Fbase, void* Fout,
                         const double* lnMin, const double* lnMbase, double* lnMout, const double* scin,
-                        double* scout, const void* sc, const EosTable& tb, const StageArgs& a, int* err,
+                        double* scout, const void* sc, const EosTable* tb, const StageArgs& a, int* err,
                         hipStream_t s) {
   const int ty = precision == LB_FP32_FP64MATCH ? TileRows<float>::v : TileRows<double>::v;
   const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
@@ -893,8 +784,67 @@ hipError_t launch_stage(int precision, int stage, const void* Fin, const void* F
   return hipGetLastError();
 }
 
+namespace {
+template <typename R, int STAGE, int kTY, int kW>
+hipError_t batch_launch_t(const BatchEvent* ev, const int32_t* te, int n_tiles, StageTime time,
+                          const StageTime* times, int tidx, int i_in, int i_base, int i_out, const void* sc,
+                          const EosTable* tb, const StageArgs& a, int* err, hipStream_t s) {
+  const unsigned per = (unsigned)((n_tiles + kXcds - 1) / kXcds);
+  hipLaunchKernelGGL((batch_stage_kernel<R, STAGE, kTY, kW>), dim3(per * kXcds), dim3(kTX * kTY * kSl), 0, s, ev,
+                     te, n_tiles, time, times, tidx, i_in, i_base, i_out, static_cast<const StageConst<R>*>(sc), tb,
+                     a, err);
+  return hipGetLastError();
+}
+// variant v of the batched kernel: tile rows kBatchTileRows[v % 3]; FP32
+// v / 3 = 0: 4 waves per SIMD, 1: 3; FP64: 2 waves per SIMD
+template <typename R, int STAGE>
+hipError_t batch_launch_s(int variant, const BatchEvent* ev, const int32_t* te, int n_tiles, StageTime time,
+                          const StageTime* times, int tidx, int i_in, int i_base, int i_out, const void* sc,
+                          const EosTable* tb, const StageArgs& a, int* err, hipStream_t s) {
+#define LB_BATCH_CASE(V, TY, W)                                                                                   \
+  case V:                                                                                                        \
+    return batch_launch_t<R, STAGE, TY, W>(ev, te, n_tiles, time, times, tidx, i_in, i_base, i_out, sc, tb, a, err, \
+                                           s);
+  if constexpr (sizeof(R) == 8) {
+    switch (variant) {
+      LB_BATCH_CASE(0, 2, 2)
+      LB_BATCH_CASE(1, 4, 2)
+      LB_BATCH_CASE(2, 8, 2)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (variant) {
+      LB_BATCH_CASE(0, 2, 4)
+      LB_BATCH_CASE(1, 4, 4)
+      LB_BATCH_CASE(2, 8, 4)
+      LB_BATCH_CASE(3, 2, 3)
+      LB_BATCH_CASE(4, 4, 3)
+      LB_BATCH_CASE(5, 8, 3)
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef LB_BATCH_CASE
+}
+}  // namespace
+
+hipError_t launch_batch_stage(int precision, int stage, int variant, const BatchEvent* ev,
+                              const int32_t* tile_event, int n_tiles, StageTime time, const StageTime* times,
+                              int time_idx, int i_in, int i_base, int i_out, const void* sc, const EosTable* tb,
+                              const StageArgs& a, int* err, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (precision == LB_FP32_FP64MATCH)
+    return stage == 0 ? batch_launch_s<float, 0>(variant, ev, tile_event, n_tiles, time, times, time_idx, i_in,
+                                                 i_base, i_out, sc, tb, a, err, s)
+                      : batch_launch_s<float, 1>(variant, ev, tile_event, n_tiles, time, times, time_idx, i_in,
+                                                 i_base, i_out, sc, tb, a, err, s);
+  return stage == 0 ? batch_launch_s<double, 0>(variant, ev, tile_event, n_tiles, time, times, time_idx, i_in,
+                                                i_base, i_out, sc, tb, a, err, s)
+                    : batch_launch_s<double, 1>(variant, ev, tile_event, n_tiles, time, times, time_idx, i_in,
+                                                i_base, i_out, sc, tb, a, err, s);
+}
+
 hipError_t launch_site(int precision, const void* F, const double* lnM, double* scout, const void* sc,
-                       const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
+                       const EosTable* tb, const StageArgs& a, int* err, hipStream_t s) {
   const int ty = precision == LB_FP32_FP64MATCH ? TileRows<float>::v : TileRows<double>::v;
   const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
   const unsigned per = (tiles + kXcds - 1) / kXcds;

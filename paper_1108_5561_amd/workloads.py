@@ -12,6 +12,12 @@ Workloads (transverse grids of boost-invariant Milne runs):
   spots   512 x 512, dx 0.03 fm, background + 40 Gaussian hot spots of width
           0.4 fm, centres uniform in a 6 fm disk, amplitudes exponential with
           mean 20 GeV/fm^3 (default_rng(3); per spot U1, U2, A), 2000 steps
+  batch   64 events: side n_e uniform on {64..256} and eta/s uniform on
+          [0.05, 0.3] (default_rng(4), per event n_e then eta/s), box
+          15.36 fm (dx = 15.36 / n_e), hot spots as `spots` with
+          default_rng(4000 + e); tau 0.5 -> 8 fm/c, dtau = 0.00375 fm/c
+The hot-spot workloads sit on a background floor the caller adds (the
+benchmark uses eps_EoS(0.25 GeV)).
 """
 from __future__ import annotations
 
@@ -21,6 +27,7 @@ WORKLOADS = {
     "small": dict(nx=32, ny=32, dx=0.2, tau0=0.5, tau1=2.0, steps=150, eta_over_s=0.08),
     "prec": dict(nx=256, ny=256, dx=0.025, tau0=0.5, tau1=8.0, steps=1000, eta_over_s=0.08),
     "spots": dict(nx=512, ny=512, dx=0.03, tau0=0.5, tau1=8.0, steps=2000, eta_over_s=0.16),
+    "batch": dict(n_events=64, n_min=64, n_max=256, box=15.36, tau0=0.5, tau1=8.0, steps=2000),
 }
 
 
@@ -67,3 +74,23 @@ def random_flow(nx, ny, amplitude, seed):
     """Small random transverse flow fields (u^x, u^y) for tests."""
     rng = np.random.default_rng(seed)
     return amplitude * rng.standard_normal((ny, nx)), amplitude * rng.standard_normal((ny, nx))
+
+
+def batch_events(n_events=64, n_min=64, n_max=256, box=15.36, eta_lo=0.05, eta_hi=0.3, seed=4):
+    """Per event (n, n, dx, eta/s): n uniform on {n_min..n_max}, then eta/s
+    uniform on [eta_lo, eta_hi), both from default_rng(seed) in that order
+    per event; dx = box / n."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_events):
+        n = int(rng.integers(n_min, n_max + 1))
+        eta = float(rng.uniform(eta_lo, eta_hi))
+        out.append((n, n, box / n, eta))
+    return out
+
+
+def batch_hot_spots(events, seed0=4000):
+    """Hot-spot profiles (GeV/fm^3, no background) of the events of
+    batch_events, event e drawn from default_rng(seed0 + e)."""
+    return [hot_spots(nx, ny, dx, seed=seed0 + e) for e, (nx, ny, dx, _) in enumerate(events)]
+

@@ -1,0 +1,99 @@
+"""Batched form on the GPU: every event of a batch advances exactly as the
+same event in a context of its own (lb_step, itself checked against the
+oracle in test_gpu_parity.py), for every kernel variant, across the graph
+replays of 48 steps and step counts that are not multiples of it."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1108_5561_amd as lb  # noqa: E402
+from paper_1108_5561_amd import workloads as wl  # noqa: E402
+
+DEV = "cuda:0"
+EVENTS = [(8, 8, 0.3, 0.08), (13, 7, 0.25, 0.2), (20, 16, 0.2, 0.12), (1, 3, 0.3, 0.3)]
+DTAU = 0.01
+
+
+def _e0(params, nx, ny, dx, seed):
+    bg = lb.eos_eval(params, [0.2])[0, 0] / lb.HBARC ** 3
+    spots = wl.hot_spots(nx, ny, dx, n_spots=4, width=0.6, disk_radius=0.3 * max(nx, ny) * dx,
+                         mean_amplitude=10.0, seed=seed)
+    return torch.from_numpy(bg + spots).to(DEV)
+
+
+def _setup(precision):
+    p = lb.make_params(8, 8, 0.3, precision=precision)
+    e0s = [_e0(p, nx, ny, dx, 100 + i) for i, (nx, ny, dx, _) in enumerate(EVENTS)]
+    return p, e0s
+
+
+def _single(precision, e0s, n_steps):
+    out = []
+    for (nx, ny, dx, eta), e0 in zip(EVENTS, e0s):
+        q = lb.make_params(nx, ny, dx, eta_over_s=eta, precision=precision)
+        c = lb.Context(q, e0)
+        c.step(n_steps, DTAU)
+        F, l, t = c.get_state()
+        out.append((F, l, t, c.moments()))
+        assert c.status() == lb.LB_OK
+        c.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", [lb.LB_FP64, lb.LB_FP32_FP64MATCH])
+def test_batch_equals_single_contexts_every_variant(precision):
+    p, e0s = _setup(precision)
+    n1, n2 = 50, 47   # 48 + 2 direct steps, then 1 + 46 direct (rotation not at 0)
+    ref = _single(precision, e0s, n1 + n2)
+    nvar = 6 if precision == lb.LB_FP32_FP64MATCH else 3
+    for v in range(nvar):
+        b = lb.Batch(p, EVENTS, e0s)
+        b.set_variant(v)
+        b.step(n1, DTAU)
+        b.step(n2, DTAU)
+        for e, (F, l, t, obs) in enumerate(ref):
+            Fb, lb_, tb = b.get_state(e)
+            assert tb == t
+            assert torch.equal(Fb, F), f"variant {v} event {e}"
+            assert torch.equal(lb_, l)
+            assert torch.equal(b.moments(e), obs)
+        assert b.status() == lb.LB_OK
+        b.close()
+
+
+def test_batch_graph_replays_match_direct_steps():
+    """96 steps as two graph replays equal 96 steps taken one by one."""
+    p, e0s = _setup(lb.LB_FP32_FP64MATCH)
+    a = lb.Batch(p, EVENTS, e0s)
+    b = lb.Batch(p, EVENTS, e0s)
+    a.set_variant(1)
+    b.set_variant(1)
+    a.step(96, DTAU)
+    for _ in range(96):
+        b.step(1, DTAU)
+    for e in range(len(EVENTS)):
+        Fa, la, ta = a.get_state(e)
+        Fb, lb_, tb = b.get_state(e)
+        assert ta == tb and torch.equal(Fa, Fb) and torch.equal(la, lb_)
+
+
+def test_batch_tune_and_errors():
+    p, e0s = _setup(lb.LB_FP32_FP64MATCH)
+    b = lb.Batch(p, EVENTS, e0s)
+    v, ms = b.tune(DTAU)
+    assert 0 <= v < 6 and len(ms) == 6 and all(m > 0 for m in ms) and ms[v] == min(ms)
+    F0, l0, t0 = b.get_state(2)
+    F1, l1, t1 = b.get_state(2)
+    assert t0 == t1 and torch.equal(F0, F1)   # tuning left the state alone
+    with pytest.raises(lb.LbError) as ei:
+        b.step(1, 1.0)                         # CFL far above 0.5
+    assert ei.value.code == lb.LB_E_ARG
+    with pytest.raises(lb.LbError):
+        b.get_state(len(EVENTS))
+    with pytest.raises(lb.LbError):
+        b.set_variant(6)
+    assert b.status() == lb.LB_OK
