@@ -37,7 +37,7 @@ def site_bytes(precision, stage):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_prec256_hbm_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1108_5561_amd", "csrc", "lb_device.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1108_5561_amd", "csrc", f) for f in ("lb_device.hip", "stage_body.inc")]
 
 
 def measured_traffic(kernel):
@@ -47,11 +47,12 @@ def measured_traffic(kernel):
     import hashlib
     try:
         txt = open(TRAFFIC_PROFILE).read()
-        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        for path in KERNEL_SOURCES:
+            src = hashlib.sha256(open(path, "rb").read()).hexdigest()
+            m = re.search(r"%s sha256: ([0-9a-f]{64})" % re.escape(os.path.basename(path)), txt)
+            if not m or m.group(1) != src:
+                return None
     except OSError:
-        return None
-    m = re.search(r"lb_device.hip sha256: ([0-9a-f]{64})", txt)
-    if not m or m.group(1) != src:
         return None
     c = re.search(r"^calibration fetch_kib (\S+) write_kib (\S+) bytes (\d+)", txt, re.M)
     k = re.search(r"^traffic %s fetch_kib (\S+) write_kib (\S+)" % re.escape(kernel), txt, re.M)
