@@ -162,12 +162,61 @@ int lb_get_state(lb_ctx* c, double* d_F, double* d_lnM, double* tau_fm);
  * state. */
 int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_fm);
 
-/*
- * Reverse-mode adjoint of one lb_step (the differentiable form).  Not
- * implemented in this build: returns LB_E_NOTIMPL and changes nothing.
+/* ---- differentiable form: discrete adjoint of the FP64 step ----
+ *
+ * The step differentiated is the FP64 Heun step of Sec. IV.D as lb_step
+ * computes it for an LB_FP64 context (same right-hand side: streaming,
+ * Milne term, BGK of eq. (bgk) with the equilibrium of eq. (feq) and the
+ * mass-gradient force, mass evolution of eqs. (edchange), (masschange); T, u
+ * and M_eq from the Landau matching of eq. (sanity) and the EoS inversion
+ * of Sec. III.A, whose derivatives are taken by the implicit-function
+ * theorem).  States and adjoints are in the canonical order of
+ * lb_get_state, FP64: F [N][ny][nx], ln M [ny][nx].  The adjoint arithmetic
+ * is FP64 for either precision of the context; for an LB_FP32_FP64MATCH
+ * context it is the FP64 step's adjoint evaluated on the states the caller
+ * passes (e.g. the FP32 trajectory).  The calls only read the context's
+ * parameters, lattice and EoS tables; its state is not used or changed.
+ * The adjoint workspace is caller-owned device memory, 256-byte aligned, of
+ * at least lb_adjoint_workspace_bytes(p) bytes, not touched by anyone else
+ * during a call.  Calls are asynchronous on the context's stream.
  */
-int lb_adjoint_step(lb_ctx* c, int32_t step_index, const void* d_fwd_state_k, void* d_adj_state,
-                    double* d_grad_eta_over_s, double* d_grad_e0);
+
+/* Adjoint workspace size for these parameters (0 on invalid parameters). */
+size_t lb_adjoint_workspace_bytes(const lb_params* p);
+
+/*
+ * One step of the differentiated FP64 step, from the state (d_F, d_lnM) at
+ * tau_fm to (d_F_out, d_lnM_out) at tau_fm + dtau_fm (outputs must not
+ * alias the inputs).  Equal to lb_step on an LB_FP64 context up to rounding
+ * order; it is the forward map whose transpose lb_adjoint_step applies.
+ * LB_E_ARG for NULL pointers, a workspace that is too small, tau <= 0, or a
+ * dtau that lb_step would reject (CFL).
+ */
+int lb_adjoint_forward_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F, const double* d_lnM,
+                            double* d_F_out, double* d_lnM_out, void* d_adj_workspace, size_t adj_ws_bytes);
+
+/*
+ * Reverse mode of one step at the forward state (d_F, d_lnM) at tau_fm:
+ * on entry (d_adj_F, d_adj_lnM) hold dL/dF and dL/d ln M of the state at
+ * tau_fm + dtau_fm; on return they hold dL/dF, dL/d ln M of the state at
+ * tau_fm.  *d_grad_eta_over_s (one device double) is incremented by the
+ * step's contribution to dL/d(eta/s) (tau_R depends on eta/s through
+ * Sec. IV.A; zero for eta/s = infinity).  Errors as lb_adjoint_forward_step;
+ * non-finite values or a failed matching set the device error word.
+ */
+int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F, const double* d_lnM,
+                    double* d_adj_F, double* d_adj_lnM, double* d_grad_eta_over_s, void* d_adj_workspace,
+                    size_t adj_ws_bytes);
+
+/*
+ * Reverse mode of the initial state of lb_init (T0 from eps_EoS(T0) = e0,
+ * M = M(T0), F_n = Z exp(-(u . P_n)/T0), the flow held fixed): writes
+ * d_grad_e0[ny][nx] = dL/d e0 (per GeV/fm^3) given (d_adj_F, d_adj_lnM) =
+ * dL/d(F, ln M) of the initial state.  d_e0, d_ux0, d_uy0 as passed to
+ * lb_init (both flows NULL for zero flow).
+ */
+int lb_adjoint_init(lb_ctx* c, const double* d_e0, const double* d_ux0, const double* d_uy0,
+                    const double* d_adj_F, const double* d_adj_lnM, double* d_grad_e0);
 
 /* Synchronise the context's stream and return the sticky device error
  * (LB_OK if none). */

@@ -73,7 +73,10 @@ def _load():
         "lb_moments": (ctypes.c_int, [vp, vp]),
         "lb_get_state": (ctypes.c_int, [vp, vp, vp, dp]),
         "lb_set_state": (ctypes.c_int, [vp, vp, vp, ctypes.c_double]),
-        "lb_adjoint_step": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
+        "lb_adjoint_workspace_bytes": (sz, [P]),
+        "lb_adjoint_forward_step": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp, sz]),
+        "lb_adjoint_step": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp, vp, sz]),
+        "lb_adjoint_init": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "lb_status": (ctypes.c_int, [vp]),
         "lb_destroy": (ctypes.c_int, [vp]),
         "lb_last_error": (ctypes.c_char_p, []),
@@ -251,8 +254,45 @@ class Context:
         check(lib.lb_profile_stage(self._ctx, int(stage), int(n), float(dtau_fm), ctypes.byref(ms)))
         return ms.value
 
-    def adjoint_step(self, *args):
-        return lib.lb_adjoint_step(self._ctx, 0, None, None, None, None)
+    # ---- differentiable form (lb_adjoint_*) ----
+    def _state_check(self, *ts):
+        torch = self.torch
+        shapes = [(self.N, self.params.ny, self.params.nx), (self.params.ny, self.params.nx)]
+        for t in ts:
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device or tuple(t.shape) not in shapes:
+                raise LbError(LB_E_ARG, "states and adjoints must be contiguous float64 [N, ny, nx] / [ny, nx] on the context's GPU")
+
+    def adjoint_workspace(self):
+        """A device buffer of lb_adjoint_workspace_bytes for this context."""
+        n = lib.lb_adjoint_workspace_bytes(ctypes.byref(self.params))
+        if n == 0:
+            raise LbError(LB_E_ARG, last_error())
+        return self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+
+    def adjoint_forward_step(self, tau_fm, dtau_fm, F, lnM, ws):
+        """The differentiated FP64 step from (F, lnM) at tau: new (F, lnM)."""
+        self._state_check(F, lnM)
+        Fo, Lo = self.torch.empty_like(F), self.torch.empty_like(lnM)
+        check(lib.lb_adjoint_forward_step(self._ctx, float(tau_fm), float(dtau_fm), F.data_ptr(), lnM.data_ptr(),
+                                          Fo.data_ptr(), Lo.data_ptr(), ws.data_ptr(), ws.numel()))
+        return Fo, Lo
+
+    def adjoint_step(self, tau_fm, dtau_fm, F, lnM, adj_F, adj_lnM, grad_eta, ws):
+        """In place: (adj_F, adj_lnM) <- transpose of the step at (F, lnM, tau)
+        applied to them; grad_eta (one float64 on the GPU) += d/d(eta/s)."""
+        self._state_check(F, lnM, adj_F, adj_lnM)
+        check(lib.lb_adjoint_step(self._ctx, float(tau_fm), float(dtau_fm), F.data_ptr(), lnM.data_ptr(),
+                                  adj_F.data_ptr(), adj_lnM.data_ptr(), grad_eta.data_ptr(), ws.data_ptr(),
+                                  ws.numel()))
+
+    def adjoint_init(self, e0, adj_F, adj_lnM, ux0=None, uy0=None):
+        """dL/d e0 [ny, nx] from the adjoint of the initial state."""
+        self._state_check(e0, adj_F, adj_lnM)
+        g = self.torch.empty_like(e0)
+        check(lib.lb_adjoint_init(self._ctx, e0.data_ptr(), ux0.data_ptr() if ux0 is not None else None,
+                                  uy0.data_ptr() if uy0 is not None else None, adj_F.data_ptr(),
+                                  adj_lnM.data_ptr(), g.data_ptr()))
+        return g
 
     def close(self):
         if self._ctx:
@@ -344,3 +384,98 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def node_tensors(p, device):
+    """Per-node quantities in the canonical node order, as float64 tensors of
+    shape [N]: weight w_n, gamma_n, v^x_n, v^y_n, v^Y_n (Sec. IV.C; the
+    moments are T^{ab}_kin = M^4/(2 pi^2) sum_n w_n F_n V^a_n V^b_n)."""
+    import numpy as np
+    import torch
+    info = lattice_info(p)
+    x, wxi, mu, wth, c, s_ = info["x"], info["w_xi"], info["mu"], info["w_th"], info["cos"], info["sin"]
+    nphi2 = 2 * p.n_phi
+    w, g, vx, vy, vY = [], [], [], [], []
+    for k in range(p.n_xi):
+        sh = math.sqrt(x[k] * x[k] - 1.0)
+        for j in range(p.n_theta):
+            sig = sh * math.sqrt(1.0 - mu[j] * mu[j])
+            for l in range(nphi2):
+                w.append(math.exp(p.z0 * x[k]) * wxi[k] * wth[j] / (2.0 * nphi2))
+                g.append(x[k])
+                vx.append(sig * c[l])
+                vy.append(sig * s_[l])
+                vY.append(sh * mu[j])
+    return tuple(torch.tensor(np.array(a), dtype=torch.float64, device=device) for a in (w, g, vx, vy, vY))
+
+
+class _Evolve:
+    """Checkpointed forward run and its adjoint (see evolve)."""
+
+    @staticmethod
+    def build():
+        import torch
+
+        class Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, e0, eta, params, n_steps, dtau, every):
+                p = lb_params.from_buffer_copy(params)
+                p.eta_over_s = float(eta)
+                c = Context(p, e0.detach().contiguous())
+                ckpt = []
+                for k in range(n_steps):
+                    if k % every == 0:
+                        ckpt.append(c.get_state())
+                    c.step(1, dtau)
+                F, lnM, _ = c.get_state()
+                if c.status() != LB_OK:
+                    raise LbError(c.status(), last_error())
+                ctx.c, ctx.ckpt, ctx.n, ctx.dtau, ctx.every = c, ckpt, n_steps, dtau, every
+                ctx.save_for_backward(e0)
+                ctx.eta_shape = eta.shape if torch.is_tensor(eta) else None
+                return F, lnM
+
+            @staticmethod
+            def backward(ctx, gF, gL):
+                (e0,) = ctx.saved_tensors
+                c = ctx.c
+                aF = (gF if gF is not None else torch.zeros((c.N, c.params.ny, c.params.nx), dtype=torch.float64,
+                                                            device=c.device)).detach().clone().contiguous()
+                aL = (gL if gL is not None else torch.zeros((c.params.ny, c.params.nx), dtype=torch.float64,
+                                                            device=c.device)).detach().clone().contiguous()
+                g_eta = torch.zeros(1, dtype=torch.float64, device=c.device)
+                ws = c.adjoint_workspace()
+                for seg in reversed(range(len(ctx.ckpt))):
+                    k0 = seg * ctx.every
+                    k1 = min(k0 + ctx.every, ctx.n)
+                    F, L, tau = ctx.ckpt[seg]
+                    c.set_state(F, L, tau)
+                    states = [(F, L, tau)]
+                    for _ in range(k0 + 1, k1):
+                        c.step(1, ctx.dtau)
+                        states.append(c.get_state())
+                    for F, L, tau in reversed(states):
+                        c.adjoint_step(tau, ctx.dtau, F, L, aF, aL, g_eta, ws)
+                g_e0 = c.adjoint_init(e0.detach().contiguous(), aF, aL)
+                if c.status() != LB_OK:
+                    raise LbError(c.status(), last_error())
+                ge = g_eta.reshape(ctx.eta_shape).to(e0.device) if ctx.eta_shape is not None else None
+                return g_e0, ge, None, None, None, None
+
+        return Fn
+
+
+_evolve_fn = None
+
+
+def evolve(params, e0, eta_over_s, n_steps, dtau_fm, checkpoint_every=50):
+    """Differentiable run: the state (F [N, ny, nx], ln M [ny, nx]) after
+    n_steps Heun steps from lb_init(e0) with the given eta/s, as a
+    torch.autograd.Function of e0 (float64 [ny, nx] on the GPU) and eta_over_s
+    (a float64 tensor with one element).  The backward pass re-runs the
+    forward from checkpoints taken every checkpoint_every steps and applies
+    lb_adjoint_step backwards, then lb_adjoint_init."""
+    global _evolve_fn
+    if _evolve_fn is None:
+        _evolve_fn = _Evolve.build()
+    return _evolve_fn.apply(e0, eta_over_s, params, int(n_steps), float(dtau_fm), int(checkpoint_every))

@@ -271,6 +271,57 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(LB_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Adjoint workspace: the predictor state, the adjoint of the predictor
+// state, R0_bar, the ln M gradient adjoint and the per-site eta/s adjoint.
+struct AdjLayout {
+  size_t Fp, Lp, aF1, aL1, Rb, gb, eta, total;
+};
+AdjLayout adj_layout(const lb_params& p) {
+  const size_t ns = (size_t)p.nx * (size_t)p.ny;
+  const size_t nF = ns * (size_t)p.n_xi * (size_t)p.n_theta * 2 * (size_t)p.n_phi * sizeof(double);
+  AdjLayout L;
+  size_t off = 0;
+  L.Fp = off;
+  off = align_up(off + nF);
+  L.Lp = off;
+  off = align_up(off + ns * sizeof(double));
+  L.aF1 = off;
+  off = align_up(off + nF);
+  L.aL1 = off;
+  off = align_up(off + ns * sizeof(double));
+  L.Rb = off;
+  off = align_up(off + nF);
+  L.gb = off;
+  off = align_up(off + 2 * ns * sizeof(double));
+  L.eta = off;
+  off = align_up(off + ns * sizeof(double));
+  L.total = off;
+  return L;
+}
+struct AdjBufs {
+  double *Fp, *Lp, *aF1, *aL1, *Rb, *gb, *eta;
+};
+int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBufs* B) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(LB_E_ARG, "tau must be finite and > 0");
+  const double cfl = c->lat.vsum_max * dtau / c->p.dx_fm;
+  if (cfl > 0.5)
+    return fail(LB_E_ARG, "CFL number " + std::to_string(cfl) + " > 0.5 (reduce dtau or increase dx)");
+  const AdjLayout L = adj_layout(c->p);
+  if (!ws || ((uintptr_t)ws % kAlign) != 0 || bytes < L.total)
+    return fail(LB_E_ARG, "adjoint workspace NULL, not 256-byte aligned or smaller than lb_adjoint_workspace_bytes");
+  char* w = (char*)ws;
+  B->Fp = (double*)(w + L.Fp);
+  B->Lp = (double*)(w + L.Lp);
+  B->aF1 = (double*)(w + L.aF1);
+  B->aL1 = (double*)(w + L.aL1);
+  B->Rb = (double*)(w + L.Rb);
+  B->gb = (double*)(w + L.gb);
+  B->eta = (double*)(w + L.eta);
+  return LB_OK;
+}
+
 int read_err_word(int* d_err, hipStream_t stream) {
   int h = 0;
   hipError_t e = hipMemcpyAsync(&h, d_err, sizeof(int), hipMemcpyDeviceToHost, stream);
@@ -477,9 +528,72 @@ int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_f
   return LB_OK;
 }
 
-int lb_adjoint_step(lb_ctx* c, int32_t, const void*, void*, double*, double*) {
-  (void)c;
-  return fail(LB_E_NOTIMPL, "lb_adjoint_step is not implemented in this build");
+size_t lb_adjoint_workspace_bytes(const lb_params* p) {
+  g_err.clear();
+  const std::string m = validate(p);
+  if (!m.empty()) {
+    fail(LB_E_ARG, m);
+    return 0;
+  }
+  return adj_layout(*p).total;
+}
+
+int lb_adjoint_forward_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F, const double* d_lnM,
+                            double* d_F_out, double* d_lnM_out, void* d_adj_workspace, size_t adj_ws_bytes) {
+  AdjBufs B;
+  int rc = adj_check(c, tau_fm, dtau_fm, d_adj_workspace, adj_ws_bytes, &B);
+  if (rc != LB_OK) return rc;
+  if (!d_F || !d_lnM || !d_F_out || !d_lnM_out) return fail(LB_E_ARG, "state pointer is NULL");
+  StageArgs a = stage_args(c, tau_fm, dtau_fm);
+  hipError_t e =
+      launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->tb, a, c->err, c->stream);
+  if (e == hipSuccess) {
+    set_tau(&a, c, tau_fm + dtau_fm);
+    e = launch_adj_stage_fwd(B.Fp, B.Lp, d_F, d_lnM, d_F_out, d_lnM_out, 1, &c->cd, c->tb, a, c->err, c->stream);
+  }
+  return e == hipSuccess ? LB_OK : hip_fail(e, "adjoint forward step");
+}
+
+int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F, const double* d_lnM,
+                    double* d_adj_F, double* d_adj_lnM, double* d_grad_eta_over_s, void* d_adj_workspace,
+                    size_t adj_ws_bytes) {
+  AdjBufs B;
+  int rc = adj_check(c, tau_fm, dtau_fm, d_adj_workspace, adj_ws_bytes, &B);
+  if (rc != LB_OK) return rc;
+  if (!d_F || !d_lnM || !d_adj_F || !d_adj_lnM || !d_grad_eta_over_s)
+    return fail(LB_E_ARG, "state, adjoint or gradient pointer is NULL");
+  const size_t ns = (size_t)c->p.nx * c->p.ny, nF = ns * (size_t)(c->lat.nxi * c->lat.nth * 2 * c->lat.nphi);
+  const StageArgs a0 = stage_args(c, tau_fm, dtau_fm);
+  StageArgs a1 = a0;
+  set_tau(&a1, c, tau_fm + dtau_fm);
+  hipStream_t st = c->stream;
+  // predictor state F* = F + dtau K(F)
+  hipError_t e = launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->tb, a0, c->err, st);
+  // corrector F_new = (F + F*)/2 + dtau/2 K(F*): adjoint of F*, and F's share
+  if (e == hipSuccess)
+    e = launch_adj_rhs(B.Fp, B.Lp, d_adj_F, d_adj_lnM, 0.5 * dtau_fm, B.aF1, B.aL1, B.Rb, B.gb, B.eta, 0, &c->cd,
+                       c->tb, a1, c->err, st);
+  if (e == hipSuccess) e = launch_adj_axpy(B.aF1, d_adj_F, 0.5, d_adj_F, 0.5, nF, st);
+  if (e == hipSuccess) e = launch_adj_axpy(B.aL1, d_adj_lnM, 0.5, d_adj_lnM, 0.5, ns, st);
+  // predictor: F* = F + dtau K(F)
+  if (e == hipSuccess) e = launch_adj_axpy(d_adj_F, B.aF1, 1.0, nullptr, 1.0, nF, st);
+  if (e == hipSuccess) e = launch_adj_axpy(d_adj_lnM, B.aL1, 1.0, nullptr, 1.0, ns, st);
+  if (e == hipSuccess)
+    e = launch_adj_rhs(d_F, d_lnM, B.aF1, B.aL1, dtau_fm, d_adj_F, d_adj_lnM, B.Rb, B.gb, B.eta, 1, &c->cd, c->tb,
+                       a0, c->err, st);
+  if (e == hipSuccess) e = launch_adj_sum(B.eta, (int)ns, d_grad_eta_over_s, st);
+  return e == hipSuccess ? LB_OK : hip_fail(e, "adjoint step");
+}
+
+int lb_adjoint_init(lb_ctx* c, const double* d_e0, const double* d_ux0, const double* d_uy0,
+                    const double* d_adj_F, const double* d_adj_lnM, double* d_grad_e0) {
+  if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  if (!d_e0 || !d_adj_F || !d_adj_lnM || !d_grad_e0) return fail(LB_E_ARG, "pointer is NULL");
+  if ((d_ux0 == nullptr) != (d_uy0 == nullptr)) return fail(LB_E_ARG, "give both ux0 and uy0 or neither");
+  const StageArgs a = stage_args(c, c->p.tau0_fm, 0.0);
+  hipError_t e = launch_adj_init(d_e0, d_ux0, d_uy0, d_adj_F, d_adj_lnM, d_grad_e0, &c->cd, c->tb, a, c->err,
+                                 c->stream);
+  return e == hipSuccess ? LB_OK : hip_fail(e, "adjoint of the initial state");
 }
 
 int lb_status(lb_ctx* c) {

@@ -72,7 +72,20 @@ def test_calls_without_context():
     assert lb.lib.lb_moments(None, None) == lb.LB_E_STATE
     assert lb.lib.lb_status(None) == lb.LB_E_STATE
     assert lb.lib.lb_destroy(None) == lb.LB_OK
-    assert lb.lib.lb_adjoint_step(None, 0, None, None, None, None) == lb.LB_E_NOTIMPL
+    assert lb.lib.lb_adjoint_step(None, 0.5, 0.01, None, None, None, None, None, None, 0) == lb.LB_E_STATE
+    assert lb.lib.lb_adjoint_forward_step(None, 0.5, 0.01, None, None, None, None, None, 0) == lb.LB_E_STATE
+    assert lb.lib.lb_adjoint_init(None, None, None, None, None, None, None) == lb.LB_E_STATE
+
+
+def test_adjoint_workspace_size():
+    import ctypes
+    p = lb.make_params(12, 10, 0.2)
+    n = lb.lib.lb_adjoint_workspace_bytes(ctypes.byref(p))
+    # predictor state, its adjoint and R0_bar (3 x N x sites doubles), two
+    # per-site doubles, the gradient pair and the eta/s partials, 256-aligned
+    assert n >= (3 * 200 + 5) * 120 * 8 and n % 256 == 0
+    p.nx = 0
+    assert lb.lib.lb_adjoint_workspace_bytes(ctypes.byref(p)) == 0
 
 
 @pytest.mark.parametrize("z0", [1.0, 2.6])

@@ -1,0 +1,261 @@
+"""GPU tests of the differentiable form: the discrete adjoint of the FP64 Heun
+step (lb_adjoint_*), through the C ABI, against finite differences of the
+library's own forward step (lb_step) and of the FP64 oracle.
+
+Tolerances
+* lb_adjoint_forward_step vs lb_step (FP64): the same arithmetic in another
+  summation order and with exp instead of exp2: 1e-12 relative.
+* Dot-product test of one step, <a, (S(x + h d) - S(x - h d))/(2h)> against
+  <S'^T a, d> with relative perturbations d and h = 1e-6: central-difference
+  truncation O(h^2) and rounding ~1e-16/h relative, so 1e-7 relative.
+* Gradients of a run (FP64) against central differences with h = 1e-4
+  relative: truncation ~1e-8 relative, 1e-6 asserted; against the oracle's
+  central differences (h = 1e-4 relative; rounding of the objective, a
+  small difference, leaves ~2e-7): 1e-6 asserted (1e-5 for eta/s, whose
+  effect on a four-step run is ~1e-5 of the objective, with h = 1e-3).
+* The 128 x 128 hot-spot run with an FP32 forward: FP32 trajectory against
+  FP64 central differences (h = 1e-4), 1e-3 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1108_5561_amd as lb  # noqa: E402
+from oracle import step as st  # noqa: E402
+from oracle.eos import HBARC, TanhEntropyEoS  # noqa: E402
+from oracle.lattice import Lattice  # noqa: E402
+from paper_1108_5561_amd import workloads as wl  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def spots_e0(p, nx, ny, dx, seed, n_spots=6, width=0.4, mean_amplitude=20.0, T_floor=0.25):
+    """Hot spots on the floor eps_EoS(T_floor) (GeV/fm^3)."""
+    bg = lb.eos_eval(p, [T_floor])[0, 0] / HBARC ** 3
+    radius = 0.3 * min(nx, ny) * dx
+    return bg + wl.hot_spots(nx, ny, dx, n_spots=n_spots, width=width, disk_radius=radius,
+                             mean_amplitude=mean_amplitude, seed=seed)
+
+
+def lib_step(c, F, L, tau, dtau):
+    c.set_state(F.contiguous(), L.contiguous(), tau)
+    c.step(1, dtau)
+    F1, L1, _ = c.get_state()
+    return F1, L1
+
+
+def objective(p, F, lnM, tau_f, nodes):
+    """tau_f dx^2 sum_sites (T^{xx} - T^{yy}) in GeV/fm (B cancels)."""
+    w, _, vx, vy, _ = nodes
+    c = (w * (vx * vx - vy * vy))[:, None, None]
+    G = torch.exp(4.0 * lnM) / (2.0 * math.pi ** 2)
+    return tau_f * p.dx_fm ** 2 * (G * (c * F).sum(0)).sum() / HBARC ** 3
+
+
+def run_objective(p, e0, eta, n, dtau, nodes):
+    q = lb.make_params(p.nx, p.ny, p.dx_fm, tau0_fm=p.tau0_fm, eta_over_s=eta, precision=lb.LB_FP64,
+                       metric=p.metric)
+    c = lb.Context(q, e0)
+    c.step(n, dtau)
+    F, L, tau = c.get_state()
+    assert c.status() == lb.LB_OK
+    return float(objective(q, F, L, tau, nodes))
+
+
+@pytest.mark.parametrize("metric", [lb.LB_METRIC_MILNE, lb.LB_METRIC_MINKOWSKI])
+def test_forward_step_equals_lb_step(metric):
+    nx, ny, dx, dtau = 14, 11, 0.15, 0.01
+    p = lb.make_params(nx, ny, dx, eta_over_s=0.1, metric=metric)
+    ux, uy = wl.random_flow(nx, ny, 0.2, seed=3)
+    c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, 7)), gpu(ux), gpu(uy))
+    c.step(3, dtau)
+    F, L, tau = c.get_state()
+    ws = c.adjoint_workspace()
+    F1, L1 = c.adjoint_forward_step(tau, dtau, F, L, ws)
+    c.step(1, dtau)
+    F2, L2, _ = c.get_state()
+    assert float((F1 - F2).abs().max()) <= 1e-12 * float(F2.abs().max())
+    assert float((L1 - L2).abs().max()) <= 1e-12
+    assert c.status() == lb.LB_OK
+
+
+@pytest.mark.parametrize("metric,part", [(lb.LB_METRIC_MILNE, "F"), (lb.LB_METRIC_MILNE, "lnM"),
+                                         (lb.LB_METRIC_MINKOWSKI, "both")])
+def test_step_adjoint_dot_product(metric, part):
+    nx, ny, dx, dtau, eta = 12, 10, 0.15, 0.01, 0.12
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta, metric=metric)
+    ux, uy = wl.random_flow(nx, ny, 0.2, seed=5)
+    c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, 9)), gpu(ux), gpu(uy))
+    c.step(4, dtau)
+    F, L, tau = c.get_state()
+    rng = np.random.default_rng(21)
+    dF = F * gpu(rng.standard_normal(tuple(F.shape))) * (part != "lnM")
+    dL = gpu(rng.standard_normal(tuple(L.shape))) * (part != "F")
+    aF = gpu(rng.standard_normal(tuple(F.shape)))
+    aL = gpu(rng.standard_normal(tuple(L.shape)))
+    ws = c.adjoint_workspace()
+    bF, bL = aF.clone(), aL.clone()
+    g_eta = torch.zeros(1, dtype=torch.float64, device=DEV)
+    c.adjoint_step(tau, dtau, F, L, bF, bL, g_eta, ws)
+    lhs = float((bF * dF).sum() + (bL * dL).sum())
+    h = 1e-6
+    Fp, Lp = lib_step(c, F + h * dF, L + h * dL, tau, dtau)
+    Fm, Lm = lib_step(c, F - h * dF, L - h * dL, tau, dtau)
+    rhs = float(((aF * (Fp - Fm)).sum() + (aL * (Lp - Lm)).sum()) / (2 * h))
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs), (lhs, rhs)
+    # eta/s: the same step from contexts with eta (1 +- he)
+    he = 1e-5
+    out = []
+    for sgn in (1, -1):
+        q = lb.make_params(nx, ny, dx, eta_over_s=eta * (1 + sgn * he), metric=metric)
+        cq = lb.Context(q, gpu(spots_e0(p, nx, ny, dx, 9)))
+        out.append(lib_step(cq, F, L, tau, dtau))
+    fd = float(((aF * (out[0][0] - out[1][0])).sum() + (aL * (out[0][1] - out[1][1])).sum()) / (2 * he * eta))
+    assert abs(float(g_eta[0]) - fd) <= 1e-6 * abs(fd), (float(g_eta[0]), fd)
+    assert c.status() == lb.LB_OK
+
+
+def test_free_streaming_has_no_eta_gradient():
+    nx, ny, dx, dtau = 8, 8, 0.15, 0.01
+    p = lb.make_params(nx, ny, dx, eta_over_s=math.inf)
+    c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, 2)))
+    F, L, tau = c.get_state()
+    aF, aL = torch.ones_like(F), torch.ones_like(L)
+    g = torch.zeros(1, dtype=torch.float64, device=DEV)
+    c.adjoint_step(tau, dtau, F, L, aF, aL, g, c.adjoint_workspace())
+    assert float(g[0]) == 0.0
+    assert torch.isfinite(aF).all() and torch.isfinite(aL).all()
+
+
+def test_adjoint_argument_errors():
+    nx, ny, dx = 8, 8, 0.15
+    p = lb.make_params(nx, ny, dx)
+    c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, 2)))
+    F, L, tau = c.get_state()
+    ws = c.adjoint_workspace()
+    g = torch.zeros(1, dtype=torch.float64, device=DEV)
+    small = ws[: ws.numel() // 2]
+    with pytest.raises(lb.LbError) as ei:
+        c.adjoint_step(tau, 0.01, F, L, F.clone(), L.clone(), g, small)
+    assert ei.value.code == lb.LB_E_ARG
+    with pytest.raises(lb.LbError) as ei:
+        c.adjoint_step(tau, 0.5, F, L, F.clone(), L.clone(), g, ws)  # CFL
+    assert ei.value.code == lb.LB_E_ARG
+    with pytest.raises(lb.LbError) as ei:
+        c.adjoint_forward_step(-1.0, 0.01, F, L, ws)
+    assert ei.value.code == lb.LB_E_ARG
+    assert c.status() == lb.LB_OK
+
+
+def test_run_gradient_matches_central_differences():
+    nx = ny = 24
+    dx, dtau, n, eta = 0.12, 0.00375, 80, 0.16
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta)
+    nodes = lb.node_tensors(p, DEV)
+    e0n = spots_e0(p, nx, ny, dx, 5)
+    e0 = gpu(e0n).requires_grad_(True)
+    et = torch.tensor([eta], dtype=torch.float64, device=DEV, requires_grad=True)
+    F, L = lb.evolve(p, e0, et, n, dtau, checkpoint_every=30)
+    O = objective(p, F, L, p.tau0_fm + n * dtau, nodes)
+    O.backward()
+    g_e0, g_eta = e0.grad.detach(), float(et.grad[0])
+    h = 1e-4
+    fd_eta = (run_objective(p, gpu(e0n), eta * (1 + h), n, dtau, nodes) -
+              run_objective(p, gpu(e0n), eta * (1 - h), n, dtau, nodes)) / (2 * h * eta)
+    assert abs(g_eta - fd_eta) <= 1e-6 * abs(fd_eta), (g_eta, fd_eta)
+    rng = np.random.default_rng(8)
+    d = e0n * rng.standard_normal(e0n.shape)
+    fd_dir = (run_objective(p, gpu(e0n + h * d), eta, n, dtau, nodes) -
+              run_objective(p, gpu(e0n - h * d), eta, n, dtau, nodes)) / (2 * h)
+    ad_dir = float((g_e0 * gpu(d)).sum())
+    assert abs(ad_dir - fd_dir) <= 1e-6 * abs(fd_dir), (ad_dir, fd_dir)
+    # single sites: the hottest, a background one, one in between
+    flat = np.argsort(e0n.ravel())
+    for site in (flat[-1], flat[0], flat[len(flat) // 2]):
+        y, x = divmod(int(site), nx)
+        hs = h * e0n[y, x]
+        ep, em = e0n.copy(), e0n.copy()
+        ep[y, x] += hs
+        em[y, x] -= hs
+        fd = (run_objective(p, gpu(ep), eta, n, dtau, nodes) - run_objective(p, gpu(em), eta, n, dtau, nodes)) / (2 * hs)
+        assert abs(float(g_e0[y, x]) - fd) <= 1e-6 * abs(fd) + 1e-12 * abs(fd_dir), (site, float(g_e0[y, x]), fd)
+
+
+def _oracle_objective(lat, eos, e0, eta, nx, ny, dx, n, dtau, tau0=0.5):
+    F, L = st.init_state(lat, eos, e0)
+    prm = st.Params(dx=dx, eta_over_s=eta)
+    tau = tau0
+    for _ in range(n):
+        F, L = st.heun_step(lat, eos, prm, F, L, tau, dtau)
+        tau += dtau
+    Tk, _ = lat.moments(F, L)
+    return tau * dx * dx * float(np.sum(Tk[1, 1] - Tk[2, 2])) / HBARC ** 3
+
+
+def test_run_gradient_matches_oracle_central_differences():
+    nx, ny, dx, dtau, n, eta = 6, 5, 0.2, 0.01, 4, 0.12
+    lat, eos = Lattice(5, 5, 4, 1.0), TanhEntropyEoS()
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta)
+    nodes = lb.node_tensors(p, DEV)
+    e0n = float(eos.eps(0.3)) / HBARC ** 3 * (1.0 + 0.6 * wl.gaussian_shape(nx, ny, dx, 0.4)) * \
+        wl.white_noise_factor(nx, ny, 0.05, seed=13)
+    e0 = gpu(e0n).requires_grad_(True)
+    et = torch.tensor([eta], dtype=torch.float64, device=DEV, requires_grad=True)
+    F, L = lb.evolve(p, e0, et, n, dtau, checkpoint_every=3)
+    O = objective(p, F, L, p.tau0_fm + n * dtau, nodes)
+    O.backward()
+    O_or = _oracle_objective(lat, eos, e0n, eta, nx, ny, dx, n, dtau)
+    assert abs(float(O) - O_or) <= 1e-10 * abs(O_or)
+    # eta/s moves O by only ~1e-5 of itself over four steps: a wider step
+    # (truncation ~1e-7) keeps the rounding of the difference below 1e-8
+    he = 1e-3
+    fd_eta = (_oracle_objective(lat, eos, e0n, eta * (1 + he), nx, ny, dx, n, dtau) -
+              _oracle_objective(lat, eos, e0n, eta * (1 - he), nx, ny, dx, n, dtau)) / (2 * he * eta)
+    assert abs(float(et.grad[0]) - fd_eta) <= 1e-5 * abs(fd_eta), (float(et.grad[0]), fd_eta)
+    # O is a small difference (T^{xx} - T^{yy}): its rounding makes the
+    # central differences drift by ~2e-6 at h = 1e-5 and ~2e-7 at h = 1e-4
+    # (truncation there ~1e-8)
+    h = 1e-4
+    for (y, x) in ((2, 3), (0, 0), (4, 5)):
+        hs = h * e0n[y, x]
+        ep, em = e0n.copy(), e0n.copy()
+        ep[y, x] += hs
+        em[y, x] -= hs
+        fd = (_oracle_objective(lat, eos, ep, eta, nx, ny, dx, n, dtau) -
+              _oracle_objective(lat, eos, em, eta, nx, ny, dx, n, dtau)) / (2 * hs)
+        assert abs(float(e0.grad[y, x]) - fd) <= 1e-6 * abs(fd), ((y, x), float(e0.grad[y, x]), fd)
+
+
+def test_hot_spot_run_fp32_forward_gradient():
+    """128 x 128 hot spots, dx 0.12 fm, 600 steps of 0.00375 fm/c, eta/s
+    0.16, checkpoints every 50 steps: gradient of the FP32 run against FP64
+    central differences."""
+    nx = ny = 128
+    dx, dtau, n, eta = 0.12, 0.00375, 600, 0.16
+    p32 = lb.make_params(nx, ny, dx, eta_over_s=eta, precision=lb.LB_FP32_FP64MATCH)
+    p64 = lb.make_params(nx, ny, dx, eta_over_s=eta)
+    nodes = lb.node_tensors(p64, DEV)
+    bg = lb.eos_eval(p64, [0.25])[0, 0] / HBARC ** 3
+    e0n = bg + wl.hot_spots(nx, ny, dx, seed=5)
+    e0 = gpu(e0n).requires_grad_(True)
+    et = torch.tensor([eta], dtype=torch.float64, device=DEV, requires_grad=True)
+    F, L = lb.evolve(p32, e0, et, n, dtau, checkpoint_every=50)
+    O = objective(p64, F, L, p64.tau0_fm + n * dtau, nodes)
+    O.backward()
+    h = 1e-4
+    fd_eta = (run_objective(p64, gpu(e0n), eta * (1 + h), n, dtau, nodes) -
+              run_objective(p64, gpu(e0n), eta * (1 - h), n, dtau, nodes)) / (2 * h * eta)
+    assert abs(float(et.grad[0]) - fd_eta) <= 1e-3 * abs(fd_eta), (float(et.grad[0]), fd_eta)
+    d = e0n * np.random.default_rng(9).standard_normal(e0n.shape)
+    fd_dir = (run_objective(p64, gpu(e0n + h * d), eta, n, dtau, nodes) -
+              run_objective(p64, gpu(e0n - h * d), eta, n, dtau, nodes)) / (2 * h)
+    ad_dir = float((e0.grad * gpu(d)).sum())
+    assert abs(ad_dir - fd_dir) <= 1e-3 * abs(fd_dir), (ad_dir, fd_dir)

@@ -262,6 +262,5 @@ def test_error_paths(eos):
     assert ei.value.code == lb.LB_E_ARG
     with pytest.raises(lb.LbError):
         c.step(1, -0.01)
-    assert c.adjoint_step() == lb.LB_E_NOTIMPL
     c.step(0, 0.01)
     assert c.status() == lb.LB_OK
