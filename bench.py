@@ -132,6 +132,55 @@ def run_batch(lb, wl, torch, steps=96):
                         "eps_EoS(0.25 GeV), eta/s U[0.05, 0.3], dtau 0.00375 fm, graph replays of 48 steps"}
 
 
+def run_adjoint(lb, wl, torch):
+    """The differentiable form on the 128x128 hot-spot workload: FP32 forward
+    with checkpoints, adjoint backward, and the eta/s derivative against FP64
+    central differences (h = 1e-4)."""
+    import math
+    w = wl.WORKLOADS["adjoint"]
+    nx, ny, dx, n, dtau, eta = w["nx"], w["ny"], w["dx"], w["steps"], w["dtau"], w["eta_over_s"]
+    p32 = lb.make_params(nx, ny, dx, tau0_fm=w["tau0"], eta_over_s=eta, precision=lb.LB_FP32_FP64MATCH)
+    p64 = lb.make_params(nx, ny, dx, tau0_fm=w["tau0"], eta_over_s=eta)
+    nodes = lb.node_tensors(p64, "cuda:0")
+    c = (nodes[0] * (nodes[2] ** 2 - nodes[3] ** 2))[:, None, None]
+    tau_f = w["tau0"] + n * dtau
+
+    def objective(F, L):  # tau_f dx^2 sum (T^xx - T^yy), GeV/fm
+        return tau_f * dx * dx * (torch.exp(4.0 * L) / (2 * math.pi ** 2) * (c * F).sum(0)).sum() / lb.HBARC ** 3
+
+    # floor eps_EoS(0.25 GeV), as the batched workload
+    e0n = lb.eos_eval(p64, [0.25])[0, 0] / lb.HBARC ** 3 + wl.hot_spots(nx, ny, dx, seed=w["seed"])
+    e0 = torch.from_numpy(e0n).to("cuda:0").requires_grad_(True)
+    et = torch.tensor([eta], dtype=torch.float64, device="cuda:0", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F, L = lb.evolve(p32, e0, et, n, dtau, checkpoint_every=w["checkpoint_every"])
+    O = objective(F, L)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    O.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+
+    def run64(e, eta_):
+        q = lb.make_params(nx, ny, dx, tau0_fm=w["tau0"], eta_over_s=eta_)
+        ctx = lb.Context(q, torch.from_numpy(e).to("cuda:0"))
+        ctx.step(n, dtau)
+        Fq, Lq, _ = ctx.get_state()
+        return float(objective(Fq, Lq))
+
+    h = 1e-4
+    fd = (run64(e0n, eta * (1 + h)) - run64(e0n, eta * (1 - h))) / (2 * h * eta)
+    g = float(et.grad[0])
+    return {"workload": f"{nx}x{ny} hot spots (rng {w['seed']}) on eps_EoS(0.25 GeV), dx {dx} fm, eta/s {eta}, "
+                        f"{n} steps of {dtau} fm/c, FP32 forward, checkpoints every {w['checkpoint_every']} steps; "
+                        "objective tau_f dx^2 sum (T^xx - T^yy)",
+            "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "adjoint_ms_per_step": (t2 - t1) * 1e3 / n,
+            "dO_deta": g, "dO_deta_fd_fp64": fd, "rel_err": abs(g - fd) / abs(fd),
+            "e0_grad_norm": float(e0.grad.norm())}
+
+
 def tmunu_rel_err(a, b):
     """max over sites of ||dT^{mu nu}||_F / ||T^{mu nu}||_F (7 components)."""
     wts = np.array([1, 2, 2, 1, 2, 1, 1.0])[:, None, None]
@@ -213,6 +262,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-form measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -251,6 +301,7 @@ def main():
 
     parity = parity_fp32_vs_fp64(lb, wl, torch)
     batch = None if args.no_batch else run_batch(lb, wl, torch)
+    adjoint = None if args.no_adjoint else run_adjoint(lb, wl, torch)
 
     out = {
         "metric": "site-updates/s & HBM GB/s: FP32+FP64-match vs FP64 step at 1e-5 rel err",
@@ -275,6 +326,7 @@ def main():
         "fp32_vs_fp64_tmunu_rel_err": parity,
         "kernels_ms": {"pred": r32["pred_ms"], "corr": r32["corr_ms"]},
         "batched": batch if batch is None else dict(batch, vs_plain_fp64_step=batch["value"] / sups64),
+        "differentiable": adjoint,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

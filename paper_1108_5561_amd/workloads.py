@@ -16,6 +16,8 @@ Workloads (transverse grids of boost-invariant Milne runs):
           [0.05, 0.3] (default_rng(4), per event n_e then eta/s), box
           15.36 fm (dx = 15.36 / n_e), hot spots as `spots` with
           default_rng(4000 + e); tau 0.5 -> 8 fm/c, dtau = 0.00375 fm/c
+  adjoint 128 x 128, dx 0.12 fm, hot spots as `spots` with default_rng(5),
+          eta/s 0.16, 600 steps of 0.00375 fm/c, checkpoints every 50 steps
 The hot-spot workloads sit on a background floor the caller adds (the
 benchmark uses eps_EoS(0.25 GeV)).
 """
@@ -28,6 +30,8 @@ WORKLOADS = {
     "prec": dict(nx=256, ny=256, dx=0.025, tau0=0.5, tau1=8.0, steps=1000, eta_over_s=0.08),
     "spots": dict(nx=512, ny=512, dx=0.03, tau0=0.5, tau1=8.0, steps=2000, eta_over_s=0.16),
     "batch": dict(n_events=64, n_min=64, n_max=256, box=15.36, tau0=0.5, tau1=8.0, steps=2000),
+    "adjoint": dict(nx=128, ny=128, dx=0.12, tau0=0.5, steps=600, dtau=0.00375, eta_over_s=0.16,
+                    checkpoint_every=50, seed=5),
 }
 
 
