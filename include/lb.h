@@ -63,7 +63,7 @@ enum {
 enum { LB_FP64 = 0, LB_FP32_FP64MATCH = 1 };          /* storage / node arithmetic */
 enum { LB_TAUR_CE = 0, LB_TAUR_MASSLESS = 1 };        /* how tau_R follows eta/s */
 enum { LB_METRIC_MILNE = 0, LB_METRIC_MINKOWSKI = 1 };
-enum { LB_EOS_TANH_P = 0, LB_EOS_CONST_MASS = 1, LB_EOS_TANH_S = 2 };
+enum { LB_EOS_TANH_P = 0, LB_EOS_CONST_MASS = 1, LB_EOS_TANH_S = 2, LB_EOS_TABLE = 3 };
 
 /*
  * Problem statement (Sec. IV.D: an initial condition is the distribution plus
@@ -90,7 +90,8 @@ typedef struct lb_params {
                           EoS inversion and mass evolution */
   int32_t metric;      /* LB_METRIC_MILNE, or LB_METRIC_MINKOWSKI (no
                           Christoffel term; for tests) */
-  int32_t eos_kind;    /* LB_EOS_TANH_S: s/T^3 = (2 pi^2/45) g (1 + tanh((T - Tc)/w))/2,
+  int32_t eos_kind;    /* LB_EOS_TABLE: tabulated s(T) (fields eos_T_GeV .. eos_n below);
+                          LB_EOS_TANH_S: s/T^3 = (2 pi^2/45) g (1 + tanh((T - Tc)/w))/2,
                           p = int_0^T s dT' (c_s^2 in (0, 1/3] for any w);
                           LB_EOS_TANH_P: p/T^4 = (pi^2/90) g (1 + tanh((T - Tc)/w))/2
                           (c_s^2 > 1/3 above Tc; rejected where d eps/dT <= 0);
@@ -101,6 +102,18 @@ typedef struct lb_params {
   double eos_mass_GeV; /* mass of the constant-mass EoS */
   double T_min_GeV;    /* EoS table range; temperatures outside are an */
   double T_max_GeV;    /*   LB_E_EOS device error (typ. 0.05 and 3.0) */
+  /* LB_EOS_TABLE: the caller's entropy density (Sec. III.A takes s(T) as
+   * the input of the quasiparticle construction), host arrays read during
+   * the calls that take params.  s(T) between the points is the cubic
+   * spline with not-a-knot ends of ln(s/T^3) against ln T (twice
+   * continuously differentiable, so beta and c_s^2, which involve s', are
+   * continuous); p(T) = eos_p0 + the integral of s from eos_T[0];
+   * [T_min, T_max] must lie inside [eos_T[0], eos_T[n-1]].  Ignored for the
+   * other kinds (set to NULL / 0). */
+  const double* eos_T_GeV;  /* [eos_n] strictly increasing, > 0 */
+  const double* eos_s_GeV3; /* [eos_n] entropy density, > 0 */
+  double eos_p0_GeV4;       /* pressure at eos_T_GeV[0] */
+  int32_t eos_n;            /* >= 4 */
 } lb_params;
 
 /*

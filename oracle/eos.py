@@ -269,6 +269,48 @@ class TanhEntropyEoS(QuasiparticleEoS):
         return (self.cs * Tf ** 4 * v).reshape(T.shape)
 
 
+class TabulatedEoS(QuasiparticleEoS):
+    """The caller's entropy density s(T_i) as the input of the quasiparticle
+    construction (Sec. III.A builds M(T) and B(T) from s(T) and p(T)).
+
+    Between the points s(T) = T^3 exp(y(ln T)), y the cubic spline with
+    not-a-knot ends (scipy's CubicSpline, extended by its end cubics) of
+    ln(s_i/T_i^3) against ln T_i; ds/dT follows from the same cubic; p(T) =
+    p0 + int_{T_0}^T s dT' (adaptive quadrature in ln T).  The spline is
+    twice continuously differentiable, so beta and c_s^2, which involve s',
+    are continuous.
+    """
+
+    def __init__(self, T, s, p0, Z):
+        from scipy.interpolate import CubicSpline
+        T = np.asarray(T, dtype=float)
+        s = np.asarray(s, dtype=float)
+        self.T0, self.p0, self.Z = float(T[0]), float(p0), float(Z)
+        self._y = CubicSpline(np.log(T), np.log(s / T ** 3), bc_type="not-a-knot", extrapolate=True)
+        self._dy = self._y.derivative()
+
+    def s(self, T):
+        T = np.asarray(T, dtype=float)
+        return T ** 3 * np.exp(self._y(np.log(T)))
+
+    def ds(self, T):
+        T = np.asarray(T, dtype=float)
+        x = np.log(T)
+        return T ** 2 * np.exp(self._y(x)) * (3.0 + self._dy(x))
+
+    def p(self, T):
+        T = np.asarray(T, dtype=float)
+        b = np.log(np.atleast_1d(T).ravel())
+        a = np.log(self.T0)
+        # int_{T0}^{T} s dT' = int_a^b exp(4 x + y(x)) dx, x = a + t (b - a),
+        # each component divided by T s(T) (~ its size) so that the common
+        # error control of the vector quadrature is relative per component
+        scale = np.exp(b) * self.s(np.exp(b))
+        f = lambda t: (b - a) * np.exp(4.0 * (a + t * (b - a)) + self._y(a + t * (b - a))) / scale
+        v, _ = quad_vec(f, 0.0, 1.0, epsabs=0.0, epsrel=1e-14, limit=4000)
+        return (self.p0 + v * scale).reshape(T.shape)
+
+
 class ConstMassEoS(QuasiparticleEoS):
     """Boltzmann gas of constant mass M0 (Sec. II.A): B = 0, M(T) = M0."""
 

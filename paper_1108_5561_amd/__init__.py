@@ -21,7 +21,7 @@ LB_OK, LB_E_ARG, LB_E_HIP, LB_E_EOS, LB_E_MATCH, LB_E_NONFINITE, LB_E_STATE, LB_
 LB_FP64, LB_FP32_FP64MATCH = 0, 1
 LB_TAUR_CE, LB_TAUR_MASSLESS = 0, 1
 LB_METRIC_MILNE, LB_METRIC_MINKOWSKI = 0, 1
-LB_EOS_TANH_P, LB_EOS_CONST_MASS, LB_EOS_TANH_S = 0, 1, 2
+LB_EOS_TANH_P, LB_EOS_CONST_MASS, LB_EOS_TANH_S, LB_EOS_TABLE = 0, 1, 2, 3
 HBARC = 0.1973269804  # GeV fm
 N_OBS = 14
 OBS_NAMES = ("Ttt", "Ttx", "Tty", "Txx", "Txy", "Tyy", "TYY", "Nt", "Nx", "Ny", "T", "ux", "uy", "M")
@@ -46,6 +46,8 @@ class lb_params(ctypes.Structure):
         ("eos_kind", ctypes.c_int32),
         ("eos_g", ctypes.c_double), ("eos_Tc_GeV", ctypes.c_double), ("eos_width_GeV", ctypes.c_double),
         ("eos_mass_GeV", ctypes.c_double), ("T_min_GeV", ctypes.c_double), ("T_max_GeV", ctypes.c_double),
+        ("eos_T_GeV", ctypes.POINTER(ctypes.c_double)), ("eos_s_GeV3", ctypes.POINTER(ctypes.c_double)),
+        ("eos_p0_GeV4", ctypes.c_double), ("eos_n", ctypes.c_int32),
     ]
 
 
@@ -131,8 +133,20 @@ def degeneracy(kappa, g):
 def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, metric=LB_METRIC_MILNE,
                 taur_rule=LB_TAUR_CE, eos_kind=LB_EOS_TANH_S, eos_g=37.0, eos_Tc_GeV=0.17, eos_width_GeV=0.02,
                 eos_mass_GeV=0.0, kappa=2.0, Z=None, z0=1.0, n_xi=5, n_theta=5, n_phi=4,
-                T_min_GeV=0.05, T_max_GeV=3.0):
+                T_min_GeV=0.05, T_max_GeV=3.0, eos_table=None):
+    """Parameters of a run.  eos_table = (T [GeV], s [GeV^3], p(T[0]) [GeV^4])
+    selects LB_EOS_TABLE with the caller's entropy density (the arrays are
+    kept alive by the returned object)."""
     p = lb_params()
+    if eos_table is not None:
+        import numpy as np
+        Tt = np.ascontiguousarray(eos_table[0], dtype=np.float64)
+        st = np.ascontiguousarray(eos_table[1], dtype=np.float64)
+        dptr = ctypes.POINTER(ctypes.c_double)
+        p.eos_T_GeV, p.eos_s_GeV3 = Tt.ctypes.data_as(dptr), st.ctypes.data_as(dptr)
+        p.eos_p0_GeV4, p.eos_n = float(eos_table[2]), int(Tt.size)
+        p._eos_keep = (Tt, st)
+        eos_kind = LB_EOS_TABLE
     p.n_xi, p.n_theta, p.n_phi, p.z0 = n_xi, n_theta, n_phi, z0
     p.Z = degeneracy(kappa, eos_g) if Z is None else Z
     p.nx, p.ny, p.dx_fm, p.tau0_fm, p.eta_over_s = nx, ny, dx_fm, tau0_fm, eta_over_s

@@ -284,9 +284,96 @@ HostEos::HostEos(const lb_params& p)
     : kind_(p.eos_kind), Z_(p.Z), g_(p.eos_g), Tc_(p.eos_Tc_GeV), w_(p.eos_width_GeV),
       m0_(p.eos_mass_GeV), taur_rule_(p.taur_rule) {
   c_ = kPi * kPi / 90.0 * g_;
+  if (kind_ != LB_EOS_TABLE) return;
+  // cubic spline of y = ln(s/T^3) on x = ln T with not-a-knot ends (the
+  // third derivative is continuous at the second and the second-to-last
+  // points): second derivatives sigma from the tridiagonal system that
+  // remains after the two end conditions are eliminated
+  const int n = p.eos_n;
+  tx_.resize(n);
+  ty_.resize(n);
+  td_.assign(n, 0.0);
+  tp_.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const double T = p.eos_T_GeV[i];
+    tx_[i] = std::log(T);
+    ty_[i] = std::log(p.eos_s_GeV3[i] / (T * T * T));
+  }
+  std::vector<double> h(n - 1), dl(n - 1);
+  for (int k = 0; k + 1 < n; ++k) {
+    h[k] = tx_[k + 1] - tx_[k];
+    dl[k] = (ty_[k + 1] - ty_[k]) / h[k];
+  }
+  // rows i = 1 .. n-2: h_{i-1} s_{i-1} + 2 (h_{i-1} + h_i) s_i + h_i s_{i+1} = 6 (dl_i - dl_{i-1})
+  const int m = n - 2;
+  std::vector<double> a(m, 0.0), b(m, 0.0), c(m, 0.0), r(m, 0.0);
+  for (int i = 1; i <= m; ++i) {
+    a[i - 1] = h[i - 1];
+    b[i - 1] = 2 * (h[i - 1] + h[i]);
+    c[i - 1] = h[i];
+    r[i - 1] = 6 * (dl[i] - dl[i - 1]);
+  }
+  // left: s_0 = ((h0 + h1) s_1 - h0 s_2) / h1; right likewise
+  {
+    const double h0 = h[0], h1 = h[1];
+    b[0] += a[0] * (h0 + h1) / h1;
+    c[0] -= a[0] * h0 / h1;
+    a[0] = 0;
+    const double hA = h[n - 2], hB = h[n - 3];  // last and second-to-last intervals
+    b[m - 1] += c[m - 1] * (hA + hB) / hB;
+    a[m - 1] -= c[m - 1] * hA / hB;
+    c[m - 1] = 0;
+  }
+  for (int i = 1; i < m; ++i) {  // forward elimination (diagonally dominant)
+    const double f = a[i] / b[i - 1];
+    b[i] -= f * c[i - 1];
+    r[i] -= f * r[i - 1];
+  }
+  std::vector<double> sg(n, 0.0);
+  sg[m] = r[m - 1] / b[m - 1];
+  for (int i = m - 2; i >= 0; --i) sg[i + 1] = (r[i] - c[i] * sg[i + 2]) / b[i];
+  sg[0] = ((h[0] + h[1]) * sg[1] - h[0] * sg[2]) / h[1];
+  sg[n - 1] = ((h[n - 2] + h[n - 3]) * sg[n - 2] - h[n - 2] * sg[n - 3]) / h[n - 3];
+  td_ = sg;
+  tp_[0] = p.eos_p0_GeV4;
+  for (int k = 0; k + 1 < n; ++k) tp_[k + 1] = tp_[k] + tab_s_integral(k, std::exp(tx_[k + 1]));
+}
+
+int HostEos::tab_interval(double x) const {
+  const int n = (int)tx_.size();
+  int k = (int)(std::upper_bound(tx_.begin(), tx_.end(), x) - tx_.begin()) - 1;
+  return std::max(0, std::min(n - 2, k));  // the end cubics extend outside
+}
+
+double HostEos::tab_y(double x, double* dy) const {
+  const int k = tab_interval(x);
+  const double h = tx_[k + 1] - tx_[k], t = x - tx_[k];
+  const double s0 = td_[k], s1 = td_[k + 1];
+  const double bb = (ty_[k + 1] - ty_[k]) / h - h * (2 * s0 + s1) / 6, cc = 0.5 * s0, dd = (s1 - s0) / (6 * h);
+  if (dy) *dy = bb + t * (2 * cc + 3 * dd * t);
+  return ty_[k] + t * (bb + t * (cc + dd * t));
+}
+
+// int_{T_k}^{T} s dT' = int exp(4 x + y(x)) dx over [x_k, ln T], 16-point
+// Gauss-Legendre (the integrand is smooth on one interpolation interval)
+double HostEos::tab_s_integral(int k, double T) const {
+  static std::vector<ld> gx, gw;
+  static std::once_flag once;
+  std::call_once(once, [] { gauss_legendre(16, &gx, &gw); });
+  const double a = tx_[k], b = std::log(T);
+  double sum = 0;
+  for (int i = 0; i < 16; ++i) {
+    const double x = 0.5 * (a + b) + 0.5 * (b - a) * (double)gx[i];
+    sum += (double)gw[i] * std::exp(4 * x + tab_y(x, nullptr));
+  }
+  return 0.5 * (b - a) * sum;
 }
 
 double HostEos::p(double T) const {
+  if (kind_ == LB_EOS_TABLE) {
+    const int k = tab_interval(std::log(T));
+    return tp_[k] + tab_s_integral(k, T);
+  }
   if (kind_ == LB_EOS_CONST_MASS) {
     double z = m0_ / T;
     return Z_ * m0_ * m0_ * T * T * std::cyl_bessel_k(2.0, z) / (2 * kPi * kPi);
@@ -319,6 +406,7 @@ double HostEos::p(double T) const {
 }
 
 double HostEos::s(double T) const {
+  if (kind_ == LB_EOS_TABLE) return T * T * T * std::exp(tab_y(std::log(T), nullptr));
   if (kind_ == LB_EOS_CONST_MASS) {
     double z = m0_ / T;
     return Z_ * m0_ * m0_ * m0_ * std::cyl_bessel_k(3.0, z) / (2 * kPi * kPi);
@@ -330,6 +418,11 @@ double HostEos::s(double T) const {
 }
 
 double HostEos::ds(double T) const {
+  if (kind_ == LB_EOS_TABLE) {
+    double dy;
+    const double y = tab_y(std::log(T), &dy);
+    return T * T * std::exp(y) * (3 + dy);  // d/dT [T^3 e^y] with dy/dx, x = ln T
+  }
   if (kind_ == LB_EOS_CONST_MASS) {
     double z = m0_ / T;
     // d/dT K_3(m/T) = K_3'(z)(-m/T^2), K_3' = -K_2 - 3 K_3/z
@@ -451,7 +544,8 @@ std::string build_tables(const lb_params& p, HostTables* out) {
   key.m0 = p.eos_mass_GeV;
   key.tmin = p.T_min_GeV;
   key.tmax = p.T_max_GeV;
-  {
+  const bool cacheable = p.eos_kind != LB_EOS_TABLE;  // a caller's table is not keyed
+  if (cacheable) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     if (g_cache_valid && g_cache_key == key) {
       *out = g_cache;
@@ -544,7 +638,7 @@ std::string build_tables(const lb_params& p, HostTables* out) {
   D.ge_inv_h = 1.0 / D.ge_h;
   D.inv_ek = T.inv_ek.data();
   D.inv_ee = T.inv_ee.data();
-  {
+  if (cacheable) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     g_cache = T;
     g_cache.desc.pts = g_cache.pts.data();

@@ -39,6 +39,12 @@ class HostEos {
   double Z() const { return Z_; }
 
  private:
+  // tabulated s(T): y = ln(s/T^3) on x = ln T, the spline's second
+  // derivatives, and p at the knots (p0 + the integral of s)
+  std::vector<double> tx_, ty_, td_, tp_;
+  int tab_interval(double x) const;
+  double tab_y(double x, double* dy) const;
+  double tab_s_integral(int k, double T) const;  // int_{T_k}^{T} s dT'
   int kind_;
   double Z_, g_, Tc_, w_, m0_, c_;
   int taur_rule_;

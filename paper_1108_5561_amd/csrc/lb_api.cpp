@@ -85,6 +85,17 @@ std::string validate(const lb_params* p) {
       return "tanh EoS needs g > 0, width > 0, finite Tc";
   } else if (p->eos_kind == LB_EOS_CONST_MASS) {
     if (!(p->eos_mass_GeV > 0) || !std::isfinite(p->eos_mass_GeV)) return "constant-mass EoS needs mass > 0";
+  } else if (p->eos_kind == LB_EOS_TABLE) {
+    if (!p->eos_T_GeV || !p->eos_s_GeV3 || p->eos_n < 4) return "tabulated EoS needs eos_T, eos_s and eos_n >= 4";
+    for (int i = 0; i < p->eos_n; ++i) {
+      if (!(p->eos_T_GeV[i] > 0) || !std::isfinite(p->eos_T_GeV[i]) || !(p->eos_s_GeV3[i] > 0) ||
+          !std::isfinite(p->eos_s_GeV3[i]))
+        return "tabulated EoS: T and s must be finite and > 0";
+      if (i > 0 && !(p->eos_T_GeV[i] > p->eos_T_GeV[i - 1])) return "tabulated EoS: T must increase strictly";
+    }
+    if (!std::isfinite(p->eos_p0_GeV4)) return "tabulated EoS: eos_p0 must be finite";
+    if (!(p->T_min_GeV >= p->eos_T_GeV[0]) || !(p->T_max_GeV <= p->eos_T_GeV[p->eos_n - 1]))
+      return "tabulated EoS: [T_min, T_max] must lie inside the table";
   } else {
     return "unknown eos_kind";
   }

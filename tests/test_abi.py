@@ -164,3 +164,68 @@ def test_const_mass_eos():
     e = ConstMassEoS(3.0, 0.4)
     assert np.allclose(out[:, 0], e.eps(T), rtol=1e-13)
     assert np.allclose(out[:, 3], 0.4) and np.all(out[:, 4] == 0) and np.all(out[:, 6] == 0)
+
+
+def _tanh_table(n=1200):
+    e = TanhEntropyEoS()
+    T = np.exp(np.linspace(np.log(0.04), np.log(3.5), n))
+    return e, (T, e.s(T), float(e.p(T[:1])[0]))
+
+
+def test_host_tabulated_eos_matches_oracle():
+    from oracle.eos import TabulatedEoS
+    e, tab = _tanh_table()
+    p = lb.make_params(8, 8, 0.2, eta_over_s=0.1, eos_table=tab)
+    o = TabulatedEoS(*tab, Z=p.Z)
+    T = np.array([0.06, 0.12, 0.17, 0.2, 0.35, 1.0, 2.9])
+    out = lb.eos_eval(p, T)
+    ref = [o.eps(T), o.p(T), o.s(T), o.M(T), o.B(T), o.eps_kin_eq(T), o.beta(T), o.tau_R(T, 0.1)]
+    for i, r in enumerate(ref):
+        scale = np.maximum(np.abs(r), 1e-300)
+        if i == 4:
+            scale = np.maximum(np.abs(r), 1e-12 * o.p(T))
+        assert np.all(np.abs(out[:, i] - r) <= 1e-10 * scale), (i, out[:, i], r)
+    # and it is the closed-form EoS to the interpolation error (1200 points)
+    ex = lb.eos_eval(lb.make_params(8, 8, 0.2, eta_over_s=0.1), T)
+    assert np.max(np.abs(out[:, :4] / ex[:, :4] - 1)) < 1e-6
+
+
+@pytest.mark.parametrize("b", [0.0, 0.6])
+def test_host_tabulated_power_law_is_exact(b):
+    # the host's spline reproduces ln(s/T^3) linear in ln T exactly
+    A, p0 = 10.0, 2e-5  # 2 pi^2 s/(Z T^3) < 8 on the queried range: M exists
+    T = np.exp(np.linspace(np.log(0.04), np.log(3.5), 30))
+    p = lb.make_params(8, 8, 0.2, Z=60.0, eos_table=(T, A * T ** (3 + b), p0))
+    Tq = np.array([0.055, 0.21, 0.77, 3.3])
+    out = lb.eos_eval(p, Tq)
+    assert np.allclose(out[:, 2], A * Tq ** (3 + b), rtol=1e-13, atol=0)
+    assert np.allclose(out[:, 1], p0 + A * (Tq ** (4 + b) - T[0] ** (4 + b)) / (4 + b), rtol=1e-12, atol=0)
+
+
+def test_tabulated_eos_validation():
+    import ctypes
+    T = np.exp(np.linspace(np.log(0.04), np.log(3.5), 20))
+    s = 10 * T ** 3
+    bad = [
+        (T[::-1].copy(), s),                     # not increasing
+        (T, -s),                                 # s <= 0
+        (T[5:], s[5:]),                          # does not cover T_min = 0.05
+    ]
+    for Tt, st in bad:
+        p = lb.make_params(8, 8, 0.2, Z=60.0, eos_table=(Tt, st, 1e-5))
+        assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) == 0
+    p = lb.make_params(8, 8, 0.2, Z=60.0, eos_table=(T[:3], s[:3], 1e-5))
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) == 0   # fewer than 4 points
+
+
+def test_host_tabulated_cubic_in_log_t_is_exact():
+    # the host spline (its own tridiagonal solve) is exact on a cubic in ln T
+    rng = np.random.default_rng(4)
+    x = np.sort(rng.uniform(np.log(0.04), np.log(3.5), 25))
+    x[0], x[-1] = np.log(0.04), np.log(3.5)
+    y = lambda x: 0.5 + 0.3 * x - 0.2 * x ** 2 + 0.05 * x ** 3
+    T = np.exp(x)
+    p = lb.make_params(8, 8, 0.2, Z=60.0, eos_table=(T, T ** 3 * np.exp(y(x)), 1e-4))
+    xq = np.array([-2.9, -1.7, -0.3, 0.9])
+    out = lb.eos_eval(p, np.exp(xq))
+    assert np.allclose(out[:, 2], np.exp(3 * xq + y(xq)), rtol=1e-12, atol=0)

@@ -264,3 +264,36 @@ def test_error_paths(eos):
         c.step(1, -0.01)
     c.step(0, 0.01)
     assert c.status() == lb.LB_OK
+
+
+@pytest.mark.parametrize("precision", [lb.LB_FP64, lb.LB_FP32_FP64MATCH])
+def test_tabulated_eos_run_matches_oracle(lat, precision):
+    # the caller's s(T) table (here sampled from the closed-form entropy EoS
+    # at 400 points): both sides interpolate it with the same spline; the
+    # device tables built from it are accurate to ~1e-12 (beta 5e-10)
+    from oracle.eos import TabulatedEoS
+    ref = TanhEntropyEoS()
+    T = np.exp(np.linspace(np.log(0.04), np.log(3.5), 400))
+    tab = (T, ref.s(T), float(ref.p(T[:1])[0]))
+    nx, ny, dx, dtau, eta = 16, 12, 0.2, 0.01, 0.1
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta, precision=precision, eos_table=tab)
+    eos = TabulatedEoS(*tab, Z=p.Z)
+    e0 = gaussian_e0(eos, nx, ny, dx, width=0.25 * nx * dx)
+    ux, uy = wl.random_flow(nx, ny, 0.15, seed=31)
+    F, l = st.init_state(lat, eos, e0, ux, uy)
+    c = lb.Context(p, gpu(e0), gpu(ux), gpu(uy))
+    Fg, lg, _ = c.get_state()
+    # FP32: the node constants (gamma, |v_perp|) are FP32 in the exponent
+    # u.P/T (up to ~50 at the largest xi): ~3e-6 relative
+    tol_init = 1e-11 if precision == lb.LB_FP64 else 1e-5
+    assert np.max(np.abs(cpu(Fg) - F)) < tol_init * F.max()
+    assert np.max(np.abs(cpu(lg) - l)) < 1e-12
+    prm = st.Params(dx=dx, eta_over_s=eta)
+    tau = 0.5
+    for _ in range(5):
+        F, l = st.heun_step(lat, eos, prm, F, l, tau, dtau)
+        tau += dtau
+    c.step(5, dtau)
+    assert c.status() == lb.LB_OK
+    err = tmunu_rel_err(cpu(c.moments()), st.observables(lat, eos, prm, F, l))
+    assert err < (1e-10 if precision == lb.LB_FP64 else 1e-5), err

@@ -147,3 +147,74 @@ def test_inversions():
     Tg = np.linspace(Tr + 1e-6, 3.0, 20000)
     assert np.all(e2.eps(Tg) > target)
     assert Tr > 0.196
+
+
+# ---- tabulated entropy density (the caller's s(T), Sec. III.A) ----
+
+def _power_table(b, A=5.0, T0=0.05, T1=3.2, n=40):
+    T = np.exp(np.linspace(np.log(T0), np.log(T1), n))
+    return T, A * T ** (3 + b)
+
+
+@pytest.mark.parametrize("b", [0.0, -0.4, 0.7])
+def test_tabulated_power_law_is_exact(b):
+    # ln(s/T^3) = ln A + b ln T is linear in ln T, which the cubic spline
+    # reproduces exactly, so s, s' and p = p0 + A (T^{4+b} - T0^{4+b})/(4+b)
+    # hold off the knots
+    from oracle.eos import TabulatedEoS
+    A = 5.0
+    T, s = _power_table(b, A)
+    p0 = 0.01
+    e = TabulatedEoS(T, s, p0, Z=20.0)
+    Tq = np.array([0.051, 0.0777, 0.19, 0.333, 1.7, 3.1])
+    assert np.allclose(e.s(Tq), A * Tq ** (3 + b), rtol=1e-13, atol=0)
+    assert np.allclose(e.ds(Tq), (3 + b) * A * Tq ** (2 + b), rtol=1e-12, atol=0)
+    p_exact = p0 + A * (Tq ** (4 + b) - T[0] ** (4 + b)) / (4 + b)
+    assert np.allclose(e.p(Tq), p_exact, rtol=1e-12, atol=0)
+
+
+def test_tabulated_cubic_in_log_t_is_exact():
+    # a not-a-knot spline is exact on cubics: ln(s/T^3) = c0 + c1 x + c2 x^2
+    # + c3 x^3 (x = ln T) on unevenly spaced points
+    from oracle.eos import TabulatedEoS
+    rng = np.random.default_rng(3)
+    x = np.sort(rng.uniform(np.log(0.04), np.log(3.5), 30))
+    x[0], x[-1] = np.log(0.04), np.log(3.5)
+    y = lambda x: 1.0 + 0.3 * x - 0.2 * x ** 2 + 0.05 * x ** 3
+    dy = lambda x: 0.3 - 0.4 * x + 0.15 * x ** 2
+    T = np.exp(x)
+    e = TabulatedEoS(T, T ** 3 * np.exp(y(x)), 1e-4, Z=40.0)
+    xq = np.array([-3.1, -2.0, -0.5, 0.4, 1.2])
+    Tq = np.exp(xq)
+    assert np.allclose(e.s(Tq), Tq ** 3 * np.exp(y(xq)), rtol=1e-12, atol=0)
+    assert np.allclose(e.ds(Tq), Tq ** 2 * np.exp(y(xq)) * (3 + dy(xq)), rtol=1e-11, atol=0)
+
+
+def test_tabulated_conformal_gas_has_constant_mass_ratio():
+    # s = A T^3 with p = A T^4 / 4: every temperature is the same state in
+    # units of T, so z = M/T and B/T^4 are constants
+    from oracle.eos import TabulatedEoS
+    T, s = _power_table(0.0, A=20.0)
+    e = TabulatedEoS(T, s, 20.0 * T[0] ** 4 / 4, Z=60.0)  # 2 pi^2 s/(Z T^3) = 6.6 < 8: M exists
+    Tq = np.array([0.07, 0.2, 0.9, 2.5])
+    z = e.z_of_T(Tq)
+    assert np.max(np.abs(z / z[0] - 1)) < 1e-12
+    bt4 = e.B(Tq) / Tq ** 4
+    assert np.max(np.abs(bt4 - bt4[0])) < 1e-12 * np.max(e.p(Tq) / Tq ** 4)
+
+
+def test_tabulated_tanh_converges_at_fourth_order():
+    # the cubic spline of a smooth function converges like h^4; halving the
+    # spacing of a table of the closed-form entropy EoS cuts the error of s
+    # and M at least 12x
+    from oracle.eos import TabulatedEoS
+    ref = TanhEntropyEoS()
+    Tq = np.exp(np.linspace(np.log(0.06), np.log(2.8), 97))
+    errs = []
+    for n in (150, 300, 600):
+        T = np.exp(np.linspace(np.log(0.04), np.log(3.5), n))
+        e = TabulatedEoS(T, ref.s(T), float(ref.p(T[:1])[0]), ref.Z)
+        errs.append((np.max(np.abs(e.s(Tq) / ref.s(Tq) - 1)), np.max(np.abs(e.M(Tq) / ref.M(Tq) - 1))))
+    for i in (0, 1):
+        assert errs[0][i] / errs[1][i] > 12 and errs[1][i] / errs[2][i] > 12, errs
+    assert errs[2][0] < 1e-6
