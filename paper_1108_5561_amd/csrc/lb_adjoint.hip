@@ -269,7 +269,9 @@ __global__ __launch_bounds__(kAdjThreads) void adj_fwd_kernel(const double* __re
 // (outF, outL) and the site's eta/s adjoint into eta_part; writes R0_bar
 // (for the transposed streaming) into Rb and the ln M gradient adjoint into
 // gb[2][site].
-__global__ __launch_bounds__(kAdjThreads) void adj_local_kernel(
+// (seven 25-value slice arrays per thread: one wave per SIMD, so that the
+// compiler may use the whole register file rather than scratch)
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void adj_local_kernel(
     const double* __restrict__ F, const double* __restrict__ Lm, const double* __restrict__ seedF,
     const double* __restrict__ seedL, double scale, double* __restrict__ outF, double* __restrict__ outL,
     double* __restrict__ Rb, double* __restrict__ gb, double* __restrict__ eta_part, int accumulate,
