@@ -125,8 +125,9 @@ def run_batch(lb, wl, torch, steps=96):
     return {"value": steps * sites / (ms / 1e3), "unit": "site-updates/s", "ms_per_step": ms / steps,
             "events": len(events), "sites": sites, "steps": steps, "dtype": "f32",
             "algorithmic_GBps_step": (site_bytes("fp32", 0) + site_bytes("fp32", 1)) * sites * steps / (ms / 1e3) / 1e9,
-            "kernel_variant": variant, "tile_rows": [2, 4, 8, 2, 4, 8][variant],
-            "waves_per_simd_target": 4 if variant < 3 else 3,
+            "kernel_variant": variant, "tile_rows": [2, 4, 8][variant % 3],
+            "waves_per_simd_target": 4 if (variant // 3) % 2 == 0 else 3,
+            "streaming_stores": variant >= 6,
             "variant_ms_per_step": ms_variants,
             "workload": "64 events, side U{64..256} (rng 4), box 15.36 fm, 40 hot spots each (rng 4000+e) on "
                         "eps_EoS(0.25 GeV), eta/s U[0.05, 0.3], dtau 0.00375 fm, graph replays of 48 steps"}

@@ -315,14 +315,17 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
                   void* d_workspace, size_t ws_bytes, const double* const* d_e0, void* hip_stream);
 
 /* Time every variant of the batched stage kernel (tile rows 2, 4, 8; in
- * FP32 with 4 or 3 waves per SIMD as occupancy target) on the batch's own
- * events for a few steps of size dtau_fm, on the spare state buffers (the
- * state is unchanged), and keep the fastest.  variant_out (may be NULL)
- * receives its index; ms_out (may be NULL) the mean milliseconds per step
- * of each variant ([6] in FP32, [3] in FP64).  Synchronous. */
+ * FP32 with 4 or 3 waves per SIMD as occupancy target, with or without
+ * streaming stores of the new state: variant v has kBatchTileRows
+ * 2, 4, 8 for v % 3, 4 waves for (v / 3) % 2 == 0 else 3, streaming for
+ * v >= 6) on the batch's own events for a few steps of size dtau_fm, on
+ * the spare state buffers (the state is unchanged), and keep the fastest.
+ * variant_out (may be NULL) receives its index; ms_out (may be NULL) the
+ * mean milliseconds per step of each variant ([12] in FP32, [3] in FP64).
+ * Synchronous. */
 int lb_batch_tune(lb_batch* b, double dtau_fm, int32_t* variant_out, double* ms_out);
 
-/* Use kernel variant `variant` (0..5 in FP32, 0..2 in FP64, numbered as in
+/* Use kernel variant `variant` (0..11 in FP32, 0..2 in FP64, numbered as in
  * lb_batch_tune) without timing: pins a tuned choice. */
 int lb_batch_set_variant(lb_batch* b, int32_t variant);
 

@@ -56,10 +56,11 @@ struct StageTime {
 };
 // Variants of the batched stage kernel (the tuning choices): variant v has
 // kBatchTileRows[v % 3] tile rows (tiles are 8 sites wide) and, in FP32,
-// 4 (v < 3) or 3 (v >= 3) waves per SIMD as occupancy target; FP64 has
+// 4 ((v / 3) % 2 = 0) or 3 waves per SIMD as occupancy target, with
+// streaming (nontemporal) stores of the new state for v >= 6; FP64 has
 // variants 0..2 at 2 waves per SIMD.
 constexpr int kBatchTileRows[3] = {2, 4, 8};
-inline int batch_variants(int precision) { return precision == 1 ? 6 : 3; }
+inline int batch_variants(int precision) { return precision == 1 ? 12 : 3; }
 inline int batch_tile_rows(int variant) { return kBatchTileRows[variant % 3]; }
 inline int batch_tiles(int nx, int ny, int tile_rows) { return ((nx + 7) / 8) * ((ny + tile_rows - 1) / tile_rows); }
 

@@ -49,7 +49,7 @@ def test_batch_equals_single_contexts_every_variant(precision):
     p, e0s = _setup(precision)
     n1, n2 = 50, 47   # 48 + 2 direct steps, then 1 + 46 direct (rotation not at 0)
     ref = _single(precision, e0s, n1 + n2)
-    nvar = 6 if precision == lb.LB_FP32_FP64MATCH else 3
+    nvar = 12 if precision == lb.LB_FP32_FP64MATCH else 3
     for v in range(nvar):
         b = lb.Batch(p, EVENTS, e0s)
         b.set_variant(v)
@@ -85,7 +85,7 @@ def test_batch_tune_and_errors():
     p, e0s = _setup(lb.LB_FP32_FP64MATCH)
     b = lb.Batch(p, EVENTS, e0s)
     v, ms = b.tune(DTAU)
-    assert 0 <= v < 6 and len(ms) == 6 and all(m > 0 for m in ms) and ms[v] == min(ms)
+    assert 0 <= v < 12 and len(ms) == 12 and all(m > 0 for m in ms) and ms[v] == min(ms)
     F0, l0, t0 = b.get_state(2)
     F1, l1, t1 = b.get_state(2)
     assert t0 == t1 and torch.equal(F0, F1)   # tuning left the state alone
@@ -95,5 +95,24 @@ def test_batch_tune_and_errors():
     with pytest.raises(lb.LbError):
         b.get_state(len(EVENTS))
     with pytest.raises(lb.LbError):
-        b.set_variant(6)
+        b.set_variant(12)
     assert b.status() == lb.LB_OK
+
+
+def test_large_grid_mode_equals_cached_tiles():
+    """A state above the last-level-cache threshold (3 x 800 B x sites >
+    192 MiB) runs lb_step with 8-row tiles and streaming stores; its result
+    equals the batched kernel's 4-row cached variant bit for bit."""
+    nx, ny, dx = 320, 304, 0.05
+    p = lb.make_params(nx, ny, dx, precision=lb.LB_FP32_FP64MATCH, eta_over_s=0.12)
+    bg = lb.eos_eval(p, [0.25])[0, 0] / lb.HBARC ** 3
+    e0 = torch.from_numpy(bg + wl.hot_spots(nx, ny, dx, n_spots=8, width=0.6, disk_radius=4.0, seed=41)).to(DEV)
+    c = lb.Context(p, e0)
+    c.step(3, DTAU)
+    F, l, t = c.get_state()
+    b = lb.Batch(p, [(nx, ny, dx, 0.12)], [e0])
+    b.set_variant(1)
+    b.step(3, DTAU)
+    Fb, lb_, tb = b.get_state(0)
+    assert tb == t and torch.equal(Fb, F) and torch.equal(lb_, l)
+    assert c.status() == lb.LB_OK and b.status() == lb.LB_OK
