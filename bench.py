@@ -173,11 +173,13 @@ def run_adjoint(lb, wl, torch):
     h = 1e-4
     fd = (run64(e0n, eta * (1 + h)) - run64(e0n, eta * (1 - h))) / (2 * h * eta)
     g = float(et.grad[0])
+    sites_steps = nx * ny * n
     return {"workload": f"{nx}x{ny} hot spots (rng {w['seed']}) on eps_EoS(0.25 GeV), dx {dx} fm, eta/s {eta}, "
                         f"{n} steps of {dtau} fm/c, FP32 forward, checkpoints every {w['checkpoint_every']} steps; "
                         "objective tau_f dx^2 sum (T^xx - T^yy)",
             "forward_s": t1 - t0, "backward_s": t2 - t1,
             "adjoint_ms_per_step": (t2 - t1) * 1e3 / n,
+            "gradient_site_updates_per_s": sites_steps / ((t1 - t0) + (t2 - t1)),
             "dO_deta": g, "dO_deta_fd_fp64": fd, "rel_err": abs(g - fd) / abs(fd),
             "e0_grad_norm": float(e0.grad.norm())}
 
@@ -327,7 +329,8 @@ def main():
         "fp32_vs_fp64_tmunu_rel_err": parity,
         "kernels_ms": {"pred": r32["pred_ms"], "corr": r32["corr_ms"]},
         "batched": batch if batch is None else dict(batch, vs_plain_fp64_step=batch["value"] / sups64),
-        "differentiable": adjoint,
+        "differentiable": adjoint if adjoint is None else dict(
+            adjoint, vs_plain_fp64_step=adjoint["gradient_site_updates_per_s"] / sups64),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

@@ -195,19 +195,56 @@ def test_prec_workload_sampled_parity(lat, eos):
         assert tmunu_rel_err(got, ref) < 1e-5, (cy, cx)
 
 
-def test_prec_workload_fp32_vs_fp64_full_run(eos):
+@pytest.mark.parametrize("eta", [0.08, 0.2])
+def test_prec_workload_fp32_vs_fp64_full_run(eos, eta):
     # the precision form against the FP64 GPU step over the whole 1000-step run
     w = wl.WORKLOADS["prec"]
     e0 = gaussian_e0(eos, w["nx"], w["ny"], w["dx"]) * wl.white_noise_factor(w["nx"], w["ny"])
     dtau = (w["tau1"] - w["tau0"]) / w["steps"]
     out = {}
     for prec in (lb.LB_FP64, lb.LB_FP32_FP64MATCH):
-        c = make_ctx(w["nx"], w["ny"], w["dx"], e0, precision=prec, eta_over_s=w["eta_over_s"])
+        c = make_ctx(w["nx"], w["ny"], w["dx"], e0, precision=prec, eta_over_s=eta)
         c.step(w["steps"], dtau)
         out[prec] = cpu(c.moments())
         assert c.status() == lb.LB_OK
     err = tmunu_rel_err(out[lb.LB_FP32_FP64MATCH], out[lb.LB_FP64])
-    print("prec workload, 1000 steps, FP32-match vs FP64 T^{mu nu} rel err:", err)
+    print(f"prec workload, eta/s {eta}, 1000 steps, FP32-match vs FP64 T^{{mu nu}} rel err:", err)
+    assert err < 1e-4
+
+
+def test_spots_workload_fp32_vs_fp64_and_oracle(lat, eos):
+    # 512 x 512 hot spots (rng 3) on the floor eps_EoS(0.25 GeV), eta/s 0.16,
+    # 2000 steps: the FP32 state (629 MB, large-grid mode: 8-row tiles,
+    # streaming stores) against the FP64 GPU step over the whole run, and one
+    # step at sampled sites against the oracle after 300 steps
+    w = wl.WORKLOADS["spots"]
+    n, dx, eta = w["nx"], w["dx"], w["eta_over_s"]
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    e0 = float(eos.eps(0.25)) / HBARC ** 3 + wl.hot_spots(n, n, dx, seed=3)
+    prm = st.Params(dx=dx, eta_over_s=eta)
+    out = {}
+    for prec in (lb.LB_FP32_FP64MATCH, lb.LB_FP64):
+        c = make_ctx(n, n, dx, e0, precision=prec, eta_over_s=eta)
+        if prec == lb.LB_FP32_FP64MATCH:
+            c.step(300, dtau)
+            F0, l0, tau = c.get_state()
+            F0, l0 = cpu(F0), cpu(l0)
+            c.step(1, dtau)
+            obs = cpu(c.moments())
+            rng = np.random.default_rng(23)
+            hot = np.unravel_index(np.argmax(e0), e0.shape)
+            for (cy, cx) in [hot, (0, 0), (n - 1, 7)] + [tuple(rng.integers(0, n, 2)) for _ in range(4)]:
+                Fp, lp = patch(F0, cy, cx, 4), patch(l0, cy, cx, 4)
+                Fo, lo = st.heun_step(lat, eos, prm, Fp, lp, tau, dtau)
+                ref = st.observables(lat, eos, prm, Fo, lo)[:, 4:5, 4:5]
+                assert tmunu_rel_err(obs[:, cy:cy + 1, cx:cx + 1], ref) < 1e-5, (cy, cx)
+            c.step(w["steps"] - 301, dtau)
+        else:
+            c.step(w["steps"], dtau)
+        out[prec] = cpu(c.moments())
+        assert c.status() == lb.LB_OK
+    err = tmunu_rel_err(out[lb.LB_FP32_FP64MATCH], out[lb.LB_FP64])
+    print("spots workload, 2000 steps, FP32-match vs FP64 T^{mu nu} rel err:", err)
     assert err < 1e-4
 
 
