@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-form measurement")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the differentiable-form measurement (one JSON object)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -287,6 +289,9 @@ def main():
     import paper_1108_5561_amd as lb
     from paper_1108_5561_amd import workloads as wl
 
+    if args.adjoint_only:
+        print(json.dumps(run_adjoint(lb, wl, torch)), flush=True)
+        return
     r32 = run_gpu(lb, wl, torch, "fp32", args.steps, args.warmup)
     r64 = run_gpu(lb, wl, torch, "fp64", args.steps, args.warmup)
     n = r32["n_sites"]
