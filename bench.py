@@ -308,8 +308,17 @@ def main():
     traffic = measured_traffic(kname)
 
     parity = parity_fp32_vs_fp64(lb, wl, torch)
-    batch = None if args.no_batch else run_batch(lb, wl, torch)
-    adjoint = None if args.no_adjoint else run_adjoint(lb, wl, torch)
+    def optional(fn):
+        # the batched and differentiable forms are reported beside the
+        # headline; a failure there is recorded, not fatal to the line
+        try:
+            return fn(lb, wl, torch)
+        except Exception as exc:  # noqa: BLE001
+            print(f"{fn.__name__} failed: {exc!r}", file=sys.stderr, flush=True)
+            return {"error": repr(exc)}
+
+    batch = None if args.no_batch else optional(run_batch)
+    adjoint = None if args.no_adjoint else optional(run_adjoint)
 
     out = {
         "metric": "site-updates/s & HBM GB/s: FP32+FP64-match vs FP64 step at 1e-5 rel err",
@@ -333,8 +342,9 @@ def main():
                  "pred_ms": r64["pred_ms"], "corr_ms": r64["corr_ms"]},
         "fp32_vs_fp64_tmunu_rel_err": parity,
         "kernels_ms": {"pred": r32["pred_ms"], "corr": r32["corr_ms"]},
-        "batched": batch if batch is None else dict(batch, vs_plain_fp64_step=batch["value"] / sups64),
-        "differentiable": adjoint if adjoint is None else dict(
+        "batched": batch if batch is None or "error" in batch else dict(
+            batch, vs_plain_fp64_step=batch["value"] / sups64),
+        "differentiable": adjoint if adjoint is None or "error" in adjoint else dict(
             adjoint, vs_plain_fp64_step=adjoint["gradient_site_updates_per_s"] / sups64),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
