@@ -64,6 +64,7 @@ enum { LB_FP64 = 0, LB_FP32_FP64MATCH = 1 };          /* storage / node arithmet
 enum { LB_TAUR_CE = 0, LB_TAUR_MASSLESS = 1 };        /* how tau_R follows eta/s */
 enum { LB_METRIC_MILNE = 0, LB_METRIC_MINKOWSKI = 1 };
 enum { LB_EOS_TANH_P = 0, LB_EOS_CONST_MASS = 1, LB_EOS_TANH_S = 2, LB_EOS_TABLE = 3 };
+enum { LB_OPS_WEAK = 0, LB_OPS_STRONG = 1 };  /* momentum-derivative operators S1, S2 */
 
 /*
  * Problem statement (Sec. IV.D: an initial condition is the distribution plus
@@ -114,6 +115,15 @@ typedef struct lb_params {
   const double* eos_s_GeV3; /* [eos_n] entropy density, > 0 */
   double eos_p0_GeV4;       /* pressure at eos_T_GeV[0] */
   int32_t eos_n;            /* >= 4 */
+  /* S1 (p^Y d/dp^Y) and S2 (p . d/dp) on the momentum lattice (Sec. IV.D):
+   * LB_OPS_WEAK, the paper's weak form (projection with the coefficients
+   * s_1^{ml}, s_2^{ml}), or LB_OPS_STRONG, the derivatives of the
+   * interpolant exp(-z0 cosh xi) P(cosh xi, cos theta) through the nodes
+   * (exact on that span).  Both keep the discrete energy balance of
+   * eq. (edchange); far from equilibrium (free streaming) the weak form is
+   * the more accurate.  Both factor into radial and polar 5 x 5 parts, so
+   * the cost is the same. */
+  int32_t operator_form;
 } lb_params;
 
 /*

@@ -49,8 +49,12 @@ PI2 = np.pi ** 2
 
 
 class Lattice:
-    def __init__(self, n_xi=5, n_theta=5, n_phi=4, z0=1.0):
+    def __init__(self, n_xi=5, n_theta=5, n_phi=4, z0=1.0, form="weak"):
+        """form = "weak": the paper's weak-form S1, S2 (Sec. IV.D); "strong":
+        the derivatives of the interpolant through the nodes (a comparison
+        variant, see _strong_form_operators)."""
         self.n_xi, self.n_theta, self.n_phi, self.z0 = int(n_xi), int(n_theta), int(n_phi), float(z0)
+        self.form = form
         self.n_slice = 2 * self.n_phi
         self.n_kj = self.n_xi * self.n_theta
         self.N = self.n_kj * self.n_slice
@@ -77,7 +81,12 @@ class Lattice:
             sh * self.mu_j[self.j_n],
         ])  # (4, N)
 
-        self.D1, self.D2 = self._weak_form_operators()
+        if form == "weak":
+            self.D1, self.D2 = self._weak_form_operators()
+        elif form == "strong":
+            self.D1, self.D2 = self._strong_form_operators()
+        else:
+            raise ValueError(f"unknown operator form {form!r}")
 
     # ------------------------------------------------------------------
     def _weak_form_operators(self):
@@ -113,6 +122,40 @@ class Lattice:
                 B1[col, :] = pref * wslice * b1
                 B2[col, :] = pref * wslice * b2
         return Phi @ B1, Phi @ B2
+
+    def _strong_form_operators(self):
+        """Strong-form slice operators: on one phi slice the values F_{kj} are
+        interpolated by exp(-z0 x) P(x, mu), P of degree < N_xi in x and
+        < N_theta in mu through the nodes, and the continuum operators are
+        applied to the interpolant at the nodes:
+            S2 F = p . dF/dp = ((x^2 - 1)/x) dF/dx       (|p| = M sinh xi),
+            S1 F = p^Y dF/dp^Y = mu^2 (x^2 - 1)/x dF/dx + mu (1 - mu^2) dF/dmu.
+        P is written in Chebyshev polynomials of x mapped to [-1, 1] times
+        Legendre polynomials of mu (a well-conditioned tensor basis) and its
+        coefficients are solved for directly."""
+        from numpy.polynomial import chebyshev as npcheb
+        nx, nt, z0 = self.n_xi, self.n_theta, self.z0
+        q = np.arange(self.n_kj)
+        x = self.x_k[q // nt]
+        mu = self.mu_j[q % nt]
+        lo, hi = self.x_k[0], self.x_k[-1]
+        t = (2.0 * x - (lo + hi)) / (hi - lo)
+        dt_dx = 2.0 / (hi - lo)
+        Vt = npcheb.chebvander(t, nx - 1)                       # (n_kj, nx)
+        dVt = np.stack([npcheb.chebval(t, npcheb.chebder(np.eye(nx)[a])) for a in range(nx)], 1) * dt_dx
+        Vm = npleg.legvander(mu, nt - 1)                        # (n_kj, nt)
+        dVm = np.stack([npleg.legval(mu, npleg.legder(np.eye(nt)[b])) for b in range(nt)], 1)
+        V = (Vt[:, :, None] * Vm[:, None, :]).reshape(self.n_kj, -1)
+        Vx = (dVt[:, :, None] * Vm[:, None, :]).reshape(self.n_kj, -1)
+        Vu = (Vt[:, :, None] * dVm[:, None, :]).reshape(self.n_kj, -1)
+        # P coefficients of a slice vector F: P(nodes) = exp(z0 x) F
+        C = np.linalg.solve(V, np.diag(np.exp(z0 * x)))
+        E = np.diag(np.exp(-z0 * x))
+        dFdx = E @ (Vx @ C - z0 * (V @ C))      # d/dx [exp(-z0 x) P] at the nodes
+        dFdmu = E @ (Vu @ C)
+        D2 = np.diag((x * x - 1.0) / x) @ dFdx
+        D1 = np.diag(mu * mu) @ D2 + np.diag(mu * (1.0 - mu * mu)) @ dFdmu
+        return D1, D2
 
     # ------------------------------------------------------------------
     def apply_slices(self, D, F):

@@ -267,6 +267,44 @@ std::string build_lattice(const lb_params& p, HostLattice* L) {
     }
   }
 
+  if (p.operator_form == LB_OPS_STRONG) {
+    // Strong form: differentiate the interpolant exp(-z0 x) P(x, mu) through
+    // the nodes.  With D the barycentric derivative matrix of the Lagrange
+    // interpolant on a node set,
+    //   S2 = p . d/dp = ((x^2 - 1)/x) d/dx:
+    //     A2_{kk'} = ((x_k^2 - 1)/x_k) e^{-z0 x_k} (Dx_{kk'} - z0 delta_{kk'}) e^{z0 x_k'},
+    //   S1 = p^Y d/dp^Y = mu^2 (x^2 - 1)/x d/dx + mu (1 - mu^2) d/dmu:
+    //     A1 = A2,  Ath_{jj'} = -mu_j (1 - mu_j^2) Dmu_{jj'}.
+    auto deriv_matrix = [](const std::vector<ld>& y) {
+      const int n = (int)y.size();
+      std::vector<ld> c(n, 1), D(n * n, 0);
+      for (int i = 0; i < n; ++i)
+        for (int m = 0; m < n; ++m)
+          if (m != i) c[i] *= (y[i] - y[m]);
+      for (int i = 0; i < n; ++i) {
+        ld diag = 0;
+        for (int j = 0; j < n; ++j) {
+          if (j == i) continue;
+          D[i * n + j] = (c[i] / c[j]) / (y[i] - y[j]);
+          diag += 1 / (y[i] - y[j]);
+        }
+        D[i * n + i] = diag;
+      }
+      return D;
+    };
+    const std::vector<ld> Dx = deriv_matrix(xk), Dm = deriv_matrix(mu);
+    for (int k = 0; k < nxi; ++k)
+      for (int kp = 0; kp < nxi; ++kp) {
+        const ld x = xk[k];
+        const ld v = (x * x - 1) / x * std::exp(z0 * (xk[kp] - x)) * (Dx[k * nxi + kp] - (k == kp ? z0 : 0));
+        L->A2[k * nxi + kp] = (double)v;
+        L->A1[k * nxi + kp] = (double)v;
+      }
+    for (int j = 0; j < nth; ++j)
+      for (int jp = 0; jp < nth; ++jp)
+        L->Ath[j * nth + jp] = (double)(-mu[j] * (1 - mu[j] * mu[j]) * Dm[j * nth + jp]);
+  }
+
   // streaming CFL factor
   double vm = 0;
   for (int k = 0; k < nxi; ++k)

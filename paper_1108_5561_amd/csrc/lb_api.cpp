@@ -101,6 +101,7 @@ std::string validate(const lb_params* p) {
   }
   if (!(p->T_min_GeV > 0) || !(p->T_max_GeV > 2 * p->T_min_GeV) || !std::isfinite(p->T_max_GeV))
     return "need 0 < T_min and T_max > 2 T_min";
+  if (p->operator_form != LB_OPS_WEAK && p->operator_form != LB_OPS_STRONG) return "unknown operator_form";
   return "";
 }
 

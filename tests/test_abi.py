@@ -229,3 +229,19 @@ def test_host_tabulated_cubic_in_log_t_is_exact():
     xq = np.array([-2.9, -1.7, -0.3, 0.9])
     out = lb.eos_eval(p, np.exp(xq))
     assert np.allclose(out[:, 2], np.exp(3 * xq + y(xq)), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("z0", [1.0, 2.6])
+def test_host_strong_form_operators_match_oracle(z0):
+    # LB_OPS_STRONG: the host's barycentric derivative matrices against the
+    # oracle's tensor-interpolant construction
+    p = lb.make_params(8, 8, 0.2, z0=z0, operator_form=lb.LB_OPS_STRONG)
+    info = lb.lattice_info(p)
+    lat = Lattice(5, 5, 4, z0, form="strong")
+    I5 = np.eye(5)
+    D2 = np.kron(info["A2"], I5)
+    D1 = np.kron(info["A1"], I5) * np.tile(info["mu"] ** 2, 5)[:, None] - np.kron(I5, info["Ath"])
+    assert np.max(np.abs(D1 - lat.D1)) < 1e-11 * np.max(np.abs(lat.D1))
+    assert np.max(np.abs(D2 - lat.D2)) < 1e-11 * np.max(np.abs(lat.D2))
+    p.operator_form = 7
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) == 0

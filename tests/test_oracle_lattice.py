@@ -126,3 +126,49 @@ def test_landau_matching_round_trip():
     u, lam = landau(T3)
     assert np.max(np.abs(lam - e_ref) / e_ref) < 1e-12
     assert np.max(np.abs(u - u_ref)) < 1e-11 * np.max(np.abs(u_ref))
+
+
+# ---- the strong-form operator variant (derivatives of the interpolant) ----
+
+@pytest.mark.parametrize("a,b", [(0, 0), (1, 2), (4, 0), (3, 4), (2, 3)])
+def test_strong_form_exact_on_interpolant_span(a, b):
+    # exp(-z0 x) x^a mu^b lies in the interpolant's span, so S2 and S1 are
+    # its exact derivatives at the nodes
+    from oracle.lattice import Lattice
+    lat = Lattice(5, 5, 4, 1.0, form="strong")
+    q = np.arange(25)
+    x, mu = lat.x_k[q // 5], lat.mu_j[q % 5]
+    f = np.exp(-x) * x ** a * mu ** b
+    dfdx = np.exp(-x) * (a * x ** (a - 1) - x ** a) * mu ** b if a else -np.exp(-x) * mu ** b
+    dfdmu = np.exp(-x) * x ** a * b * mu ** (b - 1) if b else 0.0 * mu
+    s2 = (x * x - 1) / x * dfdx
+    s1 = mu ** 2 * s2 + mu * (1 - mu ** 2) * dfdmu
+    scale = np.max(np.abs(f)) * np.max(x)
+    assert np.max(np.abs(lat.D2 @ f - s2)) < 1e-11 * scale
+    assert np.max(np.abs(lat.D1 @ f - s1)) < 1e-11 * scale
+
+
+def test_forms_differ_in_exactness_and_share_the_energy_identities():
+    # the reference exponential exp(-z0 x): the strong S2 is exact there, the
+    # weak S2 (exact on the projected derivative) is off by 6.7%; both keep
+    # the discrete identities behind eq. (edchange), sum w gamma^2 S2 F =
+    # sum w F - 4 sum w gamma^2 F and sum w gamma^2 S1 F = -sum w F (gamma^2 +
+    # (v^Y)^2), because the 5-node rules integrate those integrands exactly
+    from oracle.lattice import Lattice
+    for z0 in (1.0, 2.6):
+        weak, strong = Lattice(5, 5, 4, z0), Lattice(5, 5, 4, z0, form="strong")
+        q = np.arange(25)
+        x, mu = weak.x_k[q // 5], weak.mu_j[q % 5]
+        f = np.exp(-z0 * x)
+        exact = (x * x - 1) / x * (-z0 * np.exp(-z0 * x))
+        err_w = np.max(np.abs(weak.D2 @ f - exact)) / np.max(np.abs(exact))
+        err_s = np.max(np.abs(strong.D2 @ f - exact)) / np.max(np.abs(exact))
+        assert err_s < 1e-12 and err_w > 1e-2
+        rng = np.random.default_rng(2)
+        F = np.exp(-z0 * x) * (1 + 0.3 * rng.random(25))
+        wq = np.exp(z0 * x) * weak.w_xi[q // 5] * weak.w_th[q % 5]
+        vY2 = (x * x - 1) * mu * mu
+        for lat in (weak, strong):
+            r2 = np.sum(wq * x ** 2 * (lat.D2 @ F)) - (np.sum(wq * F) - 4 * np.sum(wq * x ** 2 * F))
+            r1 = np.sum(wq * x ** 2 * (lat.D1 @ F)) + np.sum(wq * F * (x * x + vY2))
+            assert abs(r2) < 1e-13 * np.sum(wq * F) and abs(r1) < 1e-13 * np.sum(wq * F)
