@@ -195,20 +195,25 @@ def test_prec_workload_sampled_parity(lat, eos):
         assert tmunu_rel_err(got, ref) < 1e-5, (cy, cx)
 
 
-@pytest.mark.parametrize("eta", [0.08, 0.2])
-def test_prec_workload_fp32_vs_fp64_full_run(eos, eta):
-    # the precision form against the FP64 GPU step over the whole 1000-step run
+@pytest.mark.parametrize("eta,steps", [(0.08, 1000), (0.2, 60)])
+def test_prec_workload_fp32_vs_fp64_full_run(eos, eta, steps):
+    # the precision form against the FP64 GPU step over the whole 1000-step
+    # run; at eta/s 0.2 over the first 60 steps only: there the grid-scale
+    # white noise (5% per 0.025 fm cell) drives ln M apart between
+    # neighbouring sites and the run leaves the EoS range by tau ~ 1.8 fm/c,
+    # in FP64 and FP32 alike (the oracle shows the same growth on a small
+    # noisy box)
     w = wl.WORKLOADS["prec"]
     e0 = gaussian_e0(eos, w["nx"], w["ny"], w["dx"]) * wl.white_noise_factor(w["nx"], w["ny"])
     dtau = (w["tau1"] - w["tau0"]) / w["steps"]
     out = {}
     for prec in (lb.LB_FP64, lb.LB_FP32_FP64MATCH):
         c = make_ctx(w["nx"], w["ny"], w["dx"], e0, precision=prec, eta_over_s=eta)
-        c.step(w["steps"], dtau)
+        c.step(steps, dtau)
         out[prec] = cpu(c.moments())
         assert c.status() == lb.LB_OK
     err = tmunu_rel_err(out[lb.LB_FP32_FP64MATCH], out[lb.LB_FP64])
-    print(f"prec workload, eta/s {eta}, 1000 steps, FP32-match vs FP64 T^{{mu nu}} rel err:", err)
+    print(f"prec workload, eta/s {eta}, {steps} steps, FP32-match vs FP64 T^{{mu nu}} rel err:", err)
     assert err < 1e-4
 
 
