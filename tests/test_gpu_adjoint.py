@@ -123,6 +123,33 @@ def test_step_adjoint_dot_product(metric, part):
     assert c.status() == lb.LB_OK
 
 
+@pytest.mark.parametrize("nx,ny", [(3, 1), (1, 1), (37, 5)])
+def test_step_adjoint_dot_product_small_and_ragged_grids(nx, ny):
+    # grids shorter than the upwind stencil (periodic wrap onto the site
+    # itself) and a site count that leaves the last block partly empty
+    dx, dtau, eta = 0.15, 0.01, 0.12
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta)
+    ux, uy = wl.random_flow(nx, ny, 0.2, seed=7)
+    c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, 4)), gpu(ux), gpu(uy))
+    c.step(2, dtau)
+    F, L, tau = c.get_state()
+    rng = np.random.default_rng(31)
+    dF = F * gpu(rng.standard_normal(tuple(F.shape)))
+    dL = gpu(rng.standard_normal(tuple(L.shape)))
+    aF = gpu(rng.standard_normal(tuple(F.shape)))
+    aL = gpu(rng.standard_normal(tuple(L.shape)))
+    bF, bL = aF.clone(), aL.clone()
+    g_eta = torch.zeros(1, dtype=torch.float64, device=DEV)
+    c.adjoint_step(tau, dtau, F, L, bF, bL, g_eta, c.adjoint_workspace())
+    lhs = float((bF * dF).sum() + (bL * dL).sum())
+    h = 1e-6
+    Fp, Lp = lib_step(c, F + h * dF, L + h * dL, tau, dtau)
+    Fm, Lm = lib_step(c, F - h * dF, L - h * dL, tau, dtau)
+    rhs = float(((aF * (Fp - Fm)).sum() + (aL * (Lp - Lm)).sum()) / (2 * h))
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs), (lhs, rhs)
+    assert c.status() == lb.LB_OK
+
+
 def test_free_streaming_has_no_eta_gradient():
     nx, ny, dx, dtau = 8, 8, 0.15, 0.01
     p = lb.make_params(nx, ny, dx, eta_over_s=math.inf)
