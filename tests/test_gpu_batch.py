@@ -116,3 +116,35 @@ def test_large_grid_mode_equals_cached_tiles():
     Fb, lb_, tb = b.get_state(0)
     assert tb == t and torch.equal(Fb, F) and torch.equal(lb_, l)
     assert c.status() == lb.LB_OK and b.status() == lb.LB_OK
+
+
+def test_full_batch_workload_sampled_events():
+    """The 64-event batched workload at the bench's launch configuration
+    (tuned variant, 96 steps as two 48-step graph replays): the smallest,
+    the largest and two random events equal the same events advanced alone
+    with lb_step, bit for bit."""
+    w = wl.WORKLOADS["batch"]
+    events = wl.batch_events(w["n_events"], w["n_min"], w["n_max"], w["box"])
+    p = lb.make_params(8, 8, 0.1, tau0_fm=w["tau0"], precision=lb.LB_FP32_FP64MATCH)
+    bg = lb.eos_eval(p, [0.25])[0, 0] / lb.HBARC ** 3
+    spots = wl.batch_hot_spots(events)
+    e0s = [torch.from_numpy(bg + h).to(DEV) for h in spots]
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    b = lb.Batch(p, events, e0s)
+    b.tune(dtau)
+    b.step(96, dtau)
+    assert b.status() == lb.LB_OK
+    sizes = [nx * ny for nx, ny, _, _ in events]
+    rng = np.random.default_rng(5)
+    picks = {int(np.argmin(sizes)), int(np.argmax(sizes))} | set(int(i) for i in rng.integers(0, len(events), 2))
+    for e in sorted(picks):
+        nx, ny, dx, eta = events[e]
+        q = lb.make_params(nx, ny, dx, tau0_fm=w["tau0"], eta_over_s=eta, precision=lb.LB_FP32_FP64MATCH)
+        c = lb.Context(q, e0s[e])
+        c.step(96, dtau)
+        F, l, t = c.get_state()
+        Fb, lb_, tb = b.get_state(e)
+        assert tb == t and torch.equal(Fb, F) and torch.equal(lb_, l), f"event {e} ({nx}x{ny})"
+        assert c.status() == lb.LB_OK
+        c.close()
+    b.close()
