@@ -212,8 +212,9 @@ size_t lb_adjoint_workspace_bytes(const lb_params* p);
  * tau_fm to (d_F_out, d_lnM_out) at tau_fm + dtau_fm (outputs must not
  * alias the inputs).  Equal to lb_step on an LB_FP64 context up to rounding
  * order; it is the forward map whose transpose lb_adjoint_step applies.
- * LB_E_ARG for NULL pointers, a workspace that is too small, tau <= 0, or a
- * dtau that lb_step would reject (CFL).
+ * LB_E_ARG for NULL or aliasing pointers, a workspace that is too small, a
+ * tau that is not finite (or <= 0 for the Milne metric), or a dtau that
+ * lb_step would reject (CFL).
  */
 int lb_adjoint_forward_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F, const double* d_lnM,
                             double* d_F_out, double* d_lnM_out, void* d_adj_workspace, size_t adj_ws_bytes);

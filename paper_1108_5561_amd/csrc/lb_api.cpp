@@ -316,7 +316,8 @@ struct AdjBufs {
 int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBufs* B) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
-  if (!(tau > 0) || !std::isfinite(tau)) return fail(LB_E_ARG, "tau must be finite and > 0");
+  if (!std::isfinite(tau) || (c->p.metric == LB_METRIC_MILNE && !(tau > 0)))
+    return fail(LB_E_ARG, "tau must be finite (and > 0 for the Milne metric)");
   const double cfl = c->lat.vsum_max * dtau / c->p.dx_fm;
   if (cfl > 0.5)
     return fail(LB_E_ARG, "CFL number " + std::to_string(cfl) + " > 0.5 (reduce dtau or increase dx)");
@@ -556,6 +557,7 @@ int lb_adjoint_forward_step(lb_ctx* c, double tau_fm, double dtau_fm, const doub
   int rc = adj_check(c, tau_fm, dtau_fm, d_adj_workspace, adj_ws_bytes, &B);
   if (rc != LB_OK) return rc;
   if (!d_F || !d_lnM || !d_F_out || !d_lnM_out) return fail(LB_E_ARG, "state pointer is NULL");
+  if (d_F_out == d_F || d_lnM_out == d_lnM) return fail(LB_E_ARG, "outputs must not alias the inputs");
   StageArgs a = stage_args(c, tau_fm, dtau_fm);
   hipError_t e =
       launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->tb, a, c->err, c->stream);
