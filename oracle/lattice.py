@@ -49,12 +49,16 @@ PI2 = np.pi ** 2
 
 
 class Lattice:
-    def __init__(self, n_xi=5, n_theta=5, n_phi=4, z0=1.0, form="weak"):
+    def __init__(self, n_xi=5, n_theta=5, n_phi=4, z0=1.0, form="weak", force="feq"):
         """form = "weak": the paper's weak-form S1, S2 (Sec. IV.D); "strong":
         the derivatives of the interpolant through the nodes (a comparison
-        variant, see _strong_form_operators)."""
+        variant, see _strong_form_operators).
+        force = "feq": the mass-gradient force acts on F_eq, differentiated
+        analytically; "weak3d": it acts on F through the weak-form operators
+        G_x, G_y over the whole sphere of directions (force3d)."""
         self.n_xi, self.n_theta, self.n_phi, self.z0 = int(n_xi), int(n_theta), int(n_phi), float(z0)
         self.form = form
+        self.force = force
         self.n_slice = 2 * self.n_phi
         self.n_kj = self.n_xi * self.n_theta
         self.N = self.n_kj * self.n_slice
@@ -87,6 +91,11 @@ class Lattice:
             self.D1, self.D2 = self._strong_form_operators()
         else:
             raise ValueError(f"unknown operator form {form!r}")
+        if force == "weak3d":
+            from . import force3d
+            self.Gx, self.Gy = force3d.weak_force_operators(self)
+        elif force != "feq":
+            raise ValueError(f"unknown force form {force!r}")
 
     # ------------------------------------------------------------------
     def _weak_form_operators(self):

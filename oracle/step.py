@@ -25,7 +25,9 @@ Right-hand side at (F, ln M, tau), per site (step numbers used below):
     periodic boundaries;
  8. mass-gradient force of eq. (Bmilne), (1/2) d_i M^2 d^i_(p), at fixed v:
     Gr = sum_i (g_i/gamma) [v^i (v . d_v F_eq) + d_{v^i} F_eq], g_i = d_i ln M
-    by centred differences, derivatives of F_eq taken analytically;
+    by centred differences, derivatives of F_eq taken analytically (lattice
+    force "feq"); or Gr = sum_i g_i G_i F with the weak-form operators of
+    force3d acting on F itself (lattice force "weak3d");
  9. R0 = A + S1/tau + Gr - C (the S1/tau term is the Milne Christoffel term and
     is absent for the Minkowski metric);
 10. X = d ln M/d tau from eq. (masschange) with the temperature fixed by
@@ -48,6 +50,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
+from . import force3d
 from .eos import HBARC
 
 PI2 = np.pi ** 2
@@ -159,6 +162,8 @@ def rhs(lat, eos, prm: Params, F, lnM, tau):
     v_dFeq = -(F_eq / T) * (ut * M ** 2 * sh2 / E_eq - M * uv)
     g_dFeq = -(F_eq / T) * (ut * M ** 2 * gv / E_eq - M * gu)
     Gr = (gv * v_dFeq + g_dFeq) / gam
+    if lat.force == "weak3d":
+        Gr = force3d.apply(lat.Gx, lat.Gy, F, gx, gy)
 
     # 9. R0
     R0 = A + Gr - C
