@@ -65,6 +65,7 @@ enum { LB_TAUR_CE = 0, LB_TAUR_MASSLESS = 1 };        /* how tau_R follows eta/s
 enum { LB_METRIC_MILNE = 0, LB_METRIC_MINKOWSKI = 1 };
 enum { LB_EOS_TANH_P = 0, LB_EOS_CONST_MASS = 1, LB_EOS_TANH_S = 2, LB_EOS_TABLE = 3 };
 enum { LB_OPS_WEAK = 0, LB_OPS_STRONG = 1 };  /* momentum-derivative operators S1, S2 */
+enum { LB_FORCE_FEQ = 0, LB_FORCE_WEAK3D = 1 };  /* mass-gradient force of eq. (Bmilne) */
 
 /*
  * Problem statement (Sec. IV.D: an initial condition is the distribution plus
@@ -124,6 +125,22 @@ typedef struct lb_params {
    * the more accurate.  Both factor into radial and polar 5 x 5 parts, so
    * the cost is the same. */
   int32_t operator_form;
+  /* The force term (1/2) d_i M^2 d^i_(p) of eq. (Bmilne) at fixed v = p~/M,
+   * (d_i ln M / gamma) [v^i (v . d_v) + d_{v^i}] with d_i ln M by centred
+   * differences, applied either to
+   * LB_FORCE_FEQ: the local equilibrium F_eq, differentiated analytically
+   *   (exact on F_eq; the lattice moments of the force follow the balance
+   *   laws only for F = F_eq), or to
+   * LB_FORCE_WEAK3D: F itself, through the weak form of the operator on the
+   *   test space of eq. (fansatz) (solid harmonics of v/|v| times powers
+   *   of sinh xi times polynomials in cosh xi, one factor sinh xi kept for
+   *   odd degree; 2 n_phi x n_theta x n_xi functions on the same number of
+   *   nodes).  Energy, momentum and particle-number moments of the force
+   *   then follow the balance laws exactly for any F.  It mixes the phi
+   *   slices (a real Fourier transform over them), so the stage does about
+   *   twice the arithmetic.  lb_step only: the batched and adjoint entry
+   *   points return LB_E_NOTIMPL for it. */
+  int32_t force_form;
 } lb_params;
 
 /*

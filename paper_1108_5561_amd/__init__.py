@@ -23,6 +23,7 @@ LB_TAUR_CE, LB_TAUR_MASSLESS = 0, 1
 LB_METRIC_MILNE, LB_METRIC_MINKOWSKI = 0, 1
 LB_EOS_TANH_P, LB_EOS_CONST_MASS, LB_EOS_TANH_S, LB_EOS_TABLE = 0, 1, 2, 3
 LB_OPS_WEAK, LB_OPS_STRONG = 0, 1
+LB_FORCE_FEQ, LB_FORCE_WEAK3D = 0, 1
 HBARC = 0.1973269804  # GeV fm
 N_OBS = 14
 OBS_NAMES = ("Ttt", "Ttx", "Tty", "Txx", "Txy", "Tyy", "TYY", "Nt", "Nx", "Ny", "T", "ux", "uy", "M")
@@ -49,7 +50,7 @@ class lb_params(ctypes.Structure):
         ("eos_mass_GeV", ctypes.c_double), ("T_min_GeV", ctypes.c_double), ("T_max_GeV", ctypes.c_double),
         ("eos_T_GeV", ctypes.POINTER(ctypes.c_double)), ("eos_s_GeV3", ctypes.POINTER(ctypes.c_double)),
         ("eos_p0_GeV4", ctypes.c_double), ("eos_n", ctypes.c_int32),
-        ("operator_form", ctypes.c_int32),
+        ("operator_form", ctypes.c_int32), ("force_form", ctypes.c_int32),
     ]
 
 
@@ -135,7 +136,8 @@ def degeneracy(kappa, g):
 def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, metric=LB_METRIC_MILNE,
                 taur_rule=LB_TAUR_CE, eos_kind=LB_EOS_TANH_S, eos_g=37.0, eos_Tc_GeV=0.17, eos_width_GeV=0.02,
                 eos_mass_GeV=0.0, kappa=2.0, Z=None, z0=1.0, n_xi=5, n_theta=5, n_phi=4,
-                T_min_GeV=0.05, T_max_GeV=3.0, eos_table=None, operator_form=LB_OPS_WEAK):
+                T_min_GeV=0.05, T_max_GeV=3.0, eos_table=None, operator_form=LB_OPS_WEAK,
+                force_form=LB_FORCE_FEQ):
     """Parameters of a run.  eos_table = (T [GeV], s [GeV^3], p(T[0]) [GeV^4])
     selects LB_EOS_TABLE with the caller's entropy density (the arrays are
     kept alive by the returned object)."""
@@ -156,6 +158,7 @@ def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, 
     p.eos_g, p.eos_Tc_GeV, p.eos_width_GeV, p.eos_mass_GeV = eos_g, eos_Tc_GeV, eos_width_GeV, eos_mass_GeV
     p.T_min_GeV, p.T_max_GeV = T_min_GeV, T_max_GeV
     p.operator_form = operator_form
+    p.force_form = force_form
     return p
 
 

@@ -19,6 +19,8 @@ inline size_t site_scalar_bytes(size_t n_sites, size_t elt) { return n_sites * s
 struct StageArgs {
   int32_t nx, ny, n_sites;
   int32_t metric;
+  int32_t force_form;    // LB_FORCE_FEQ or LB_FORCE_WEAK3D (lb_step only)
+  int32_t pad_;
   double inv2dx;         // 1/(2 dx)    [fm^-1]
   double inv_dx;         // 1/dx
   double tau;            // time of this stage [fm]

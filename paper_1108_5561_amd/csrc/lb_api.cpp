@@ -102,6 +102,7 @@ std::string validate(const lb_params* p) {
   if (!(p->T_min_GeV > 0) || !(p->T_max_GeV > 2 * p->T_min_GeV) || !std::isfinite(p->T_max_GeV))
     return "need 0 < T_min and T_max > 2 T_min";
   if (p->operator_form != LB_OPS_WEAK && p->operator_form != LB_OPS_STRONG) return "unknown operator_form";
+  if (p->force_form != LB_FORCE_FEQ && p->force_form != LB_FORCE_WEAK3D) return "unknown force_form";
   return "";
 }
 
@@ -177,6 +178,76 @@ void fill_const(const HostLattice& L, LatticeConst<R, 5, 5>* C) {
   }
 }
 
+// Derivative matrix of polynomial interpolation through the nodes z:
+// D[a][b] = l_b'(z_a), l_b the Lagrange polynomial of node b.
+void lagrange_derivative(const std::vector<double>& z, double* D) {
+  const int n = (int)z.size();
+  std::vector<double> c(n, 1.0);
+  for (int a = 0; a < n; ++a)
+    for (int m = 0; m < n; ++m)
+      if (m != a) c[a] *= z[a] - z[m];
+  for (int a = 0; a < n; ++a) {
+    double diag = 0.0;
+    for (int b = 0; b < n; ++b) {
+      if (b == a) continue;
+      D[a * n + b] = (c[a] / c[b]) / (z[a] - z[b]);
+      diag += 1.0 / (z[a] - z[b]);
+    }
+    D[a * n + a] = diag;
+  }
+}
+
+// Constants of the weak-form 3-D force.  The weak operator is minus the
+// w-weighted transpose of the strong-form derivatives on the test space,
+//   sum_i g_i G_i F = -(1/w) [Ds^T (g_r sin(theta) x w F) + Dmu^T (-g_r mu sin(theta) w F / (s x))
+//                             + Dphi^T (g_t w F / (s sin(theta) x)) + 2 g_r s sin(theta) w F / x],
+// g_r = g_x cos phi + g_y sin phi, g_t = g_y cos phi - g_x sin phi, with
+// Ds, Dmu, Dphi the partial derivatives (s, mu, phi) of the interpolant in
+// the test space; per Fourier mode m of phi these are a radial matrix on
+// s^e P(x) (e = parity of m + the mu-parity), the polar matrix on
+// (1 - mu^2)^{m/2} P(mu) and a cos/sin swap times m.
+template <typename R>
+void fill_force_const(const HostLattice& L, StageConst<R>* S) {
+  const int nxi = 5, nth = 5;
+  double Dx[25], Dm[25];
+  lagrange_derivative(L.x, Dx);
+  lagrange_derivative(L.mu, Dm);
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) {
+      S->fDxT[a * 5 + b] = (R)Dx[b * 5 + a];
+      S->fDmT[a * 5 + b] = (R)Dm[b * 5 + a];
+    }
+  for (int k = 0; k < nxi; ++k) {
+    const double x = L.x[k], sh = std::sqrt(x * x - 1.0);
+    S->frho0[k] = (R)(sh / x);
+    S->frho1[k] = (R)(sh * sh / x);
+    S->fsig1[k] = (R)(1.0 / sh);
+    for (int j = 0; j < nth; ++j) {
+      const int q = k * nth + j;
+      const double mu = L.mu[j], st = std::sqrt(1.0 - mu * mu);
+      const double w = std::exp(L.z0 * x) * L.wxi[k] * L.wth[j] / (4.0 * L.nphi);
+      S->fw[q] = (R)w;
+      S->finvw[q] = (R)(1.0 / w);
+      S->fa[q] = (R)(st * x);
+      S->fb[q] = (R)(-mu * st / (sh * x));
+      S->fc[q] = (R)(1.0 / (sh * st * x));
+      S->fy[q] = (R)(2.0 * sh * st / x);
+    }
+  }
+  for (int pr = 0; pr < 2; ++pr) S->fst[pr] = (R)std::sqrt(1.0 - L.mu[pr] * L.mu[pr]);
+  for (int j = 0; j < nth; ++j) S->fmr[j] = (R)(L.mu[j] / (1.0 - L.mu[j] * L.mu[j]));
+  // cos and sin of multiples of pi/4, exact where they are 0 or +-1
+  const double h = std::sqrt(0.5);
+  const double c8[8] = {1, h, 0, -h, -1, -h, 0, h}, s8[8] = {0, h, 1, h, 0, -h, -1, -h};
+  const int mode[8] = {0, 4, 1, 1, 2, 2, 3, 3};
+  const bool sine[8] = {false, false, false, true, false, true, false, true};
+  for (int l = 0; l < 8; ++l)
+    for (int r = 0; r < 8; ++r) {
+      const int i = (mode[r] * l) % 8;
+      S->fphi[l * 8 + r] = (R)(sine[r] ? s8[i] : c8[i]);
+    }
+}
+
 // Stage constants (mirror-pair form, see StageConst) with S1 unscaled.
 template <typename R>
 void fill_stage_const(const HostLattice& L, StageConst<R>* S) {
@@ -222,6 +293,7 @@ void fill_stage_const(const HostLattice& L, StageConst<R>* S) {
     S->cosl[l] = (R)L.cosl[l];
     S->sinl[l] = (R)L.sinl[l];
   }
+  fill_force_const(L, S);
 }
 
 // The stage constants of a context: as built for the Milne metric (the
@@ -261,6 +333,8 @@ StageArgs params_args(const lb_params& p, double tau, double dtau) {
   a.ny = p.ny;
   a.n_sites = p.nx * p.ny;
   a.metric = p.metric;
+  a.force_form = p.force_form;
+  a.pad_ = 0;
   a.inv2dx = 0.5 / p.dx_fm;
   a.inv_dx = 1.0 / p.dx_fm;
   a.dtau = dtau;
@@ -315,6 +389,7 @@ struct AdjBufs {
 };
 int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBufs* B) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
+  if (c->p.force_form != LB_FORCE_FEQ) return fail(LB_E_NOTIMPL, "the adjoint step has the F_eq force only");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
   if (!std::isfinite(tau) || (c->p.metric == LB_METRIC_MILNE && !(tau > 0)))
     return fail(LB_E_ARG, "tau must be finite (and > 0 for the Milne metric)");
@@ -1060,6 +1135,7 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
   *out = nullptr;
   std::string m = validate_batch(p, events, n_events);
   if (!m.empty()) return fail(LB_E_ARG, m);
+  if (p->force_form != LB_FORCE_FEQ) return fail(LB_E_NOTIMPL, "the batched form has the F_eq force only");
   if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(LB_E_ARG, "workspace NULL or not 256-byte aligned");
   if (!d_e0) return fail(LB_E_ARG, "e0 pointer array is NULL");
   for (int i = 0; i < n_events; ++i)

@@ -135,6 +135,22 @@ struct StageConst {
   // (f_0 + f_4, f_1 + f_3, f_2) for j = 2.
   R Ev[2][3], Od[2][2], Mid[3];
   R cosl[8], sinl[8];
+  // Weak-form 3-D mass-gradient force (weak_force), per node q = k * 5 + j
+  // of a slice (s = sinh xi_k, x = cosh xi_k, mu = cos theta_j):
+  R fw[25];      // w_n
+  R finvw[25];   // 1/w_n
+  R fa[25];      // sin theta x               (radial part)
+  R fb[25];      // -mu sin theta / (s x)     (polar part)
+  R fc[25];      // 1 / (s sin theta x)       (azimuthal part)
+  R fy[25];      // 2 s sin theta / x
+  R fDxT[25];    // [k][k']: derivative of the k-th Lagrange polynomial of the radial nodes at x_k'
+  R fDmT[25];    // [j][j']: the same for the polar nodes mu
+  R frho0[5], frho1[5], fsig1[5];  // s/x, s^2/x, 1/s per radial node
+  R fst[2];      // sin theta of polar pairs 0 and 1 (pair 2: mu = 0, sin theta = 1)
+  R fmr[5];      // mu / (1 - mu^2) per polar node
+  R fphi[64];    // [l][r]: the Fourier function of lane r at phi_l; lane r holds
+                 // mode 0, cos 4 phi, cos phi, sin phi, cos 2 phi, sin 2 phi,
+                 // cos 3 phi, sin 3 phi for r = 0 .. 7
 };
 
 }  // namespace lbmi

@@ -66,6 +66,9 @@ template <typename R, int STAGE> struct MinWaves {
   static constexpr int v = STAGE == 0 ? LB_WAVES_PER_EU_F32 : LB_WAVES_PER_EU_F32_CORR;
 };
 template <int STAGE> struct MinWaves<double, STAGE> { static constexpr int v = LB_WAVES_PER_EU_F64; };
+// with the weak-form 3-D force (about twice the registers in flight)
+template <typename R> struct ForceWaves { static constexpr int v = 2; };
+template <> struct ForceWaves<double> { static constexpr int v = 1; };
 
 // A distribution buffer is read and written as one raw buffer: one
 // descriptor (uniform, scalar registers), the plane offset q * plane bytes
@@ -254,6 +257,176 @@ __device__ __forceinline__ EosTable load_table(const EosTable* p) {
   t.u_hi = q->u_hi;
   return t;
 }
+// ---- weak-form 3-D mass-gradient force ---------------------------------
+// Value of lane (lane ^ d) of the 8-lane group (one site's phi slices) for
+// d = 0 .. 7: xor 1, 2, 3 are quad permutations, xor 7 the half-row mirror,
+// xor 4, 5, 6 quad permutations of the mirrored value.
+template <int CTRL>
+__device__ __forceinline__ float lane_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_mov(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+template <typename R>
+__device__ __forceinline__ void group8(R v, R p[8]) {
+  constexpr int kX1 = 0xB1, kX2 = 0x4E, kX3 = 0x1B, kMirror = 0x141;
+  p[0] = v;
+  p[1] = lane_mov<kX1>(v);
+  p[2] = lane_mov<kX2>(v);
+  p[3] = lane_mov<kX3>(v);
+  const R h = lane_mov<kMirror>(v);
+  p[7] = h;
+  p[6] = lane_mov<kX1>(h);
+  p[5] = lane_mov<kX2>(h);
+  p[4] = lane_mov<kX3>(h);
+}
+
+// radial part of the transposed strong-form derivative for one mu column
+// h[k] of a Fourier mode: odd (e = 1) for s P(x), even for P(x):
+//   e = 0: r = Dx^T (s/x . h);   e = 1: r = (1/s) (Dx^T (s^2/x . h) + h)
+template <typename R>
+__device__ __forceinline__ void radial_t(const R h[5], bool e, CPtr<R> C, R r[5]) {
+  R u[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) u[k] = (e ? C->frho1[k] : C->frho0[k]) * h[k];
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    R acc = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc += C->fDxT[b * 5 + k] * u[k];
+    r[b] = e ? C->fsig1[b] * (acc + h[b]) : acc;
+  }
+}
+
+// Adds scale * sum_i g_i G_i F to r0 for this lane's phi slice l, where G_i
+// is the weak form of (1/gamma) [v^i (v . d_v) + d_{v^i}] on the test space
+// of eq. (fansatz) (Sec. IV.B: harmonics of v/|v| of degree n = m + j,
+// Fourier mode m in phi, times s^{n mod 2} P(cosh xi)).  Weak form: for
+// every test function psi, sum w psi (G_i F) = sum w F b_i[psi] with
+// b_i[psi] = -(1/gamma) [v^i (v . grad psi) + d_i psi + 2 v^i psi], which is
+// minus the w-weighted transpose of the strong derivatives of the
+// interpolant (StageConst::f* documents the factors).  The phi dependence
+// goes through a real Fourier transform across the 8 lanes of the site
+// (lane r holds mode r after the analysis); radial and polar derivatives
+// act per mode; the synthesis brings the result back to phi slices.
+template <typename R>
+__device__ __forceinline__ void weak_force(const R f[25], CPtr<R> C, R gx, R gy, int l, R scale, R r0[25]) {
+  const R cl = C->cosl[l], sl = C->sinl[l];
+  const R gr = gx * cl + gy * sl;  // g . (cos phi, sin phi)
+  const R gt = gy * cl - gx * sl;  // g . (-sin phi, cos phi)
+  // this lane's mode (as a mode index r = l): 0, 4, 1c, 1s, 2c, 2s, 3c, 3s
+  const int m = l < 2 ? 4 * l : (l >> 1);
+  const bool sine = l >= 2 && (l & 1);
+  const bool modd = (m & 1) != 0;
+  const R invN = l < 2 ? (R)0.125 : (R)0.25;  // 1 / sum_l Phi_r(phi_l)^2
+  // d/dphi: cos m phi -> -m sin m phi, sin m phi -> m cos m phi; the
+  // transpose takes -m times the sine partner into a cosine mode, +m times
+  // the cosine partner into a sine mode (partners are lanes r and r ^ 1)
+  const R dphi = l < 2 ? (R)0 : (sine ? (R)m : (R)(-m));
+
+  R ph[25], out[25];
+  {
+    R ca[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) ca[d] = C->fphi[(l ^ d) * 8 + l];
+#pragma unroll
+    for (int q = 0; q < 25; ++q) {
+      const R wf = C->fw[q] * f[q];
+      R p[8], t[8];
+      group8<R>(gr * wf, p);
+      group8<R>(gt * wf, t);
+      R a = 0, b = 0;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        a += ca[d] * p[d];
+        b += ca[d] * t[d];
+      }
+      ph[q] = a;
+      out[q] = dphi * lane_mov<0xB1>(C->fc[q] * b);
+    }
+  }
+  // radial: even and odd parts in mu carry s^{m mod 2} and s^{(m+1) mod 2}
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    R he[5], ho[5], re[5], ro[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int qa = k * 5 + pr, qb = k * 5 + 4 - pr;
+      const R aa = C->fa[qa] * ph[qa];
+      if (pr < 2) {
+        const R ab = C->fa[qb] * ph[qb];
+        he[k] = (R)0.5 * (aa + ab);
+        ho[k] = (R)0.5 * (aa - ab);
+      } else {
+        he[k] = aa;
+      }
+    }
+    radial_t<R>(he, modd, C, re);
+    if (pr < 2) {
+      radial_t<R>(ho, !modd, C, ro);
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        out[k * 5 + pr] += re[k] + ro[k];
+        out[k * 5 + 4 - pr] += re[k] - ro[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) out[k * 5 + 2] += re[k];
+    }
+  }
+  // polar: similarity by (1 - mu^2)^{m/2} of the Legendre-node derivative
+  {
+    R pw0 = 1, pw1 = 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < m) {
+        pw0 *= C->fst[0];
+        pw1 *= C->fst[1];
+      }
+    const R pw[5] = {pw0, pw1, (R)1, pw1, pw0};
+    const R ipw0 = (R)1 / pw0, ipw1 = (R)1 / pw1;
+    const R ipw[5] = {ipw0, ipw1, (R)1, ipw1, ipw0};
+    const R mr = (R)m;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      R b[5], v[5];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        b[j] = C->fb[k * 5 + j] * ph[k * 5 + j];
+        v[j] = pw[j] * b[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        R acc = 0;
+#pragma unroll
+        for (int jp = 0; jp < 5; ++jp) acc += C->fDmT[j * 5 + jp] * v[jp];
+        out[k * 5 + j] += acc * ipw[j] - mr * C->fmr[j] * b[j];
+      }
+    }
+  }
+  // synthesis and the undifferentiated term
+  {
+    R cs[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) cs[d] = C->fphi[l * 8 + (l ^ d)];
+#pragma unroll
+    for (int q = 0; q < 25; ++q) {
+      R p[8];
+      group8<R>(invN * out[q], p);
+      R acc = 0;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) acc += cs[d] * p[d];
+      const R P = gr * C->fw[q] * f[q];
+      r0[q] -= scale * C->finvw[q] * (acc + C->fy[q] * P);
+    }
+  }
+}
+
 // Partial moments of one slice over the mirror pairs: w gamma^2, w gamma
 // |v_perp|, w |v_perp|^2 and w, summed over the 25 nodes (eq. (emtnew)).
 template <typename R>
@@ -375,8 +548,8 @@ __device__ __forceinline__ LaneSite lane_site(int tile, int tiles_x, int ts, int
 // XCD-aware tile order of xcd_tile.  kStream = kNT streams the new state
 // past the caches (stores, and the corrector's base slice, read once) for
 // states larger than the last-level cache; 0 keeps them cached.
-template <typename R, int STAGE, int kTY = TileRows<R>::v, int kStream = 0>
-__global__ __launch_bounds__(kTX * kTY * kSl, (MinWaves<R, STAGE>::v)) void stage_kernel(
+template <typename R, int STAGE, int kTY = TileRows<R>::v, int kStream = 0, int kForce = 0>
+__global__ __launch_bounds__(kTX * kTY * kSl, (kForce ? ForceWaves<R>::v : MinWaves<R, STAGE>::v)) void stage_kernel(
     const R* __restrict__ Fin, const R* __restrict__ Fbase, R* __restrict__ Fout,
     const double* __restrict__ lnMin, const double* __restrict__ lnMbase, double* __restrict__ lnMout,
     const double* __restrict__ scin, double* __restrict__ scout, const StageConst<R>* __restrict__ Cg,
@@ -436,6 +609,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
   double* __restrict__ lnMout = ep->lnM[i_out];
   const double* __restrict__ scin = ep->sc[i_in];
   double* __restrict__ scout = ep->sc[i_out];
+  constexpr int kForce = 0;  // the batched form has the F_eq force
   {
     const int tile_g = tile;
     {
@@ -614,11 +788,34 @@ hipError_t launch_stage(int precision, int stage, const void* Fin, const void* F
   // FP32 states whose three buffers exceed the last-level cache: 8-row
   // tiles and streaming stores (measured 5-6% faster per step at 512 x 512,
   // 20% slower at 256 x 256, where the state stays in the cache)
-  const bool big = precision == LB_FP32_FP64MATCH && (size_t)a.n_sites * kSl * 25 * sizeof(float) * 3 > kMallBytes;
+  const bool force3d = a.force_form == LB_FORCE_WEAK3D;
+  const bool big = !force3d && precision == LB_FP32_FP64MATCH &&
+                   (size_t)a.n_sites * kSl * 25 * sizeof(float) * 3 > kMallBytes;
   const int ty = precision == LB_FP32_FP64MATCH ? (big ? kBigTileRows : TileRows<float>::v) : TileRows<double>::v;
   const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
   const unsigned per = (tiles + kXcds - 1) / kXcds;
   const dim3 g(per * kXcds), b(kTX * ty * kSl);
+  if (force3d) {
+    // the weak-form 3-D force: default tiles, cached stores
+    if (precision == LB_FP32_FP64MATCH) {
+      const auto* C = static_cast<const StageConst<float>*>(sc);
+      if (stage == 0)
+        hipLaunchKernelGGL((stage_kernel<float, 0, TileRows<float>::v, 0, 1>), g, b, 0, s, (const float*)Fin,
+                           (const float*)Fbase, (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+      else
+        hipLaunchKernelGGL((stage_kernel<float, 1, TileRows<float>::v, 0, 1>), g, b, 0, s, (const float*)Fin,
+                           (const float*)Fbase, (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+    } else {
+      const auto* C = static_cast<const StageConst<double>*>(sc);
+      if (stage == 0)
+        hipLaunchKernelGGL((stage_kernel<double, 0, TileRows<double>::v, 0, 1>), g, b, 0, s, (const double*)Fin,
+                           (const double*)Fbase, (double*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+      else
+        hipLaunchKernelGGL((stage_kernel<double, 1, TileRows<double>::v, 0, 1>), g, b, 0, s, (const double*)Fin,
+                           (const double*)Fbase, (double*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+    }
+    return hipGetLastError();
+  }
   if (precision == LB_FP32_FP64MATCH) {
     const auto* C = static_cast<const StageConst<float>*>(sc);
     if (big) {

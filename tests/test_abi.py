@@ -245,3 +245,12 @@ def test_host_strong_form_operators_match_oracle(z0):
     assert np.max(np.abs(D2 - lat.D2)) < 1e-11 * np.max(np.abs(lat.D2))
     p.operator_form = 7
     assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_force_form_validation():
+    # LB_FORCE_WEAK3D is a valid parameter set; unknown force forms are not
+    p = lb.make_params(8, 8, 0.2, force_form=lb.LB_FORCE_WEAK3D)
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) > 0
+    p.force_form = 2
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) == 0
+    assert "force_form" in lb.last_error()

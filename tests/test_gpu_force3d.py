@@ -1,0 +1,147 @@
+"""GPU parity of the weak-form 3-D mass-gradient force (force_form
+LB_FORCE_WEAK3D; paper eq. (fansatz) test space, eq. (Bmilne) force term)
+against the FP64 oracle built with the same force (oracle.force3d).
+
+Tolerances as for the plain step: 1e-10 per FP64 step (table interpolation
+of the EoS), 1e-5 relative in T^{mu nu} per FP32 step.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1108_5561_amd as lb  # noqa: E402
+from oracle import step as st  # noqa: E402
+from oracle.eos import HBARC, TanhEntropyEoS  # noqa: E402
+from oracle.lattice import Lattice  # noqa: E402
+from paper_1108_5561_amd import workloads as wl  # noqa: E402
+
+from _helpers import tmunu_rel_err  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lat3():
+    return Lattice(5, 5, 4, 1.0, force="weak3d")
+
+
+@pytest.fixture(scope="module")
+def eos():
+    return TanhEntropyEoS()
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def _state(lat, eos, nx, ny, dx, seed):
+    # a hot spot with flow, F and ln M perturbed off equilibrium
+    e0 = float(eos.eps(0.4)) / HBARC ** 3 * wl.gaussian_shape(nx, ny, dx, 0.25 * nx * dx)
+    ux, uy = wl.random_flow(nx, ny, 0.15, seed=seed)
+    F, l = st.init_state(lat, eos, e0, ux, uy)
+    rng = np.random.default_rng(seed)
+    F = F * (1 + 0.05 * rng.random(F.shape))
+    l = l + 0.02 * rng.standard_normal(l.shape)
+    return e0, F, l
+
+
+def _ctx(nx, ny, dx, e0, precision, eta, force=lb.LB_FORCE_WEAK3D):
+    p = lb.make_params(nx, ny, dx, precision=precision, eta_over_s=eta, force_form=force)
+    return lb.Context(p, gpu(e0))
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 23), (8, 5), (2, 3)])
+def test_one_step_fp64(lat3, eos, nx, ny):
+    dx, dtau, eta = 0.2, 0.01, 0.08
+    e0, F, l = _state(lat3, eos, nx, ny, dx, seed=nx * 10 + ny)
+    print(f"weak3d FP64 one step {nx}x{ny}", flush=True)
+    c = _ctx(nx, ny, dx, e0, lb.LB_FP64, eta)
+    c.set_state(gpu(F), gpu(l), 0.7)
+    prm = st.Params(dx=dx, eta_over_s=eta)
+    Fo, lo = st.heun_step(lat3, eos, prm, F, l, 0.7, dtau)
+    c.step(1, dtau)
+    Fg, lg, _ = c.get_state()
+    assert c.status() == lb.LB_OK
+    assert np.max(np.abs(cpu(Fg) - Fo)) < 1e-10 * Fo.max()
+    assert np.max(np.abs(cpu(lg) - lo)) < 1e-11
+    assert tmunu_rel_err(cpu(c.moments()), st.observables(lat3, eos, prm, Fo, lo)) < 1e-10
+
+
+def test_one_step_fp32(lat3, eos):
+    nx, ny, dx, dtau, eta = 37, 23, 0.2, 0.01, 0.08
+    e0, F, l = _state(lat3, eos, nx, ny, dx, seed=3)
+    print("weak3d FP32 one step 37x23", flush=True)
+    c = _ctx(nx, ny, dx, e0, lb.LB_FP32_FP64MATCH, eta)
+    c.set_state(gpu(F), gpu(l), 0.7)
+    F32 = F.astype(np.float32).astype(np.float64)
+    prm = st.Params(dx=dx, eta_over_s=eta)
+    Fo, lo = st.heun_step(lat3, eos, prm, F32, l, 0.7, dtau)
+    c.step(1, dtau)
+    _, lg, _ = c.get_state()
+    assert c.status() == lb.LB_OK
+    assert tmunu_rel_err(cpu(c.moments()), st.observables(lat3, eos, prm, Fo, lo)) < 1e-5
+    assert np.max(np.abs(cpu(lg) - lo)) < 1e-6
+
+
+def test_force_form_changes_the_step(lat3, eos):
+    # the two force forms differ by far more than the parity bar, so the
+    # parity above is not met by the F_eq path
+    nx, ny, dx, dtau, eta = 16, 12, 0.2, 0.01, 0.08
+    e0, F, l = _state(lat3, eos, nx, ny, dx, seed=21)
+    out = []
+    for force in (lb.LB_FORCE_FEQ, lb.LB_FORCE_WEAK3D):
+        c = _ctx(nx, ny, dx, e0, lb.LB_FP64, eta, force)
+        c.set_state(gpu(F), gpu(l), 0.7)
+        c.step(1, dtau)
+        out.append(cpu(c.get_state()[0]))
+    assert np.max(np.abs(out[0] - out[1])) > 1e-6 * np.max(np.abs(out[0]))
+
+
+def test_hot_spot_run_fp64_and_fp32(lat3, eos):
+    # 40 steps of a hot-spot state (spots of 0.8 fm on 0.12 fm cells): FP64
+    # against the oracle, FP32 against FP64
+    nx, ny, dx, dtau, eta = 24, 20, 0.12, 0.00375, 0.16
+    rng = np.random.default_rng(8)
+    xs = (np.arange(nx) - nx / 2 + 0.5) * dx
+    ys = (np.arange(ny) - ny / 2 + 0.5) * dx
+    X, Y = np.meshgrid(xs, ys)
+    e0 = 0.517 + sum(a * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * 0.8 ** 2))
+                     for a, cx, cy in zip(rng.exponential(10.0, 4), rng.uniform(-1, 1, 4), rng.uniform(-1, 1, 4)))
+    print("weak3d hot-spot run 24x20, 40 steps", flush=True)
+    prm = st.Params(dx=dx, eta_over_s=eta)
+    F, l = st.init_state(lat3, eos, e0)
+    tau = 0.5
+    for _ in range(40):
+        F, l = st.heun_step(lat3, eos, prm, F, l, tau, dtau)
+        tau += dtau
+    ref = st.observables(lat3, eos, prm, F, l)
+    c64 = _ctx(nx, ny, dx, e0, lb.LB_FP64, eta)
+    c32 = _ctx(nx, ny, dx, e0, lb.LB_FP32_FP64MATCH, eta)
+    c64.step(40, dtau)
+    c32.step(40, dtau)
+    assert c64.status() == lb.LB_OK
+    assert c32.status() == lb.LB_OK
+    o64, o32 = cpu(c64.moments()), cpu(c32.moments())
+    assert tmunu_rel_err(o64, ref) < 1e-9
+    assert tmunu_rel_err(o32, o64) < 1e-4
+
+
+def test_batched_and_adjoint_forms_reject_the_3d_force(eos):
+    nx, ny, dx = 8, 8, 0.2
+    e0 = float(eos.eps(0.3)) / HBARC ** 3 * np.ones((ny, nx))
+    c = _ctx(nx, ny, dx, e0, lb.LB_FP64, 0.1)
+    ws = c.adjoint_workspace()
+    F, lnM, _ = c.get_state()
+    with pytest.raises(lb.LbError) as ei:
+        c.adjoint_forward_step(0.5, 0.005, F, lnM, ws)
+    assert ei.value.code == lb.LB_E_NOTIMPL
+    p = lb.make_params(nx, ny, dx, force_form=lb.LB_FORCE_WEAK3D)
+    with pytest.raises(lb.LbError) as ei:
+        lb.Batch(p, [(nx, ny, dx, 0.1)], [gpu(e0)])
+    assert ei.value.code == lb.LB_E_NOTIMPL
