@@ -64,10 +64,11 @@ def measured_traffic(kernel):
     return float(k.group(1)) * 1024.0 * f_scale + float(k.group(2)) * 1024.0 * w_scale
 
 
-def run_gpu(lb, wl, torch, precision, steps, warmup):
+def run_gpu(lb, wl, torch, precision, steps, warmup, force=0):
     w = wl.WORKLOADS["prec"]
     prec = lb.LB_FP32_FP64MATCH if precision == "fp32" else lb.LB_FP64
-    p = lb.make_params(w["nx"], w["ny"], w["dx"], tau0_fm=w["tau0"], eta_over_s=w["eta_over_s"], precision=prec)
+    p = lb.make_params(w["nx"], w["ny"], w["dx"], tau0_fm=w["tau0"], eta_over_s=w["eta_over_s"], precision=prec,
+                       force_form=force)
     e_peak = lb.eos_eval(p, [0.4])[0, 0] / lb.HBARC ** 3
     e0 = e_peak * wl.gaussian_shape(w["nx"], w["ny"], w["dx"], 2.0) * wl.white_noise_factor(w["nx"], w["ny"])
     c = lb.Context(p, torch.from_numpy(e0).to("cuda:0"))
@@ -92,6 +93,18 @@ def run_gpu(lb, wl, torch, precision, steps, warmup):
     n_sites = w["nx"] * w["ny"]
     obs = c.moments().cpu().numpy()
     return dict(ms=ms, wall=wall, n_sites=n_sites, pred_ms=ms_pred, corr_ms=ms_corr, obs=obs, e0=e0, dtau=dtau)
+
+
+def run_force3d(lb, wl, torch, steps=200, warmup=10):
+    """The plain FP32 step with the weak-form 3-D mass-gradient force
+    (LB_FORCE_WEAK3D) on the same 256 x 256 workload: throughput, stage
+    kernel durations, and the relative difference of T^{mu nu} from the
+    F_eq-force step after the same steps."""
+    r = run_gpu(lb, wl, torch, "fp32", steps, warmup, force=lb.LB_FORCE_WEAK3D)
+    ref = run_gpu(lb, wl, torch, "fp32", steps, warmup)
+    return {"value": steps * r["n_sites"] / (r["ms"] / 1e3), "unit": "site-updates/s",
+            "ms_per_step": r["ms"] / steps, "pred_ms": r["pred_ms"], "corr_ms": r["corr_ms"],
+            "steps": steps, "tmunu_rel_diff_vs_feq_force": tmunu_rel_err(r["obs"], ref["obs"])}
 
 
 def run_batch(lb, wl, torch, steps=96):
@@ -266,6 +279,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-form measurement")
+    ap.add_argument("--no-force3d", action="store_true", help="skip the weak-form 3-D force measurement")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the differentiable-form measurement (one JSON object)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -319,6 +333,7 @@ def main():
 
     batch = None if args.no_batch else optional(run_batch)
     adjoint = None if args.no_adjoint else optional(run_adjoint)
+    force3d = None if args.no_force3d else optional(run_force3d)
 
     out = {
         "metric": "site-updates/s & HBM GB/s: FP32+FP64-match vs FP64 step at 1e-5 rel err",
@@ -346,6 +361,8 @@ def main():
             batch, vs_plain_fp64_step=batch["value"] / sups64),
         "differentiable": adjoint if adjoint is None or "error" in adjoint else dict(
             adjoint, vs_plain_fp64_step=adjoint["gradient_site_updates_per_s"] / sups64),
+        "force3d": force3d if force3d is None or "error" in force3d else dict(
+            force3d, vs_feq_force_step=force3d["value"] / sups32),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

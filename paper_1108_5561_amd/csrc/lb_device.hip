@@ -67,7 +67,10 @@ template <typename R, int STAGE> struct MinWaves {
 };
 template <int STAGE> struct MinWaves<double, STAGE> { static constexpr int v = LB_WAVES_PER_EU_F64; };
 // with the weak-form 3-D force (about twice the registers in flight)
-template <typename R> struct ForceWaves { static constexpr int v = 2; };
+#ifndef LB_FORCE_WAVES_F32
+#define LB_FORCE_WAVES_F32 2
+#endif
+template <typename R> struct ForceWaves { static constexpr int v = LB_FORCE_WAVES_F32; };
 template <> struct ForceWaves<double> { static constexpr int v = 1; };
 
 // A distribution buffer is read and written as one raw buffer: one
@@ -258,32 +261,35 @@ __device__ __forceinline__ EosTable load_table(const EosTable* p) {
   return t;
 }
 // ---- weak-form 3-D mass-gradient force ---------------------------------
-// Value of lane (lane ^ d) of the 8-lane group (one site's phi slices) for
-// d = 0 .. 7: xor 1, 2, 3 are quad permutations, xor 7 the half-row mirror,
-// xor 4, 5, 6 quad permutations of the mirrored value.
-template <int CTRL>
-__device__ __forceinline__ float lane_mov(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+// Value of lane (lane ^ 1) (the cos/sin partner mode) of the 8-lane group.
+template <typename R>
+__device__ __forceinline__ R partner_lane(R v);
+template <>
+__device__ __forceinline__ float partner_lane<float>(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
-template <int CTRL>
-__device__ __forceinline__ double lane_mov(double v) {
+template <>
+__device__ __forceinline__ double partner_lane<double>(double v) {
   const uint64_t b = (uint64_t)__double_as_longlong(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0xB1, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0xB1, 0xF, 0xF, false);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
+
+// The eight phi-slice values of node q of this lane's site from the wave's
+// exchange area sw[25][64] (lane-in-wave order), two 16-byte reads per
+// 4 values; the site's lanes read the same addresses (broadcast).
 template <typename R>
-__device__ __forceinline__ void group8(R v, R p[8]) {
-  constexpr int kX1 = 0xB1, kX2 = 0x4E, kX3 = 0x1B, kMirror = 0x141;
-  p[0] = v;
-  p[1] = lane_mov<kX1>(v);
-  p[2] = lane_mov<kX2>(v);
-  p[3] = lane_mov<kX3>(v);
-  const R h = lane_mov<kMirror>(v);
-  p[7] = h;
-  p[6] = lane_mov<kX1>(h);
-  p[5] = lane_mov<kX2>(h);
-  p[4] = lane_mov<kX3>(h);
+__device__ __forceinline__ void site_values(const R* sw, int q, int sb, R v[8]) {
+  constexpr int V = 16 / (int)sizeof(R);
+  typedef R Vec __attribute__((ext_vector_type(V)));
+  const Vec* p = reinterpret_cast<const Vec*>(sw + q * 64 + sb);
+#pragma unroll
+  for (int i = 0; i < 8 / V; ++i) {
+    const Vec x = p[i];
+#pragma unroll
+    for (int c = 0; c < V; ++c) v[i * V + c] = x[c];
+  }
 }
 
 // radial part of the transposed strong-form derivative for one mu column
@@ -311,43 +317,55 @@ __device__ __forceinline__ void radial_t(const R h[5], bool e, CPtr<R> C, R r[5]
 // b_i[psi] = -(1/gamma) [v^i (v . grad psi) + d_i psi + 2 v^i psi], which is
 // minus the w-weighted transpose of the strong derivatives of the
 // interpolant (StageConst::f* documents the factors).  The phi dependence
-// goes through a real Fourier transform across the 8 lanes of the site
-// (lane r holds mode r after the analysis); radial and polar derivatives
-// act per mode; the synthesis brings the result back to phi slices.
+// goes through a real Fourier transform over the site's 8 lanes (lane r
+// holds mode r after the analysis), exchanged through the wave's LDS area
+// sw[25][64] (lw = lane in the wave); radial and polar derivatives act per
+// mode; the synthesis brings the result back to phi slices.  Every thread
+// of the block calls it (block barriers).
 template <typename R>
-__device__ __forceinline__ void weak_force(const R f[25], CPtr<R> C, R gx, R gy, int l, R scale, R r0[25]) {
+__device__ __forceinline__ void weak_force(const R f[25], CPtr<R> C, R gx, R gy, int l, R scale, R r0[25], R* sw,
+                                           int lw) {
+  const int sb = lw & 56;  // first lane of this site in the wave
   const R cl = C->cosl[l], sl = C->sinl[l];
   const R gr = gx * cl + gy * sl;  // g . (cos phi, sin phi)
-  const R gt = gy * cl - gx * sl;  // g . (-sin phi, cos phi)
   // this lane's mode (as a mode index r = l): 0, 4, 1c, 1s, 2c, 2s, 3c, 3s
   const int m = l < 2 ? 4 * l : (l >> 1);
   const bool sine = l >= 2 && (l & 1);
   const bool modd = (m & 1) != 0;
-  const R invN = l < 2 ? (R)0.125 : (R)0.25;  // 1 / sum_l Phi_r(phi_l)^2
   // d/dphi: cos m phi -> -m sin m phi, sin m phi -> m cos m phi; the
   // transpose takes -m times the sine partner into a cosine mode, +m times
   // the cosine partner into a sine mode (partners are lanes r and r ^ 1)
   const R dphi = l < 2 ? (R)0 : (sine ? (R)m : (R)(-m));
 
   R ph[25], out[25];
-  {
-    R ca[8];
+  // analysis of g_r w F and g_t w F (g_r = g . (cos, sin), g_t = g . (-sin,
+  // cos)) from one exchange of F: with A_r = sum_l Phi_r(phi_l) cos(phi_l) F_l
+  // and B_r the same with sin(phi_l), the modes are w (g_x A + g_y B) and
+  // w (g_y A - g_x B)
 #pragma unroll
-    for (int d = 0; d < 8; ++d) ca[d] = C->fphi[(l ^ d) * 8 + l];
+  for (int q = 0; q < 25; ++q) sw[q * 64 + lw] = f[q];
+  __syncthreads();
+  {
+    R ca[8], cb[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      const R ph_ = C->fphi[d * 8 + l];
+      ca[d] = ph_ * C->cosl[d];
+      cb[d] = ph_ * C->sinl[d];
+    }
 #pragma unroll
     for (int q = 0; q < 25; ++q) {
-      const R wf = C->fw[q] * f[q];
-      R p[8], t[8];
-      group8<R>(gr * wf, p);
-      group8<R>(gt * wf, t);
-      R a = 0, b = 0;
+      R v[8];
+      site_values<R>(sw, q, sb, v);
+      R A = 0, B = 0;
 #pragma unroll
       for (int d = 0; d < 8; ++d) {
-        a += ca[d] * p[d];
-        b += ca[d] * t[d];
+        A += ca[d] * v[d];
+        B += cb[d] * v[d];
       }
-      ph[q] = a;
-      out[q] = dphi * lane_mov<0xB1>(C->fc[q] * b);
+      const R wq = C->fw[q];
+      ph[q] = wq * (gx * A + gy * B);
+      out[q] = dphi * partner_lane<R>(C->fc[q] * (wq * (gy * A - gx * B)));
     }
   }
   // radial: even and odd parts in mu carry s^{m mod 2} and s^{(m+1) mod 2}
@@ -409,18 +427,23 @@ __device__ __forceinline__ void weak_force(const R f[25], CPtr<R> C, R gx, R gy,
       }
     }
   }
-  // synthesis and the undifferentiated term
+  // synthesis (1/sum_l Phi_r(phi_l)^2 folded into the coefficients) and the
+  // undifferentiated term
+  __syncthreads();  // every lane has read F
+#pragma unroll
+  for (int q = 0; q < 25; ++q) sw[q * 64 + lw] = out[q];
+  __syncthreads();
   {
     R cs[8];
 #pragma unroll
-    for (int d = 0; d < 8; ++d) cs[d] = C->fphi[l * 8 + (l ^ d)];
+    for (int d = 0; d < 8; ++d) cs[d] = C->fphi[l * 8 + d] * (d < 2 ? (R)0.125 : (R)0.25);
 #pragma unroll
     for (int q = 0; q < 25; ++q) {
-      R p[8];
-      group8<R>(invN * out[q], p);
+      R v[8];
+      site_values<R>(sw, q, sb, v);
       R acc = 0;
 #pragma unroll
-      for (int d = 0; d < 8; ++d) acc += cs[d] * p[d];
+      for (int d = 0; d < 8; ++d) acc += cs[d] * v[d];
       const R P = gr * C->fw[q] * f[q];
       r0[q] -= scale * C->finvw[q] * (acc + C->fy[q] * P);
     }
@@ -555,6 +578,8 @@ __global__ __launch_bounds__(kTX * kTY * kSl, (kForce ? ForceWaves<R>::v : MinWa
     const double* __restrict__ scin, double* __restrict__ scout, const StageConst<R>* __restrict__ Cg,
     const EosTable* __restrict__ tbg, const StageArgs a, int* __restrict__ err) {
   __shared__ double s_mom[7][kTX * kTY];
+  // exchange area of the 3-D force: per wave 25 nodes x 64 lanes
+  __shared__ __attribute__((aligned(16))) R s_force[kForce ? kTY * 25 * 64 : 1];
   const int n_tiles = ((a.nx + kTX - 1) / kTX) * ((a.ny + kTY - 1) / kTY);
   const int tile = xcd_tile(n_tiles);
   if (tile >= n_tiles) return;  // whole block
@@ -610,6 +635,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
   const double* __restrict__ scin = ep->sc[i_in];
   double* __restrict__ scout = ep->sc[i_out];
   constexpr int kForce = 0;  // the batched form has the F_eq force
+  R* const s_force = nullptr;
   {
     const int tile_g = tile;
     {
