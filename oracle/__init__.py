@@ -16,6 +16,9 @@ Non-Ideal Equation of State", arXiv:1108.5561) computes:
   time from the Chapman-Enskog shear viscosity of Sec. IV.A.
 * ``lattice``     - node table, weights and the weak-form momentum-derivative
   operators S1, S2 of Sec. IV.D (projection onto L_m(cos theta) R_l(cosh xi)).
+* ``force3d``     - the weak-form 3-D operator of the mass-gradient force on
+  the test space of eq. (fansatz) (harmonics of v/|v| times powers of
+  sinh xi times polynomials in cosh xi).
 * ``step``        - one Heun (predictor / corrector) step of the Milne
   lattice-Boltzmann scheme of Sec. IV.D, extended to a periodic transverse
   (x, y) lattice; Landau matching of eq. (sanity).
