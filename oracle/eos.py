@@ -166,6 +166,43 @@ class QuasiparticleEoS:
             return 5.0 * eta_over_s / T * HBARC
         return eta_over_s * self.s(T) / self.h(T) * HBARC
 
+    # ---- conserved particle number (eqs. (epsp), (sanity) with mu != 0) ----
+    def n_kin_eq(self, T):
+        """Particle density at mu = 0, n0 = Z M^2 T K_2(z) / (2 pi^2) (eq. (epsp)).
+        At chemical potential mu the Boltzmann factor exp(mu/T) multiplies
+        n, eps - B and p + B alike."""
+        T = np.asarray(T, dtype=float)
+        z = self.z_of_T(T).reshape(T.shape)
+        return self.Z * z ** 2 * T ** 3 * kv(2, z) / (2 * PI2)
+
+    def T_alpha_from_eps_n(self, e, n, T_lo=0.05, T_hi=3.0):
+        """(T, alpha = mu/T) with eps_kin_eq = e and n = n_kin (eq. (sanity)).
+
+        The fugacity exp(alpha) cancels in the ratio eps_kin_eq / n =
+        eps0(T) / n0(T) (= 3 T + M K_1/K_2 for a constant mass, increasing in
+        T), so T is its root and alpha = ln(n / n0(T))."""
+        e = np.atleast_1d(np.asarray(e, dtype=float))
+        n = np.atleast_1d(np.asarray(n, dtype=float))
+        if np.any(n <= 0) or np.any(e <= 0):
+            raise FloatingPointError("non-positive energy or particle density")
+        f = lambda T, r: self.eps_kin_eq(T) / self.n_kin_eq(T) - r
+        T = _root(f, np.full_like(e, T_lo), np.full_like(e, T_hi), args=(e / n,))
+        return T, np.log(n / self.n_kin_eq(T))
+
+    def tau_R_mu(self, T, alpha, eta_over_s, rule="ce"):
+        """tau_R at chemical potential mu = alpha T in fm/c.  CE rule:
+        eta = (eta/s) s(T, mu), eta/tau_R = h(T, mu); for the Boltzmann gas
+        s(T, mu) = exp(alpha) (s0 - alpha n0) (s = dp/dT at fixed mu with
+        p = exp(mu/T) p0(T), p0 = n0 T) and h(T, mu) = exp(alpha) h0(T)."""
+        T = np.atleast_1d(np.asarray(T, dtype=float))
+        alpha = np.atleast_1d(np.asarray(alpha, dtype=float))
+        if rule == "massless":
+            return 5.0 * eta_over_s / T * HBARC
+        s_mu = self.s(T) - alpha * self.n_kin_eq(T)
+        if np.any(s_mu <= 0):
+            raise FloatingPointError("non-positive entropy density at this chemical potential")
+        return eta_over_s * s_mu / self.h(T) * HBARC
+
     # ---- inversions used by the lattice-Boltzmann step ----
     def T_from_eps_kin_eq(self, e, T_lo=0.05, T_hi=3.0):
         """Unique T with eps_kin_eq(T) = e (monotone in T), on [T_lo, T_hi]."""

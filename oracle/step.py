@@ -66,6 +66,7 @@ class Params:
     metric: int = METRIC_MILNE
     T_lo: float = 0.05
     T_hi: float = 3.0
+    conserve_n: bool = False  # match n = u_a N^a as well: T and mu/T per site
 
 
 def landau(Tk3):
@@ -117,11 +118,17 @@ def rhs(lat, eos, prm: Params, F, lnM, tau):
     ut, ux, uy = u[0], u[1], u[2]
 
     # 3. temperature and EoS functions
-    T = eos.T_from_eps_kin_eq(lam.ravel(), prm.T_lo, prm.T_hi).reshape(lam.shape)
+    alpha = np.zeros_like(lam)
+    if prm.conserve_n:
+        T, alpha = _match_n(lat, eos, prm, F, lnM, u, lam)
+    else:
+        T = eos.T_from_eps_kin_eq(lam.ravel(), prm.T_lo, prm.T_hi).reshape(lam.shape)
     M_eq = eos.M(T)
     beta = eos.beta(T)
     if np.isinf(prm.eta_over_s):
         inv_tauR = np.zeros_like(T)
+    elif prm.conserve_n:
+        inv_tauR = 1.0 / eos.tau_R_mu(T.ravel(), alpha.ravel(), prm.eta_over_s, prm.taur_rule).reshape(T.shape)
     else:
         inv_tauR = 1.0 / eos.tau_R(T.ravel(), prm.eta_over_s, prm.taur_rule).reshape(T.shape)
 
@@ -131,7 +138,7 @@ def rhs(lat, eos, prm: Params, F, lnM, tau):
     sh2 = (lat.gamma ** 2 - 1.0)[bc]
     E_eq = np.sqrt(M_eq ** 2 + M ** 2 * sh2)
     uv = ux * vx + uy * vy
-    F_eq = eos.Z * np.exp(-(ut * E_eq - M * uv) / T)
+    F_eq = eos.Z * np.exp(alpha - (ut * E_eq - M * uv) / T)
 
     # 5. BGK
     uV = ut * gam - uv
@@ -179,8 +186,22 @@ def rhs(lat, eos, prm: Params, F, lnM, tau):
 
     # 11. dF/dtau
     K = R0 + X * S2
-    diag = dict(T=T, u=u, lam=lam, M_eq=M_eq, beta=beta, inv_tauR=inv_tauR)
+    diag = dict(T=T, u=u, lam=lam, M_eq=M_eq, beta=beta, inv_tauR=inv_tauR, alpha=alpha)
     return K, X, diag
+
+
+def _match_n(lat, eos, prm, F, lnM, u, lam):
+    """Conserved particle number (eq. (sanity), second condition): with the
+    Landau u, n = u_a N^a (N^a of eq. (NTdisc)), and T, alpha = mu/T from
+    eps_kin_eq(T, mu) = lambda, n(T, mu) = n (eq. (epsp)).  Only for a
+    constant mass: a mass depending on T alone is thermodynamically
+    consistent (eq. (cdef)) at mu != 0 only if it is constant."""
+    if np.any(eos.beta(np.array([0.2, 0.4])) != 0):
+        raise ValueError("conserved particle number needs the constant-mass equation of state")
+    _, Nk = lat.moments(F, lnM)
+    n = u[0] * Nk[0] - u[1] * Nk[1] - u[2] * Nk[2]
+    T, alpha = eos.T_alpha_from_eps_n(lam.ravel(), n.ravel(), prm.T_lo, prm.T_hi)
+    return T.reshape(lam.shape), alpha.reshape(lam.shape)
 
 
 def heun_step(lat, eos, prm, F, lnM, tau, dtau):
@@ -192,14 +213,16 @@ def heun_step(lat, eos, prm, F, lnM, tau, dtau):
     return F + 0.5 * dtau * (K0 + K1), lnM + 0.5 * dtau * (X0 + X1)
 
 
-def init_state(lat, eos, e0_GeVfm3, ux0=None, uy0=None, T_lo=0.05, T_hi=3.0):
+def init_state(lat, eos, e0_GeVfm3, ux0=None, uy0=None, T_lo=0.05, T_hi=3.0, alpha0=0.0):
     """Local equilibrium initial state (reading of Sec. IV.D: the initial
     condition consists of the distribution plus T and M).
 
     T0 is the largest root of eps_EoS(T) = e0; M = M(T0); u^tau = sqrt(1 + u_perp^2);
-    F = Z exp(-(u . P_n)/T0) with P_n = M V_n.
+    F = Z exp(-(u . P_n)/T0) with P_n = M V_n.  With a chemical potential
+    mu0 = alpha0 T0 (constant mass, B = 0) eps = exp(alpha0) eps0(T0) = e0 and
+    F carries the factor exp(alpha0).
     """
-    e0 = np.asarray(e0_GeVfm3, dtype=float) * HBARC ** 3
+    e0 = np.asarray(e0_GeVfm3, dtype=float) * HBARC ** 3 * np.exp(-alpha0)
     sh = e0.shape
     T0 = eos.T_from_eps_largest(e0.ravel(), T_lo, T_hi).reshape(sh)
     M = eos.M(T0)
@@ -208,7 +231,7 @@ def init_state(lat, eos, e0_GeVfm3, ux0=None, uy0=None, T_lo=0.05, T_hi=3.0):
     ut = np.sqrt(1.0 + ux ** 2 + uy ** 2)
     bc = (slice(None), None, None)
     uP = M * (ut * lat.gamma[bc] - ux * lat.V[1][bc] - uy * lat.V[2][bc])
-    F = eos.Z * np.exp(-uP / T0)
+    F = eos.Z * np.exp(alpha0 - uP / T0)
     return F, np.log(M)
 
 
@@ -221,7 +244,10 @@ def observables(lat, eos, prm, F, lnM):
     """
     Tk, Nk = lat.moments(F, lnM)
     u, lam = landau(Tk[:3, :3])
-    T = eos.T_from_eps_kin_eq(lam.ravel(), prm.T_lo, prm.T_hi).reshape(lam.shape)
+    if prm.conserve_n:
+        T, _ = _match_n(lat, eos, prm, F, lnM, u, lam)
+    else:
+        T = eos.T_from_eps_kin_eq(lam.ravel(), prm.T_lo, prm.T_hi).reshape(lam.shape)
     B = eos.B(T)
     c3 = HBARC ** 3
     out = np.stack([
