@@ -66,6 +66,7 @@ enum { LB_METRIC_MILNE = 0, LB_METRIC_MINKOWSKI = 1 };
 enum { LB_EOS_TANH_P = 0, LB_EOS_CONST_MASS = 1, LB_EOS_TANH_S = 2, LB_EOS_TABLE = 3 };
 enum { LB_OPS_WEAK = 0, LB_OPS_STRONG = 1 };  /* momentum-derivative operators S1, S2 */
 enum { LB_FORCE_FEQ = 0, LB_FORCE_WEAK3D = 1 };  /* mass-gradient force of eq. (Bmilne) */
+enum { LB_N_FREE = 0, LB_N_CONSERVED = 1 };      /* particle number, eq. (sanity) */
 
 /*
  * Problem statement (Sec. IV.D: an initial condition is the distribution plus
@@ -141,6 +142,21 @@ typedef struct lb_params {
    *   twice the arithmetic.  lb_step only: the batched and adjoint entry
    *   points return LB_E_NOTIMPL for it. */
   int32_t force_form;
+  /* LB_N_FREE: the equilibrium is matched to the energy density only (mu = 0,
+   * as in the paper's runs).  LB_N_CONSERVED: also to the particle density
+   * n = u_a N^a (second condition of eq. (sanity)), so that the collisions
+   * conserve the current N^a; each site then has a temperature and a
+   * chemical potential mu, F_eq carries exp(mu/T) (eq. (epsp)) and the CE
+   * relaxation time uses s(T, mu) and h(T, mu).  Requires eos_kind
+   * LB_EOS_CONST_MASS: a mass depending on T alone is thermodynamically
+   * consistent (eq. (cdef)) at mu != 0 only if it is constant.  The site's
+   * mu/T follows from the outputs as ln(n / n0(T)), n0 the density at mu = 0.
+   * lb_step and lb_moments only: the batched and adjoint entry points return
+   * LB_E_NOTIMPL for it. */
+  int32_t particle_number;
+  /* mu/T of the initial state (uniform; lb_init): eps(T0, mu0) = e0 and
+   * F = Z exp(mu0/T0 - u.P/T0).  Must be 0 unless LB_N_CONSERVED. */
+  double mu_over_T0;
 } lb_params;
 
 /*

@@ -24,6 +24,7 @@ LB_METRIC_MILNE, LB_METRIC_MINKOWSKI = 0, 1
 LB_EOS_TANH_P, LB_EOS_CONST_MASS, LB_EOS_TANH_S, LB_EOS_TABLE = 0, 1, 2, 3
 LB_OPS_WEAK, LB_OPS_STRONG = 0, 1
 LB_FORCE_FEQ, LB_FORCE_WEAK3D = 0, 1
+LB_N_FREE, LB_N_CONSERVED = 0, 1
 HBARC = 0.1973269804  # GeV fm
 N_OBS = 14
 OBS_NAMES = ("Ttt", "Ttx", "Tty", "Txx", "Txy", "Tyy", "TYY", "Nt", "Nx", "Ny", "T", "ux", "uy", "M")
@@ -51,6 +52,7 @@ class lb_params(ctypes.Structure):
         ("eos_T_GeV", ctypes.POINTER(ctypes.c_double)), ("eos_s_GeV3", ctypes.POINTER(ctypes.c_double)),
         ("eos_p0_GeV4", ctypes.c_double), ("eos_n", ctypes.c_int32),
         ("operator_form", ctypes.c_int32), ("force_form", ctypes.c_int32),
+        ("particle_number", ctypes.c_int32), ("mu_over_T0", ctypes.c_double),
     ]
 
 
@@ -137,7 +139,7 @@ def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, 
                 taur_rule=LB_TAUR_CE, eos_kind=LB_EOS_TANH_S, eos_g=37.0, eos_Tc_GeV=0.17, eos_width_GeV=0.02,
                 eos_mass_GeV=0.0, kappa=2.0, Z=None, z0=1.0, n_xi=5, n_theta=5, n_phi=4,
                 T_min_GeV=0.05, T_max_GeV=3.0, eos_table=None, operator_form=LB_OPS_WEAK,
-                force_form=LB_FORCE_FEQ):
+                force_form=LB_FORCE_FEQ, particle_number=LB_N_FREE, mu_over_T0=0.0):
     """Parameters of a run.  eos_table = (T [GeV], s [GeV^3], p(T[0]) [GeV^4])
     selects LB_EOS_TABLE with the caller's entropy density (the arrays are
     kept alive by the returned object)."""
@@ -159,6 +161,7 @@ def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, 
     p.T_min_GeV, p.T_max_GeV = T_min_GeV, T_max_GeV
     p.operator_form = operator_form
     p.force_form = force_form
+    p.particle_number, p.mu_over_T0 = particle_number, mu_over_T0
     return p
 
 

@@ -126,6 +126,45 @@ __device__ inline bool eos_from_lambda(const EosTable& tb, double lam, EosAt* o)
   return ok;
 }
 
+// Conserved particle number (eqs. (sanity), (epsp); constant mass): the
+// fugacity exp(mu/T) multiplies eps - B and n alike, so T solves
+// ln(eps_kin/n) = lnEk(u) - lnN(u), increasing and convex in u = ln T;
+// Newton starts from the bound eps/n > 3T (above the root) and converges
+// from above.  Then alpha = mu/T = ln n - lnN(u) and, for the CE rule,
+// q(T, mu) = T s(T, mu)/h(T, mu) = q - alpha T n0/h.  False if lambda or
+// n is not positive, the root leaves the table, or s(T, mu) <= 0.
+__device__ inline bool eos_mu(const EosTable& tb, double lam, double n, EosAt* o, double* alpha) {
+  bool ok = lam > 0.0 && n > 0.0 && isfinite(lam) && isfinite(n);
+  const double g = ok ? log(lam / n) : 0.0;
+  double u = ok ? log(lam / (3.0 * n)) : tb.u_lo;
+  u = fmin(fmax(u, tb.u_lo), tb.u_hi);
+  double t, w[4], dw[4], res = 0.0;
+  int i = 0;
+  for (int it = 0; it < 60; ++it) {
+    i = eos_locate(tb, u, &t);
+    lagrange4(t, w, dw);
+    res = eos_field(tb, i, w, kLnEk) - eos_field(tb, i, w, kLnN) - g;
+    const double der = (eos_field(tb, i, dw, kLnEk) - eos_field(tb, i, dw, kLnN)) * tb.inv_h;
+    const double un = fmin(fmax(u - res / der, tb.u_lo), tb.u_hi);
+    const bool done = fabs(un - u) < 1e-14;
+    u = un;
+    if (done) break;
+  }
+  i = eos_locate(tb, u, &t);
+  lagrange4(t, w, dw);
+  res = eos_field(tb, i, w, kLnEk) - eos_field(tb, i, w, kLnN) - g;
+  ok = ok && fabs(res) < 1e-9;
+  o->T = exp(u);
+  o->M_eq = eos_field(tb, i, w, kZ) * o->T;
+  o->beta = eos_field(tb, i, w, kBeta);
+  o->Bt4 = eos_field(tb, i, w, kBt4);
+  *alpha = ok ? log(n) - eos_field(tb, i, w, kLnN) : 0.0;
+  o->q = eos_field(tb, i, w, kQ) - *alpha * eos_field(tb, i, w, kNq);
+  ok = ok && o->q > 0.0;
+  if (!ok) o->q = 1.0;
+  return ok;
+}
+
 // u-derivatives of the interpolated EoS at the solution of eos_cell (for the
 // adjoint): du/dlambda = 1/(lambda d lnEk/du), and dz/du, dbeta/du, dq/du of
 // the same cubic.

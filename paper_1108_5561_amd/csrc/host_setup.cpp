@@ -546,12 +546,15 @@ bool HostEos::eval(double T, double z_guess, Point* o, double* z_used) const {
     double dB = -Z_ * M * M * T * k1 * dM / tp2;
     o->beta = dB / (T * dsT - dB);
   }
+  o->n0 = pkin / T;  // n = Z M^2 T K_2/(2 pi^2) of eq. (epsp) at mu = 0
   if (taur_rule_ == LB_TAUR_MASSLESS) {
     o->q = 5.0;
+    o->qn = 0.0;
   } else {
     // h = eta/tau_R = Z M^5/(30 pi^2 T) int sinh^6/cosh exp(-z cosh)
     double h = Z_ * std::pow(M, 5) / (30 * kPi * kPi * T) * h_integral(z);
     o->q = T * o->s / h;
+    o->qn = T * o->n0 / h;
   }
   *z_used = z;
   return true;
@@ -623,6 +626,8 @@ std::string build_tables(const lb_params& p, HostTables* out) {
         d[kBeta] = pt.beta;
         d[kQ] = pt.q;
         d[kBt4] = pt.B / (Tt * Tt * Tt * Tt);
+        d[kLnN] = std::log(pt.n0);
+        d[kNq] = pt.qn;
         deps[i] = Tt * eos.ds(Tt);
       }
     });

@@ -34,6 +34,7 @@ class HostEos {
   bool z_of_T(double T, double z_guess, double* z) const;
   struct Point {
     double eps, p, s, M, B, ekin, beta, q;
+    double n0, qn;  // particle density at mu = 0; T n0/h (0 for the massless rule)
   };
   bool eval(double T, double z_guess, Point* out, double* z_used) const;
   double Z() const { return Z_; }

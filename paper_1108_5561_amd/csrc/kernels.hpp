@@ -20,7 +20,7 @@ struct StageArgs {
   int32_t nx, ny, n_sites;
   int32_t metric;
   int32_t force_form;    // LB_FORCE_FEQ or LB_FORCE_WEAK3D (lb_step only)
-  int32_t pad_;
+  int32_t mu_mode;       // 1: conserved particle number (n matching; record slot beta holds mu/T)
   double inv2dx;         // 1/(2 dx)    [fm^-1]
   double inv_dx;         // 1/dx
   double tau;            // time of this stage [fm]
@@ -30,6 +30,7 @@ struct StageArgs {
   double inv_eta_hbarc;  // 1/((eta/s) hbar c), 0 for eta/s = inf
   double Z;
   double log2Z;          // log2(Z)
+  double alpha0;         // mu/T of the initial state (lb_init)
 };
 
 // One Heun stage.  stage 0: F* = F + dtau K(F); stage 1:

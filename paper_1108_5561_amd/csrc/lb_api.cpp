@@ -103,6 +103,13 @@ std::string validate(const lb_params* p) {
     return "need 0 < T_min and T_max > 2 T_min";
   if (p->operator_form != LB_OPS_WEAK && p->operator_form != LB_OPS_STRONG) return "unknown operator_form";
   if (p->force_form != LB_FORCE_FEQ && p->force_form != LB_FORCE_WEAK3D) return "unknown force_form";
+  if (p->particle_number != LB_N_FREE && p->particle_number != LB_N_CONSERVED) return "unknown particle_number";
+  if (p->particle_number == LB_N_CONSERVED && p->eos_kind != LB_EOS_CONST_MASS)
+    return "particle_number LB_N_CONSERVED needs eos_kind LB_EOS_CONST_MASS";
+  if (!std::isfinite(p->mu_over_T0) || std::fabs(p->mu_over_T0) > 20.0)
+    return "mu_over_T0 must be finite and within +-20";
+  if (p->mu_over_T0 != 0.0 && p->particle_number != LB_N_CONSERVED)
+    return "mu_over_T0 needs particle_number LB_N_CONSERVED";
   return "";
 }
 
@@ -334,7 +341,8 @@ StageArgs params_args(const lb_params& p, double tau, double dtau) {
   a.n_sites = p.nx * p.ny;
   a.metric = p.metric;
   a.force_form = p.force_form;
-  a.pad_ = 0;
+  a.mu_mode = p.particle_number == LB_N_CONSERVED ? 1 : 0;
+  a.alpha0 = p.mu_over_T0;
   a.inv2dx = 0.5 / p.dx_fm;
   a.inv_dx = 1.0 / p.dx_fm;
   a.dtau = dtau;
@@ -390,6 +398,7 @@ struct AdjBufs {
 int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBufs* B) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   if (c->p.force_form != LB_FORCE_FEQ) return fail(LB_E_NOTIMPL, "the adjoint step has the F_eq force only");
+  if (c->p.particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the adjoint step has mu = 0 only");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
   if (!std::isfinite(tau) || (c->p.metric == LB_METRIC_MILNE && !(tau > 0)))
     return fail(LB_E_ARG, "tau must be finite (and > 0 for the Milne metric)");
@@ -679,6 +688,7 @@ int lb_adjoint_init(lb_ctx* c, const double* d_e0, const double* d_ux0, const do
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   if (!d_e0 || !d_adj_F || !d_adj_lnM || !d_grad_e0) return fail(LB_E_ARG, "pointer is NULL");
   if ((d_ux0 == nullptr) != (d_uy0 == nullptr)) return fail(LB_E_ARG, "give both ux0 and uy0 or neither");
+  if (c->p.particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the adjoint of lb_init has mu = 0 only");
   const StageArgs a = stage_args(c, c->p.tau0_fm, 0.0);
   hipError_t e = launch_adj_init(d_e0, d_ux0, d_uy0, d_adj_F, d_adj_lnM, d_grad_e0, &c->cd, c->tb, a, c->err,
                                  c->stream);
@@ -1136,6 +1146,7 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
   std::string m = validate_batch(p, events, n_events);
   if (!m.empty()) return fail(LB_E_ARG, m);
   if (p->force_form != LB_FORCE_FEQ) return fail(LB_E_NOTIMPL, "the batched form has the F_eq force only");
+  if (p->particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the batched form has mu = 0 only");
   if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(LB_E_ARG, "workspace NULL or not 256-byte aligned");
   if (!d_e0) return fail(LB_E_ARG, "e0 pointer array is NULL");
   for (int i = 0; i < n_events; ++i)

@@ -18,7 +18,9 @@ enum EosField : int {
   kBeta = 3,    // beta = dB/d(eps - B)
   kQ = 4,       // q = T tau_R / (hbar c eta/s) = T s/h (CE) or 5 (massless)
   kBt4 = 5,     // B(T)/T^4
-  kFields = 8   // padded to 64 bytes per point
+  kLnN = 6,     // ln n0(T), the particle density at mu = 0          [GeV^3]
+  kNq = 7,      // T n0/h (CE; 0 for the massless rule): q(T, mu) = q - (mu/T) kNq
+  kFields = 8   // 64 bytes per point
 };
 
 struct EosTable {

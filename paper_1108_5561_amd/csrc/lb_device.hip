@@ -48,6 +48,8 @@ constexpr int kTX = 8;
 constexpr int kXcds = 8;  // accelerator complex dies of the MI355X
 constexpr size_t kMallBytes = (size_t)192 << 20;  // below the 256 MB last-level cache
 constexpr int kBigTileRows = 8;
+// rows of the per-tile moment exchange: T^{ab} (6), ln M, N^a (3, mu mode)
+constexpr int kMomRows = 10;
 #ifndef LB_TILE_ROWS_F32
 #define LB_TILE_ROWS_F32 4
 #endif
@@ -473,6 +475,25 @@ __device__ __forceinline__ void slice_moments(const R f[25], CPtr<R> C, R* p0, R
   *p3 = a3;
 }
 
+// Particle-current partial sums of one slice over the mirror pairs:
+// w gamma and w |v_perp| (eq. (NTdisc)).
+template <typename R>
+__device__ __forceinline__ void slice_current(const R f[25], CPtr<R> C, R* p0, R* p1) {
+  R a0 = 0, a1 = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr) {
+      const R fs = pr < 2 ? f[k * 5 + pr] + f[k * 5 + 4 - pr] : f[k * 5 + 2];
+      const int i = k * 3 + pr;
+      a0 += C->w[i] * C->x[k] * fs;
+      a1 += C->w[i] * C->sig[i] * fs;
+    }
+  }
+  *p0 = a0;
+  *p1 = a1;
+}
+
 // Landau matching (eq. (sanity)) and EoS inversion of a tile's state from
 // the slices in registers, writing the site scalars.  Every thread of the
 // block calls it (one barrier inside); lane l of site ts holds slice l and
@@ -499,6 +520,16 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
     s_mom[5][ts] = (double)m22;
     s_mom[6][ts] = lnM;
   }
+  if (a.mu_mode) {  // uniform: the particle current for the n matching
+    R c0, c1;
+    slice_current(f, C, &c0, &c1);
+    const R n0 = sum8(c0), n1 = sum8(c1 * cl), n2 = sum8(c1 * sl);
+    if (l == 0) {
+      s_mom[7][ts] = (double)n0;
+      s_mom[8][ts] = (double)n1;
+      s_mom[9][ts] = (double)n2;
+    }
+  }
   __syncthreads();
   if (t >= kTile) return;
   const int sx = bx * kTX + (t % kTX), sy = by * kTY + (t / kTX);
@@ -517,7 +548,15 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   const bool matched = landau3(tk, &lam, u);
   EosAt E;
   const EosTable tb = load_table(tbg);  // read here, where it is used
-  const bool eos_ok = eos_cell(tb, lam, &E);
+  bool eos_ok;
+  double alpha = 0.0;
+  if (a.mu_mode) {
+    // n = u_a N^a with N^a = M^3/(2 pi^2) sum w F V^a (eq. (NTdisc))
+    const double n = G / M * (u[0] * s_mom[7][t] - u[1] * s_mom[8][t] - u[2] * s_mom[9][t]);
+    eos_ok = eos_mu(tb, lam, n, &E, &alpha);
+  } else {
+    eos_ok = eos_cell(tb, lam, &E);
+  }
   if (!finite) flag(err, kErrNonfinite);
   else if (!matched) flag(err, kErrMatch);
   else if (!eos_ok) flag(err, kErrEos);
@@ -531,7 +570,7 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   rec.v[kScRate] = (R)(E.T * a.inv_eta_hbarc / E.q);  // 1/tau_R [fm^-1]
   rec.v[kScMinvT] = (R)(M * invT);
   rec.v[kScL2invT] = (R)(1.4426950408889634 * invT);  // log2(e)/T
-  rec.beta = E.beta;
+  rec.beta = a.mu_mode ? alpha : E.beta;  // beta = 0 for the constant mass of the mu mode
   rec.lnM = s_mom[6][t];
   store_record<R>(buf_rsrc(sc, (uint32_t)a.n_sites * SiteRecord<R>::kBytes), ss, rec);
 }
@@ -577,7 +616,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, (kForce ? ForceWaves<R>::v : MinWa
     const double* __restrict__ lnMin, const double* __restrict__ lnMbase, double* __restrict__ lnMout,
     const double* __restrict__ scin, double* __restrict__ scout, const StageConst<R>* __restrict__ Cg,
     const EosTable* __restrict__ tbg, const StageArgs a, int* __restrict__ err) {
-  __shared__ double s_mom[7][kTX * kTY];
+  __shared__ double s_mom[kMomRows][kTX * kTY];
   // exchange area of the 3-D force: per wave 25 nodes x 64 lanes
   __shared__ __attribute__((aligned(16))) R s_force[kForce ? kTY * 25 * 64 : 1];
   const int n_tiles = ((a.nx + kTX - 1) / kTX) * ((a.ny + kTY - 1) / kTY);
@@ -596,7 +635,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
     const StageTime* __restrict__ times, int time_idx, int i_in, int i_base, int i_out,
     const StageConst<R>* __restrict__ Cg, const EosTable* __restrict__ tbg, StageArgs a,
     int* __restrict__ err) {
-  __shared__ double s_mom[7][kTX * kTY];
+  __shared__ double s_mom[kMomRows][kTX * kTY];
   const int tile = xcd_tile(n_tiles);
   if (tile >= n_tiles) return;  // whole block
   // the event, its buffers and the stage time through constant-address
@@ -616,6 +655,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
     time.tau_s = tp->tau_s;
     time.inv_tau_s = tp->inv_tau_s;
   }
+  a.mu_mode = 0;  // the batched form matches the energy only (mu = 0)
   a.nx = ep->nx;
   a.ny = ep->ny;
   a.n_sites = ep->n_sites;
@@ -654,7 +694,7 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl) void site_kernel(
     int* __restrict__ err) {
   const CPtr<R> C = const_ptr(Cg);
   constexpr int kTY = TileRows<R>::v;
-  __shared__ double s_mom[7][kTX * kTY];
+  __shared__ double s_mom[kMomRows][kTX * kTY];
   const int t = threadIdx.x;
   const int ts = t >> 3, l = t & 7;
   const int tiles_x = (a.nx + kTX - 1) / kTX;
@@ -685,7 +725,8 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const double* __restrict__
   const int site = tid >> 3;
   const int l = tid & 7;
   if (site >= a.n_sites) return;
-  const double e = e0[site] * (kHbarC * kHbarC * kHbarC);
+  // with mu0 = alpha0 T0 (constant mass): eps0(T0) = e0 exp(-alpha0)
+  const double e = e0[site] * (kHbarC * kHbarC * kHbarC) * exp(-a.alpha0);
   const double vx = ux0 ? ux0[site] : 0.0, vy = uy0 ? uy0[site] : 0.0;
   int bad = 0;
   if (!isfinite(e) || !(e > 0.0) || !isfinite(vx) || !isfinite(vy)) bad = kErrNonfinite;
@@ -704,7 +745,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(const double* __restrict__
   for (int q = 0; q < Q; ++q) {
     const int k = q / NTH;
     const double uP = M * (ut * (double)C.x[k] - cu * (double)C.sig[q]);
-    F[NodeLayout<R>::offset(q, site, l, a.n_sites) / sizeof(R)] = (R)(a.Z * exp(-uP / T0));
+    F[NodeLayout<R>::offset(q, site, l, a.n_sites) / sizeof(R)] = (R)(a.Z * exp(a.alpha0 - uP / T0));
   }
   if (l == 0) {
     lnM[site] = log(M);
@@ -749,7 +790,9 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const R* __restrict__ F
   double lam, u[3];
   const bool matched = landau3(tk, &lam, u);
   EosAt E;
-  const bool eos_ok = eos_from_lambda(tb, lam, &E);
+  double alpha;
+  const bool eos_ok = a.mu_mode ? eos_mu(tb, lam, G3 * (u[0] * n0 - u[1] * n1 - u[2] * n2), &E, &alpha)
+                                : eos_from_lambda(tb, lam, &E);
   if (l == 0) {
     bool finite = true;
     for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);

@@ -254,3 +254,17 @@ def test_force_form_validation():
     p.force_form = 2
     assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) == 0
     assert "force_form" in lb.last_error()
+
+
+def test_particle_number_validation():
+    # LB_N_CONSERVED needs the constant-mass EoS; mu_over_T0 needs it too
+    p = lb.make_params(8, 8, 0.2, eos_kind=lb.LB_EOS_CONST_MASS, eos_mass_GeV=0.4, Z=3.0,
+                       particle_number=lb.LB_N_CONSERVED, mu_over_T0=0.5)
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) > 0
+    p.eos_kind = lb.LB_EOS_TANH_S
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) == 0
+    assert "LB_EOS_CONST_MASS" in lb.last_error()
+    q = lb.make_params(8, 8, 0.2, mu_over_T0=0.5)
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(q)) == 0
+    q.mu_over_T0, q.particle_number = 0.0, 2
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(q)) == 0

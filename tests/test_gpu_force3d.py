@@ -17,7 +17,7 @@ from oracle.eos import HBARC, TanhEntropyEoS  # noqa: E402
 from oracle.lattice import Lattice  # noqa: E402
 from paper_1108_5561_amd import workloads as wl  # noqa: E402
 
-from _helpers import tmunu_rel_err  # noqa: E402
+from _helpers import patch, tmunu_rel_err  # noqa: E402
 
 DEV = "cuda:0"
 
@@ -145,3 +145,30 @@ def test_batched_and_adjoint_forms_reject_the_3d_force(eos):
     with pytest.raises(lb.LbError) as ei:
         lb.Batch(p, [(nx, ny, dx, 0.1)], [gpu(e0)])
     assert ei.value.code == lb.LB_E_NOTIMPL
+
+
+def test_prec_workload_sampled_parity(lat3, eos):
+    # 256 x 256 precision workload at the launch configuration the benchmark
+    # times for this force: 50 steps, then one more step checked at sampled
+    # sites against the oracle on 9 x 9 periodic windows (the step reaches
+    # 4 sites; the force's ln M gradient 1 per stage)
+    w = wl.WORKLOADS["prec"]
+    e0 = (float(eos.eps(0.4)) / HBARC ** 3 * wl.gaussian_shape(w["nx"], w["ny"], w["dx"], 2.0)
+          * wl.white_noise_factor(w["nx"], w["ny"]))
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    prm = st.Params(dx=w["dx"], eta_over_s=w["eta_over_s"])
+    print("weak3d 256x256 FP32, sampled sites", flush=True)
+    c = _ctx(w["nx"], w["ny"], w["dx"], e0, lb.LB_FP32_FP64MATCH, w["eta_over_s"])
+    c.step(50, dtau)
+    F0, l0, tau = c.get_state()
+    F0, l0 = cpu(F0), cpu(l0)
+    c.step(1, dtau)
+    obs = cpu(c.moments())
+    assert c.status() == lb.LB_OK
+    rng = np.random.default_rng(19)
+    sites = [(0, 0), (255, 255), (128, 128), (0, 200)] + [tuple(rng.integers(0, 256, 2)) for _ in range(6)]
+    for (cy, cx) in sites:
+        Fp, lp = patch(F0, cy, cx, 4), patch(l0, cy, cx, 4)
+        Fo, lo = st.heun_step(lat3, eos, prm, Fp, lp, tau, dtau)
+        ref = st.observables(lat3, eos, prm, Fo, lo)[:, 4:5, 4:5]
+        assert tmunu_rel_err(obs[:, cy:cy + 1, cx:cx + 1], ref) < 1e-5, (cy, cx)

@@ -1,0 +1,145 @@
+"""GPU parity of the conserved particle number (particle_number
+LB_N_CONSERVED: n matching of eq. (sanity), fugacity exp(mu/T) of
+eq. (epsp) in F_eq, tau_R at (T, mu)) against the FP64 oracle with the same
+matching, on the constant-mass equation of state.
+
+Tolerances as for the plain step: 1e-10 per FP64 step, 1e-5 relative in
+T^{mu nu} per FP32 step.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1108_5561_amd as lb  # noqa: E402
+from oracle import step as st  # noqa: E402
+from oracle.eos import ConstMassEoS  # noqa: E402
+from oracle.lattice import Lattice  # noqa: E402
+from paper_1108_5561_amd import workloads as wl  # noqa: E402
+
+from _helpers import tmunu_rel_err  # noqa: E402
+
+DEV = "cuda:0"
+Z, M0 = 3.0, 0.4
+
+
+@pytest.fixture(scope="module")
+def lat():
+    return Lattice(5, 5, 4, 1.0)
+
+
+@pytest.fixture(scope="module")
+def eos():
+    return ConstMassEoS(Z=Z, M0=M0)
+
+
+def gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def _params(nx, ny, dx, precision, eta, alpha0, metric=lb.LB_METRIC_MILNE):
+    return lb.make_params(nx, ny, dx, precision=precision, eta_over_s=eta, metric=metric,
+                          eos_kind=lb.LB_EOS_CONST_MASS, eos_mass_GeV=M0, Z=Z,
+                          particle_number=lb.LB_N_CONSERVED, mu_over_T0=alpha0)
+
+
+def _e0(nx, ny, dx):
+    # 1.5 GeV/fm^3 background and a Gaussian of 6 GeV/fm^3 (T about 0.3-0.5 GeV)
+    return 1.5 + 6.0 * wl.gaussian_shape(nx, ny, dx, 0.25 * nx * dx)
+
+
+def test_init_with_chemical_potential(lat, eos):
+    nx, ny, dx = 13, 7, 0.2
+    e0 = _e0(nx, ny, dx)
+    ux, uy = wl.random_flow(nx, ny, 0.15, seed=4)
+    c = lb.Context(_params(nx, ny, dx, lb.LB_FP64, 0.1, 0.6), gpu(e0), gpu(ux), gpu(uy))
+    F, l = st.init_state(lat, eos, e0, ux, uy, alpha0=0.6)
+    Fg, lg, _ = c.get_state()
+    assert c.status() == lb.LB_OK
+    assert np.max(np.abs(cpu(Fg) - F)) < 1e-11 * F.max()
+    assert np.max(np.abs(cpu(lg) - l)) < 1e-13
+
+
+@pytest.mark.parametrize("nx,ny", [(37, 23), (8, 5)])
+def test_one_step_fp64(lat, eos, nx, ny):
+    dx, dtau, eta = 0.2, 0.01, 0.1
+    e0 = _e0(nx, ny, dx)
+    ux, uy = wl.random_flow(nx, ny, 0.15, seed=nx + ny)
+    F, l = st.init_state(lat, eos, e0, ux, uy, alpha0=0.4)
+    rng = np.random.default_rng(nx * ny)
+    F = F * (1 + 0.05 * rng.random(F.shape))   # off equilibrium, n and eps both changed
+    print(f"mu mode FP64 one step {nx}x{ny}", flush=True)
+    c = lb.Context(_params(nx, ny, dx, lb.LB_FP64, eta, 0.4), gpu(e0))
+    c.set_state(gpu(F), gpu(l), 0.7)
+    prm = st.Params(dx=dx, eta_over_s=eta, conserve_n=True)
+    Fo, lo = st.heun_step(lat, eos, prm, F, l, 0.7, dtau)
+    c.step(1, dtau)
+    Fg, lg, _ = c.get_state()
+    assert c.status() == lb.LB_OK
+    assert np.max(np.abs(cpu(Fg) - Fo)) < 1e-10 * Fo.max()
+    assert np.max(np.abs(cpu(lg) - lo)) < 1e-12
+    obs, ref = cpu(c.moments()), st.observables(lat, eos, prm, Fo, lo)
+    assert tmunu_rel_err(obs, ref) < 1e-10
+    assert np.max(np.abs(obs[10] - ref[10]) / ref[10]) < 1e-10   # T at (T, mu)
+
+
+def test_one_step_fp32(lat, eos):
+    nx, ny, dx, dtau, eta = 37, 23, 0.2, 0.01, 0.1
+    e0 = _e0(nx, ny, dx)
+    ux, uy = wl.random_flow(nx, ny, 0.15, seed=2)
+    F, l = st.init_state(lat, eos, e0, ux, uy, alpha0=-0.3)
+    F = F * (1 + 0.05 * np.random.default_rng(2).random(F.shape))
+    c = lb.Context(_params(nx, ny, dx, lb.LB_FP32_FP64MATCH, eta, -0.3), gpu(e0))
+    c.set_state(gpu(F), gpu(l), 0.7)
+    prm = st.Params(dx=dx, eta_over_s=eta, conserve_n=True)
+    Fo, lo = st.heun_step(lat, eos, prm, F.astype(np.float32).astype(np.float64), l, 0.7, dtau)
+    c.step(1, dtau)
+    assert c.status() == lb.LB_OK
+    assert tmunu_rel_err(cpu(c.moments()), st.observables(lat, eos, prm, Fo, lo)) < 1e-5
+
+
+def test_run_conserves_particle_number(lat, eos):
+    # Minkowski metric, periodic box: 30 FP64 steps against the oracle, and
+    # the total N^tau kept to the equilibrium quadrature error with the n
+    # matching, not without it
+    nx, ny, dx, dtau, eta = 12, 10, 0.2, 0.02, 0.1
+    e0 = _e0(nx, ny, dx)
+    prm = st.Params(dx=dx, eta_over_s=eta, conserve_n=True, metric=st.METRIC_MINKOWSKI)
+    F, l = st.init_state(lat, eos, e0, alpha0=0.5)
+    for _ in range(30):
+        F, l = st.heun_step(lat, eos, prm, F, l, 1.0, dtau)
+    ref = st.observables(lat, eos, prm, F, l)
+    drift = []
+    for pn, a0 in ((lb.LB_N_CONSERVED, 0.5), (lb.LB_N_FREE, 0.0)):
+        p = _params(nx, ny, dx, lb.LB_FP64, eta, a0, metric=lb.LB_METRIC_MINKOWSKI)
+        p.particle_number = pn
+        c = lb.Context(p, gpu(e0))
+        n0 = cpu(c.moments())[7].sum()
+        c.step(30, dtau)
+        assert c.status() == lb.LB_OK
+        obs = cpu(c.moments())
+        drift.append(abs(obs[7].sum() - n0) / n0)
+        if pn == lb.LB_N_CONSERVED:
+            assert tmunu_rel_err(obs, ref) < 1e-9
+    assert drift[0] < 1e-6
+    assert drift[1] > 20 * drift[0]
+
+
+def test_batched_and_adjoint_forms_reject_mu(eos):
+    nx, ny, dx = 8, 8, 0.2
+    e0 = _e0(nx, ny, dx)
+    p = _params(nx, ny, dx, lb.LB_FP64, 0.1, 0.2)
+    c = lb.Context(p, gpu(e0))
+    ws = c.adjoint_workspace()
+    F, lnM, _ = c.get_state()
+    with pytest.raises(lb.LbError) as ei:
+        c.adjoint_forward_step(0.5, 0.005, F, lnM, ws)
+    assert ei.value.code == lb.LB_E_NOTIMPL
+    with pytest.raises(lb.LbError) as ei:
+        lb.Batch(p, [(nx, ny, dx, 0.1)], [gpu(e0)])
+    assert ei.value.code == lb.LB_E_NOTIMPL
