@@ -107,6 +107,42 @@ def run_force3d(lb, wl, torch, steps=200, warmup=10):
             "steps": steps, "tmunu_rel_diff_vs_feq_force": tmunu_rel_err(r["obs"], ref["obs"])}
 
 
+def run_number(lb, wl, torch, steps=200, warmup=10):
+    """The plain FP32 step with conserved particle number (LB_N_CONSERVED,
+    constant-mass EoS M = 0.4 GeV, Z = 3, initial mu/T = 0.5) on the
+    256 x 256 grid of the precision workload (e0 = 1.5 GeV/fm^3 + the
+    Gaussian x noise shape times 40 GeV/fm^3), against the same step matched
+    to the energy only."""
+    w = wl.WORKLOADS["prec"]
+    e0 = 1.5 + 40.0 * wl.gaussian_shape(w["nx"], w["ny"], w["dx"], 2.0) * wl.white_noise_factor(w["nx"], w["ny"])
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    out = {}
+    for name, pn, a0 in (("n", lb.LB_N_CONSERVED, 0.5), ("energy_only", lb.LB_N_FREE, 0.0)):
+        p = lb.make_params(w["nx"], w["ny"], w["dx"], tau0_fm=w["tau0"], eta_over_s=w["eta_over_s"],
+                           precision=lb.LB_FP32_FP64MATCH, eos_kind=lb.LB_EOS_CONST_MASS, eos_mass_GeV=0.4,
+                           Z=3.0, particle_number=pn, mu_over_T0=a0)
+        c = lb.Context(p, torch.from_numpy(e0).to("cuda:0"))
+        c.step(warmup, dtau)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n_before = float(c.moments()[7].sum())
+        start.record()
+        c.step(steps, dtau)
+        stop.record()
+        torch.cuda.synchronize()
+        if c.status() != lb.LB_OK:
+            raise RuntimeError(lb.last_error())
+        # tau N^tau is conserved in the Milne box (boost-invariant flow)
+        tau0, tau1 = w["tau0"] + warmup * dtau, w["tau0"] + (warmup + steps) * dtau
+        n_after = float(c.moments()[7].sum())
+        out[name] = dict(ms=start.elapsed_time(stop), drift=abs(tau1 * n_after - tau0 * n_before) / (tau0 * n_before))
+    n_sites = w["nx"] * w["ny"]
+    return {"value": steps * n_sites / (out["n"]["ms"] / 1e3), "unit": "site-updates/s",
+            "ms_per_step": out["n"]["ms"] / steps, "steps": steps,
+            "vs_energy_only_step": out["energy_only"]["ms"] / out["n"]["ms"],
+            "tau_N_tau_rel_drift": out["n"]["drift"], "tau_N_tau_rel_drift_energy_only": out["energy_only"]["drift"]}
+
+
 def run_batch(lb, wl, torch, steps=96):
     """The batched form on the 64-event hot-spot workload (FP32+FP64-match):
     tune the kernel variant on the batch, warm up one graph replay, then time
@@ -280,6 +316,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-form measurement")
     ap.add_argument("--no-force3d", action="store_true", help="skip the weak-form 3-D force measurement")
+    ap.add_argument("--no-number", action="store_true", help="skip the conserved-particle-number measurement")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the differentiable-form measurement (one JSON object)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -334,6 +371,7 @@ def main():
     batch = None if args.no_batch else optional(run_batch)
     adjoint = None if args.no_adjoint else optional(run_adjoint)
     force3d = None if args.no_force3d else optional(run_force3d)
+    number = None if args.no_number else optional(run_number)
 
     out = {
         "metric": "site-updates/s & HBM GB/s: FP32+FP64-match vs FP64 step at 1e-5 rel err",
@@ -363,6 +401,7 @@ def main():
             adjoint, vs_plain_fp64_step=adjoint["gradient_site_updates_per_s"] / sups64),
         "force3d": force3d if force3d is None or "error" in force3d else dict(
             force3d, vs_feq_force_step=force3d["value"] / sups32),
+        "conserved_n": number,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
