@@ -74,6 +74,9 @@ template <int STAGE> struct MinWaves<double, STAGE> { static constexpr int v = L
 #endif
 template <typename R> struct ForceWaves { static constexpr int v = LB_FORCE_WAVES_F32; };
 template <> struct ForceWaves<double> { static constexpr int v = 1; };
+// with the conserved particle number (the n matching's registers)
+template <typename R> struct MuWaves { static constexpr int v = 3; };
+template <> struct MuWaves<double> { static constexpr int v = LB_WAVES_PER_EU_F64; };
 
 // A distribution buffer is read and written as one raw buffer: one
 // descriptor (uniform, scalar registers), the plane offset q * plane bytes
@@ -498,7 +501,7 @@ __device__ __forceinline__ void slice_current(const R f[25], CPtr<R> C, R* p0, R
 // the slices in registers, writing the site scalars.  Every thread of the
 // block calls it (one barrier inside); lane l of site ts holds slice l and
 // lnM = ln M of its site.  s_mom is the block's LDS scratch [7][tile sites].
-template <typename R, int kTY>
+template <typename R, int kTY, int kMu>
 __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM, int t, int bx,
                                            int by, const EosTable* __restrict__ tbg, const StageArgs& a,
                                            double* __restrict__ sc, int* __restrict__ err,
@@ -520,7 +523,7 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
     s_mom[5][ts] = (double)m22;
     s_mom[6][ts] = lnM;
   }
-  if (a.mu_mode) {  // uniform: the particle current for the n matching
+  if constexpr (kMu) {  // the particle current for the n matching
     R c0, c1;
     slice_current(f, C, &c0, &c1);
     const R n0 = sum8(c0), n1 = sum8(c1 * cl), n2 = sum8(c1 * sl);
@@ -550,7 +553,7 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   const EosTable tb = load_table(tbg);  // read here, where it is used
   bool eos_ok;
   double alpha = 0.0;
-  if (a.mu_mode) {
+  if constexpr (kMu) {
     // n = u_a N^a with N^a = M^3/(2 pi^2) sum w F V^a (eq. (NTdisc))
     const double n = G / M * (u[0] * s_mom[7][t] - u[1] * s_mom[8][t] - u[2] * s_mom[9][t]);
     eos_ok = eos_mu(tb, lam, n, &E, &alpha);
@@ -570,7 +573,7 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   rec.v[kScRate] = (R)(E.T * a.inv_eta_hbarc / E.q);  // 1/tau_R [fm^-1]
   rec.v[kScMinvT] = (R)(M * invT);
   rec.v[kScL2invT] = (R)(1.4426950408889634 * invT);  // log2(e)/T
-  rec.beta = a.mu_mode ? alpha : E.beta;  // beta = 0 for the constant mass of the mu mode
+  rec.beta = kMu ? alpha : E.beta;  // beta = 0 for the constant mass of the mu mode
   rec.lnM = s_mom[6][t];
   store_record<R>(buf_rsrc(sc, (uint32_t)a.n_sites * SiteRecord<R>::kBytes), ss, rec);
 }
@@ -610,8 +613,8 @@ __device__ __forceinline__ LaneSite lane_site(int tile, int tiles_x, int ts, int
 // XCD-aware tile order of xcd_tile.  kStream = kNT streams the new state
 // past the caches (stores, and the corrector's base slice, read once) for
 // states larger than the last-level cache; 0 keeps them cached.
-template <typename R, int STAGE, int kTY = TileRows<R>::v, int kStream = 0, int kForce = 0>
-__global__ __launch_bounds__(kTX * kTY * kSl, (kForce ? ForceWaves<R>::v : MinWaves<R, STAGE>::v)) void stage_kernel(
+template <typename R, int STAGE, int kTY = TileRows<R>::v, int kStream = 0, int kForce = 0, int kMu = 0>
+__global__ __launch_bounds__(kTX * kTY * kSl, (kForce ? ForceWaves<R>::v : (kMu ? MuWaves<R>::v : MinWaves<R, STAGE>::v))) void stage_kernel(
     const R* __restrict__ Fin, const R* __restrict__ Fbase, R* __restrict__ Fout,
     const double* __restrict__ lnMin, const double* __restrict__ lnMbase, double* __restrict__ lnMout,
     const double* __restrict__ scin, double* __restrict__ scout, const StageConst<R>* __restrict__ Cg,
@@ -655,7 +658,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
     time.tau_s = tp->tau_s;
     time.inv_tau_s = tp->inv_tau_s;
   }
-  a.mu_mode = 0;  // the batched form matches the energy only (mu = 0)
+  constexpr int kMu = 0;  // the batched form matches the energy only (mu = 0)
   a.nx = ep->nx;
   a.ny = ep->ny;
   a.n_sites = ep->n_sites;
@@ -687,7 +690,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
 
 // Site scalars of a state that no stage produced (after lb_init or
 // lb_set_state): the matching phase of the stage kernel on its own.
-template <typename R>
+template <typename R, int kMu>
 __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl) void site_kernel(
     const R* __restrict__ F, const double* __restrict__ lnMv, double* __restrict__ sc,
     const StageConst<R>* __restrict__ Cg, const EosTable* __restrict__ tbg, const StageArgs a,
@@ -708,7 +711,7 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl) void site_kernel(
   R f[25];
   load_slice<R>(buf_rsrc(F, (uint32_t)a.n_sites * kSl * 25u * (uint32_t)sizeof(R)), (uint32_t)site * kSl + l,
                 NodeLayout<R>::gbytes(a.n_sites), f);
-  match_tile<R, kTY>(f, C, lnMv[site], t, bx, by, tbg, a, sc, err, s_mom);
+  match_tile<R, kTY, kMu>(f, C, lnMv[site], t, bx, by, tbg, a, sc, err, s_mom);
 }
 
 // Initial local equilibrium (Sec. IV.D): T0 from eps_EoS(T0) = e0.
@@ -850,67 +853,53 @@ namespace {
 inline dim3 grid_for(int n_sites) { return dim3((unsigned)(((size_t)n_sites * kSl + kBlock - 1) / kBlock)); }
 }  // namespace
 
+namespace {
+// one stage of the single-event kernel with the given template flags
+template <typename R, int kTY, int kStream, int kForce, int kMu>
+hipError_t stage_launch_t(int stage, dim3 g, dim3 b, const void* Fin, const void* Fbase, void* Fout,
+                          const double* lnMin, const double* lnMbase, double* lnMout, const double* scin,
+                          double* scout, const void* sc, const EosTable* tb, const StageArgs& a, int* err,
+                          hipStream_t s) {
+  const auto* C = static_cast<const StageConst<R>*>(sc);
+  if (stage == 0)
+    hipLaunchKernelGGL((stage_kernel<R, 0, kTY, kStream, kForce, kMu>), g, b, 0, s, (const R*)Fin, (const R*)Fbase,
+                       (R*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+  else
+    hipLaunchKernelGGL((stage_kernel<R, 1, kTY, kStream, kForce, kMu>), g, b, 0, s, (const R*)Fin, (const R*)Fbase,
+                       (R*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_stage(int precision, int stage, const void* Fin, const void* Fbase, void* Fout,
                         const double* lnMin, const double* lnMbase, double* lnMout, const double* scin,
                         double* scout, const void* sc, const EosTable* tb, const StageArgs& a, int* err,
                         hipStream_t s) {
   // FP32 states whose three buffers exceed the last-level cache: 8-row
   // tiles and streaming stores (measured 5-6% faster per step at 512 x 512,
-  // 20% slower at 256 x 256, where the state stays in the cache)
-  const bool force3d = a.force_form == LB_FORCE_WEAK3D;
-  const bool big = !force3d && precision == LB_FP32_FP64MATCH &&
+  // 20% slower at 256 x 256, where the state stays in the cache); the
+  // weak-form 3-D force and the conserved particle number run with the
+  // default tiles and cached stores
+  const bool force3d = a.force_form == LB_FORCE_WEAK3D, mu = a.mu_mode != 0;
+  const bool big = !force3d && !mu && precision == LB_FP32_FP64MATCH &&
                    (size_t)a.n_sites * kSl * 25 * sizeof(float) * 3 > kMallBytes;
   const int ty = precision == LB_FP32_FP64MATCH ? (big ? kBigTileRows : TileRows<float>::v) : TileRows<double>::v;
   const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
   const unsigned per = (tiles + kXcds - 1) / kXcds;
   const dim3 g(per * kXcds), b(kTX * ty * kSl);
-  if (force3d) {
-    // the weak-form 3-D force: default tiles, cached stores
-    if (precision == LB_FP32_FP64MATCH) {
-      const auto* C = static_cast<const StageConst<float>*>(sc);
-      if (stage == 0)
-        hipLaunchKernelGGL((stage_kernel<float, 0, TileRows<float>::v, 0, 1>), g, b, 0, s, (const float*)Fin,
-                           (const float*)Fbase, (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-      else
-        hipLaunchKernelGGL((stage_kernel<float, 1, TileRows<float>::v, 0, 1>), g, b, 0, s, (const float*)Fin,
-                           (const float*)Fbase, (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-    } else {
-      const auto* C = static_cast<const StageConst<double>*>(sc);
-      if (stage == 0)
-        hipLaunchKernelGGL((stage_kernel<double, 0, TileRows<double>::v, 0, 1>), g, b, 0, s, (const double*)Fin,
-                           (const double*)Fbase, (double*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-      else
-        hipLaunchKernelGGL((stage_kernel<double, 1, TileRows<double>::v, 0, 1>), g, b, 0, s, (const double*)Fin,
-                           (const double*)Fbase, (double*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-    }
-    return hipGetLastError();
-  }
+#define LB_STAGE_ARGS stage, g, b, Fin, Fbase, Fout, lnMin, lnMbase, lnMout, scin, scout, sc, tb, a, err, s
   if (precision == LB_FP32_FP64MATCH) {
-    const auto* C = static_cast<const StageConst<float>*>(sc);
-    if (big) {
-      if (stage == 0)
-        hipLaunchKernelGGL((stage_kernel<float, 0, kBigTileRows, kNT>), g, b, 0, s, (const float*)Fin,
-                           (const float*)Fbase, (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-      else
-        hipLaunchKernelGGL((stage_kernel<float, 1, kBigTileRows, kNT>), g, b, 0, s, (const float*)Fin,
-                           (const float*)Fbase, (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-    } else if (stage == 0) {
-      hipLaunchKernelGGL((stage_kernel<float, 0>), g, b, 0, s, (const float*)Fin, (const float*)Fbase,
-                         (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-    } else {
-      hipLaunchKernelGGL((stage_kernel<float, 1>), g, b, 0, s, (const float*)Fin, (const float*)Fbase,
-                         (float*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-    }
-  } else {
-    const auto* C = static_cast<const StageConst<double>*>(sc);
-    if (stage == 0)
-      hipLaunchKernelGGL((stage_kernel<double, 0>), g, b, 0, s, (const double*)Fin, (const double*)Fbase,
-                         (double*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
-    else
-      hipLaunchKernelGGL((stage_kernel<double, 1>), g, b, 0, s, (const double*)Fin, (const double*)Fbase,
-                         (double*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+    constexpr int TY = TileRows<float>::v;
+    if (big) return stage_launch_t<float, kBigTileRows, kNT, 0, 0>(LB_STAGE_ARGS);
+    if (force3d)
+      return mu ? stage_launch_t<float, TY, 0, 1, 1>(LB_STAGE_ARGS) : stage_launch_t<float, TY, 0, 1, 0>(LB_STAGE_ARGS);
+    return mu ? stage_launch_t<float, TY, 0, 0, 1>(LB_STAGE_ARGS) : stage_launch_t<float, TY, 0, 0, 0>(LB_STAGE_ARGS);
   }
-  return hipGetLastError();
+  constexpr int TY = TileRows<double>::v;
+  if (force3d)
+    return mu ? stage_launch_t<double, TY, 0, 1, 1>(LB_STAGE_ARGS) : stage_launch_t<double, TY, 0, 1, 0>(LB_STAGE_ARGS);
+  return mu ? stage_launch_t<double, TY, 0, 0, 1>(LB_STAGE_ARGS) : stage_launch_t<double, TY, 0, 0, 0>(LB_STAGE_ARGS);
+#undef LB_STAGE_ARGS
 }
 
 namespace {
@@ -985,12 +974,19 @@ hipError_t launch_site(int precision, const void* F, const double* lnM, double* 
   const unsigned tiles = (unsigned)(((a.nx + kTX - 1) / kTX) * ((a.ny + ty - 1) / ty));
   const unsigned per = (tiles + kXcds - 1) / kXcds;
   const dim3 g(per * kXcds), b(kTX * ty * kSl);
-  if (precision == LB_FP32_FP64MATCH)
-    hipLaunchKernelGGL(site_kernel<float>, g, b, 0, s, (const float*)F, lnM, scout,
-                       static_cast<const StageConst<float>*>(sc), tb, a, err);
-  else
-    hipLaunchKernelGGL(site_kernel<double>, g, b, 0, s, (const double*)F, lnM, scout,
-                       static_cast<const StageConst<double>*>(sc), tb, a, err);
+  if (precision == LB_FP32_FP64MATCH) {
+    const auto* C = static_cast<const StageConst<float>*>(sc);
+    if (a.mu_mode)
+      hipLaunchKernelGGL((site_kernel<float, 1>), g, b, 0, s, (const float*)F, lnM, scout, C, tb, a, err);
+    else
+      hipLaunchKernelGGL((site_kernel<float, 0>), g, b, 0, s, (const float*)F, lnM, scout, C, tb, a, err);
+  } else {
+    const auto* C = static_cast<const StageConst<double>*>(sc);
+    if (a.mu_mode)
+      hipLaunchKernelGGL((site_kernel<double, 1>), g, b, 0, s, (const double*)F, lnM, scout, C, tb, a, err);
+    else
+      hipLaunchKernelGGL((site_kernel<double, 0>), g, b, 0, s, (const double*)F, lnM, scout, C, tb, a, err);
+  }
   return hipGetLastError();
 }
 
