@@ -139,8 +139,8 @@ typedef struct lb_params {
    *   nodes).  Energy, momentum and particle-number moments of the force
    *   then follow the balance laws exactly for any F.  It mixes the phi
    *   slices (a real Fourier transform over them), so the stage does about
-   *   twice the arithmetic.  lb_step only: the batched and adjoint entry
-   *   points return LB_E_NOTIMPL for it. */
+   *   twice the arithmetic.  lb_step and the batched form; the adjoint
+   *   entry points return LB_E_NOTIMPL for it. */
   int32_t force_form;
   /* LB_N_FREE: the equilibrium is matched to the energy density only (mu = 0,
    * as in the paper's runs).  LB_N_CONSERVED: also to the particle density
@@ -151,8 +151,9 @@ typedef struct lb_params {
    * LB_EOS_CONST_MASS: a mass depending on T alone is thermodynamically
    * consistent (eq. (cdef)) at mu != 0 only if it is constant.  The site's
    * mu/T follows from the outputs as ln(n / n0(T)), n0 the density at mu = 0.
-   * lb_step and lb_moments only: the batched and adjoint entry points return
-   * LB_E_NOTIMPL for it. */
+   * lb_step, lb_moments and the batched form (not together with
+   * LB_FORCE_WEAK3D there); the adjoint entry points return LB_E_NOTIMPL
+   * for it. */
   int32_t particle_number;
   /* mu/T of the initial state (uniform; lb_init): eps(T0, mu0) = e0 and
    * F = Z exp(mu0/T0 - u.P/T0).  Must be 0 unless LB_N_CONSERVED. */
@@ -366,11 +367,14 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
  * the spare state buffers (the state is unchanged), and keep the fastest.
  * variant_out (may be NULL) receives its index; ms_out (may be NULL) the
  * mean milliseconds per step of each variant ([12] in FP32, [3] in FP64).
+ * With LB_FORCE_WEAK3D or LB_N_CONSERVED there are three variants, tile
+ * rows 2, 4, 8 (v = 0, 1, 2) at the single-event kernel's occupancy.
  * Synchronous. */
 int lb_batch_tune(lb_batch* b, double dtau_fm, int32_t* variant_out, double* ms_out);
 
-/* Use kernel variant `variant` (0..11 in FP32, 0..2 in FP64, numbered as in
- * lb_batch_tune) without timing: pins a tuned choice. */
+/* Use kernel variant `variant` (0..11 in FP32, 0..2 in FP64 or with the 3-D
+ * force or the conserved particle number, numbered as in lb_batch_tune)
+ * without timing: pins a tuned choice. */
 int lb_batch_set_variant(lb_batch* b, int32_t variant);
 
 /* Advance every event n_steps Heun steps of dtau_fm (as lb_step; LB_E_ARG

@@ -362,7 +362,8 @@ class Batch:
 
     def tune(self, dtau_fm):
         """Time the kernel variants, keep the fastest; returns (variant, ms per step of each)."""
-        nv = 12 if self.params.precision == LB_FP32_FP64MATCH else 3
+        plain = self.params.force_form == LB_FORCE_FEQ and self.params.particle_number == LB_N_FREE
+        nv = 12 if self.params.precision == LB_FP32_FP64MATCH and plain else 3
         ms = (ctypes.c_double * nv)()
         v = ctypes.c_int32()
         check(lib.lb_batch_tune(self._b, float(dtau_fm), ctypes.byref(v), ms))

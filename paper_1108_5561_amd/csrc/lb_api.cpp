@@ -1105,7 +1105,7 @@ hipError_t time_variant(lb_batch* b, int v, double dtau, int n, float* ms) {
 }
 
 int batch_tune(lb_batch* b, double dtau, int32_t* variant_out, double* ms_out) {
-  const int nv = batch_variants(b->p.precision);
+  const int nv = batch_variants(b->p.precision, b->p.force_form, b->p.particle_number);
   int best = -1;
   float best_ms = 0;
   for (int v = 0; v < nv; ++v) {
@@ -1145,8 +1145,8 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
   *out = nullptr;
   std::string m = validate_batch(p, events, n_events);
   if (!m.empty()) return fail(LB_E_ARG, m);
-  if (p->force_form != LB_FORCE_FEQ) return fail(LB_E_NOTIMPL, "the batched form has the F_eq force only");
-  if (p->particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the batched form has mu = 0 only");
+  if (p->force_form != LB_FORCE_FEQ && p->particle_number != LB_N_FREE)
+    return fail(LB_E_NOTIMPL, "the batched form has the 3-D force or the conserved particle number, not both");
   if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(LB_E_ARG, "workspace NULL or not 256-byte aligned");
   if (!d_e0) return fail(LB_E_ARG, "e0 pointer array is NULL");
   for (int i = 0; i < n_events; ++i)
@@ -1265,7 +1265,8 @@ int lb_batch_tune(lb_batch* b, double dtau_fm, int32_t* variant_out, double* ms_
 
 int lb_batch_set_variant(lb_batch* b, int32_t variant) {
   if (!b) return fail(LB_E_STATE, "batch not initialised");
-  if (variant < 0 || variant >= batch_variants(b->p.precision)) return fail(LB_E_ARG, "no such kernel variant");
+  if (variant < 0 || variant >= batch_variants(b->p.precision, b->p.force_form, b->p.particle_number))
+    return fail(LB_E_ARG, "no such kernel variant");
   hipError_t e = set_variant(b, variant);
   if (e != hipSuccess) return hip_fail(e, "batch tile map");
   return LB_OK;

@@ -632,13 +632,14 @@ __global__ __launch_bounds__(kTX * kTY * kSl, (kForce ? ForceWaves<R>::v : (kMu 
 // (event e owns tiles [tile0_e, tile0_e + tiles_e)), taken in the XCD-aware
 // order; each block looks up its event and runs the single-event tile code,
 // so an event's result does not depend on the batch it is in.
-template <typename R, int STAGE, int kTY, int kW, int kStream>
+template <typename R, int STAGE, int kTY, int kW, int kStream, int kForce, int kMu>
 __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
     const BatchEvent* __restrict__ ev, const int32_t* __restrict__ tile_event, int n_tiles, StageTime time,
     const StageTime* __restrict__ times, int time_idx, int i_in, int i_base, int i_out,
     const StageConst<R>* __restrict__ Cg, const EosTable* __restrict__ tbg, StageArgs a,
     int* __restrict__ err) {
   __shared__ double s_mom[kMomRows][kTX * kTY];
+  __shared__ __attribute__((aligned(16))) R s_force[kForce ? kTY * 25 * 64 : 1];
   const int tile = xcd_tile(n_tiles);
   if (tile >= n_tiles) return;  // whole block
   // the event, its buffers and the stage time through constant-address
@@ -658,7 +659,6 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
     time.tau_s = tp->tau_s;
     time.inv_tau_s = tp->inv_tau_s;
   }
-  constexpr int kMu = 0;  // the batched form matches the energy only (mu = 0)
   a.nx = ep->nx;
   a.ny = ep->ny;
   a.n_sites = ep->n_sites;
@@ -677,8 +677,6 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
   double* __restrict__ lnMout = ep->lnM[i_out];
   const double* __restrict__ scin = ep->sc[i_in];
   double* __restrict__ scout = ep->sc[i_out];
-  constexpr int kForce = 0;  // the batched form has the F_eq force
-  R* const s_force = nullptr;
   {
     const int tile_g = tile;
     {
@@ -903,12 +901,12 @@ hipError_t launch_stage(int precision, int stage, const void* Fin, const void* F
 }
 
 namespace {
-template <typename R, int STAGE, int kTY, int kW, int kStream>
+template <typename R, int STAGE, int kTY, int kW, int kStream, int kForce = 0, int kMu = 0>
 hipError_t batch_launch_t(const BatchEvent* ev, const int32_t* te, int n_tiles, StageTime time,
                           const StageTime* times, int tidx, int i_in, int i_base, int i_out, const void* sc,
                           const EosTable* tb, const StageArgs& a, int* err, hipStream_t s) {
   const unsigned per = (unsigned)((n_tiles + kXcds - 1) / kXcds);
-  hipLaunchKernelGGL((batch_stage_kernel<R, STAGE, kTY, kW, kStream>), dim3(per * kXcds), dim3(kTX * kTY * kSl), 0, s, ev,
+  hipLaunchKernelGGL((batch_stage_kernel<R, STAGE, kTY, kW, kStream, kForce, kMu>), dim3(per * kXcds), dim3(kTX * kTY * kSl), 0, s, ev,
                      te, n_tiles, time, times, tidx, i_in, i_base, i_out, static_cast<const StageConst<R>*>(sc), tb,
                      a, err);
   return hipGetLastError();
@@ -924,6 +922,29 @@ hipError_t batch_launch_s(int variant, const BatchEvent* ev, const int32_t* te, 
   case V:                                                                                                        \
     return batch_launch_t<R, STAGE, TY, W, NT>(ev, te, n_tiles, time, times, tidx, i_in, i_base, i_out, sc, tb, a,  \
                                                err, s);
+#define LB_BATCH_CASE_FM(V, TY, W, F, MU)                                                                         \
+  case V:                                                                                                        \
+    return batch_launch_t<R, STAGE, TY, W, 0, F, MU>(ev, te, n_tiles, time, times, tidx, i_in, i_base, i_out, sc,  \
+                                                     tb, a, err, s);
+  // the weak-form 3-D force or the conserved particle number: tile rows 2,
+  // 4, 8 at the occupancy of the single-event kernel (a block of 8 rows is
+  // 8 waves, so at least 2 waves per SIMD)
+  if (a.force_form == LB_FORCE_WEAK3D) {
+    switch (variant) {
+      LB_BATCH_CASE_FM(0, 2, ForceWaves<R>::v, 1, 0)
+      LB_BATCH_CASE_FM(1, 4, ForceWaves<R>::v, 1, 0)
+      LB_BATCH_CASE_FM(2, 8, 2, 1, 0)
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (a.mu_mode) {
+    switch (variant) {
+      LB_BATCH_CASE_FM(0, 2, MuWaves<R>::v, 0, 1)
+      LB_BATCH_CASE_FM(1, 4, MuWaves<R>::v, 0, 1)
+      LB_BATCH_CASE_FM(2, 8, MuWaves<R>::v, 0, 1)
+      default: return hipErrorInvalidValue;
+    }
+  }
   if constexpr (sizeof(R) == 8) {
     switch (variant) {
       LB_BATCH_CASE(0, 2, 2, 0)
@@ -949,6 +970,7 @@ hipError_t batch_launch_s(int variant, const BatchEvent* ev, const int32_t* te, 
     }
   }
 #undef LB_BATCH_CASE
+#undef LB_BATCH_CASE_FM
 }
 }  // namespace
 

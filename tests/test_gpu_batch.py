@@ -18,8 +18,8 @@ EVENTS = [(8, 8, 0.3, 0.08), (13, 7, 0.25, 0.2), (20, 16, 0.2, 0.12), (1, 3, 0.3
 DTAU = 0.01
 
 
-def _e0(params, nx, ny, dx, seed):
-    bg = lb.eos_eval(params, [0.2])[0, 0] / lb.HBARC ** 3
+def _e0(params, nx, ny, dx, seed, T_bg=0.2):
+    bg = lb.eos_eval(params, [T_bg])[0, 0] / lb.HBARC ** 3
     spots = wl.hot_spots(nx, ny, dx, n_spots=4, width=0.6, disk_radius=0.3 * max(nx, ny) * dx,
                          mean_amplitude=10.0, seed=seed)
     return torch.from_numpy(bg + spots).to(DEV)
@@ -62,6 +62,47 @@ def test_batch_equals_single_contexts_every_variant(precision):
             assert torch.equal(lb_, l)
             assert torch.equal(b.moments(e), obs)
         assert b.status() == lb.LB_OK
+        b.close()
+
+
+def _mode_params(mode, nx, ny, dx, eta, precision):
+    if mode == "force3d":
+        return lb.make_params(nx, ny, dx, eta_over_s=eta, precision=precision, force_form=lb.LB_FORCE_WEAK3D)
+    return lb.make_params(nx, ny, dx, eta_over_s=eta, precision=precision, eos_kind=lb.LB_EOS_CONST_MASS,
+                          eos_mass_GeV=0.4, Z=3.0, particle_number=lb.LB_N_CONSERVED, mu_over_T0=0.3)
+
+
+@pytest.mark.parametrize("mode", ["force3d", "mu"])
+@pytest.mark.parametrize("precision", [lb.LB_FP64, lb.LB_FP32_FP64MATCH])
+def test_batch_modes_equal_single_contexts(precision, mode):
+    # the weak-form 3-D force and the conserved particle number in the
+    # batched form: every variant, every event bitwise as lb_step
+    p = _mode_params(mode, 8, 8, 0.3, 0.1, precision)
+    # with the particle number conserved the heavy gas cools faster in the
+    # expansion: a hotter background keeps the cold sites inside the EoS range
+    T_bg = 0.35 if mode == "mu" else 0.2
+    e0s = [_e0(p, nx, ny, dx, 200 + i, T_bg) for i, (nx, ny, dx, _) in enumerate(EVENTS)]
+    n1, n2 = 50, 2
+    ref = []
+    for (nx, ny, dx, eta), e0 in zip(EVENTS, e0s):
+        c = lb.Context(_mode_params(mode, nx, ny, dx, eta, precision), e0)
+        c.step(n1 + n2, DTAU)
+        assert c.status() == lb.LB_OK
+        ref.append(c.get_state()[:2])
+        c.close()
+    for v in range(3):
+        print(f"batch {mode} precision {precision} variant {v}", flush=True)
+        b = lb.Batch(p, EVENTS, e0s)
+        b.set_variant(v)
+        b.step(n1, DTAU)
+        b.step(n2, DTAU)
+        assert b.status() == lb.LB_OK
+        for e, (F, l) in enumerate(ref):
+            Fb, lb_, _ = b.get_state(e)
+            assert torch.equal(Fb, F), f"variant {v} event {e}"
+            assert torch.equal(lb_, l)
+        with pytest.raises(lb.LbError):
+            b.set_variant(3)
         b.close()
 
 

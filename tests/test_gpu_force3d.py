@@ -132,7 +132,7 @@ def test_hot_spot_run_fp64_and_fp32(lat3, eos):
     assert tmunu_rel_err(o32, o64) < 1e-4
 
 
-def test_batched_and_adjoint_forms_reject_the_3d_force(eos):
+def test_adjoint_form_rejects_the_3d_force(eos):
     nx, ny, dx = 8, 8, 0.2
     e0 = float(eos.eps(0.3)) / HBARC ** 3 * np.ones((ny, nx))
     c = _ctx(nx, ny, dx, e0, lb.LB_FP64, 0.1)
@@ -140,10 +140,6 @@ def test_batched_and_adjoint_forms_reject_the_3d_force(eos):
     F, lnM, _ = c.get_state()
     with pytest.raises(lb.LbError) as ei:
         c.adjoint_forward_step(0.5, 0.005, F, lnM, ws)
-    assert ei.value.code == lb.LB_E_NOTIMPL
-    p = lb.make_params(nx, ny, dx, force_form=lb.LB_FORCE_WEAK3D)
-    with pytest.raises(lb.LbError) as ei:
-        lb.Batch(p, [(nx, ny, dx, 0.1)], [gpu(e0)])
     assert ei.value.code == lb.LB_E_NOTIMPL
 
 
