@@ -144,3 +144,31 @@ def test_adjoint_form_and_mixed_batch_reject_mu(eos):
     with pytest.raises(lb.LbError) as ei:
         lb.Batch(p, [(nx, ny, dx, 0.1)], [gpu(e0)])
     assert ei.value.code == lb.LB_E_NOTIMPL
+
+
+def test_bench_grid_sampled_parity(lat, eos):
+    # the 256 x 256 grid that the benchmark's conserved-number leg times
+    # (FP32, constant mass, mu0/T0 = 0.5): 30 steps, then one more step at
+    # sampled sites against the oracle on 9 x 9 periodic windows
+    from _helpers import patch
+    w = wl.WORKLOADS["prec"]
+    e0 = 1.5 + 40.0 * wl.gaussian_shape(w["nx"], w["ny"], w["dx"], 2.0) * wl.white_noise_factor(w["nx"], w["ny"])
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    print("mu mode 256x256 FP32, sampled sites", flush=True)
+    p = _params(w["nx"], w["ny"], w["dx"], lb.LB_FP32_FP64MATCH, w["eta_over_s"], 0.5)
+    p.tau0_fm = w["tau0"]
+    c = lb.Context(p, gpu(e0))
+    c.step(30, dtau)
+    F0, l0, tau = c.get_state()
+    F0, l0 = cpu(F0), cpu(l0)
+    c.step(1, dtau)
+    obs = cpu(c.moments())
+    assert c.status() == lb.LB_OK
+    prm = st.Params(dx=w["dx"], eta_over_s=w["eta_over_s"], conserve_n=True)
+    rng = np.random.default_rng(23)
+    sites = [(0, 0), (255, 255), (128, 128), (0, 200)] + [tuple(rng.integers(0, 256, 2)) for _ in range(6)]
+    for (cy, cx) in sites:
+        Fp, lp = patch(F0, cy, cx, 4), patch(l0, cy, cx, 4)
+        Fo, lo = st.heun_step(lat, eos, prm, Fp, lp, tau, dtau)
+        ref = st.observables(lat, eos, prm, Fo, lo)[:, 4:5, 4:5]
+        assert tmunu_rel_err(obs[:, cy:cy + 1, cx:cx + 1], ref) < 1e-5, (cy, cx)
