@@ -165,6 +165,41 @@ __device__ inline bool eos_mu(const EosTable& tb, double lam, double n, EosAt* o
   return ok;
 }
 
+// EoS at lambda = eps - B for the stage kernels' matching: one read of the
+// 4-point stencil of the table on the uniform g = ln(lambda) grid and a cubic
+// interpolation of T, M_eq/T, beta, q and B/T^4 (the table holds the
+// u-table's inversion at its nodes, so the two agree to the interpolation
+// error).  False if lambda is outside the accepted range.
+__device__ inline bool eos_g(const EosTable& tb, double lam, EosAt* o) {
+  const double g = log(lam);
+  double s = (g - tb.gg0) * tb.gg_inv_h;
+  const bool ok = (lam > 0.0) && (s >= 0.0) && (s <= (double)(tb.gn - 1));
+  if (!ok) s = (s > 0.0) ? (double)(tb.gn - 1) : 0.0;
+  int i = (int)s;
+  if (i < 1) i = 1;
+  if (i > tb.gn - 3) i = tb.gn - 3;
+  const double t = s - (double)i;
+  double w[4], dw[4];
+  lagrange4(t, w, dw);
+  const double* p = tb.gpts + (size_t)(i - 1) * kGFields;
+  double T = 0, z = 0, be = 0, q = 0, b4 = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* r = p + k * kGFields;
+    T += w[k] * r[kGT];
+    z += w[k] * r[kGZ];
+    be += w[k] * r[kGBeta];
+    q += w[k] * r[kGQ];
+    b4 += w[k] * r[kGBt4];
+  }
+  o->T = T;
+  o->M_eq = z * T;
+  o->beta = be;
+  o->q = q;
+  o->Bt4 = b4;
+  return ok;
+}
+
 // u-derivatives of the interpolated EoS at the solution of eos_cell (for the
 // adjoint): du/dlambda = 1/(lambda d lnEk/du), and dz/du, dbeta/du, dq/du of
 // the same cubic.

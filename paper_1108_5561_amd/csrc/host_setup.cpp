@@ -681,12 +681,41 @@ std::string build_tables(const lb_params& p, HostTables* out) {
   D.ge_inv_h = 1.0 / D.ge_h;
   D.inv_ek = T.inv_ek.data();
   D.inv_ee = T.inv_ee.data();
+  // the g table: the u-table cubic inverted at each g_i = ln(eps - B) of a
+  // uniform grid over the accepted range, and its fields there
+  {
+    const int gn = kGPoints;
+    const double ga = D.gk0, gb = D.gk0 + (ninv - 1) * D.gk_h;
+    D.gn = gn;
+    D.gpad_ = 0;
+    D.gg0 = ga;
+    D.gg_h = (gb - ga) / (gn - 1);
+    D.gg_inv_h = 1.0 / D.gg_h;
+    T.gpts.assign((size_t)gn * kGFields, 0.0);
+    for (int i = 0; i < gn; ++i) {
+      const double g = ga + i * D.gg_h;
+      double lo = ulo - 2 * h, hi = uhi + 2 * h;
+      for (int it = 0; it < 80; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (fwd(kLnEk, mid) < g) lo = mid; else hi = mid;
+      }
+      const double u = 0.5 * (lo + hi);
+      double* d = &T.gpts[(size_t)i * kGFields];
+      d[kGT] = std::exp(u);
+      d[kGZ] = fwd(kZ, u);
+      d[kGBeta] = fwd(kBeta, u);
+      d[kGQ] = fwd(kQ, u);
+      d[kGBt4] = fwd(kBt4, u);
+    }
+    D.gpts = T.gpts.data();
+  }
   if (cacheable) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     g_cache = T;
     g_cache.desc.pts = g_cache.pts.data();
     g_cache.desc.inv_ek = g_cache.inv_ek.data();
     g_cache.desc.inv_ee = g_cache.inv_ee.data();
+    g_cache.desc.gpts = g_cache.gpts.data();
     g_cache_key = key;
     g_cache_valid = true;
   }
@@ -694,6 +723,7 @@ std::string build_tables(const lb_params& p, HostTables* out) {
   out->desc.pts = out->pts.data();
   out->desc.inv_ek = out->inv_ek.data();
   out->desc.inv_ee = out->inv_ee.data();
+  out->desc.gpts = out->gpts.data();
   return "";
 }
 

@@ -52,7 +52,7 @@ class HostEos {
 };
 
 struct HostTables {
-  std::vector<double> pts, inv_ek, inv_ee;
+  std::vector<double> pts, inv_ek, inv_ee, gpts;
   EosTable desc;  // pointers filled in when copied to the device
 };
 
@@ -62,5 +62,6 @@ std::string build_tables(const lb_params& p, HostTables* out);
 // Expected table point count (for workspace sizing).
 constexpr int kTablePoints = 32768;
 constexpr int kInvPoints = 32768;
+constexpr int kGPoints = 32768;
 
 }  // namespace lbmi

@@ -54,7 +54,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t F[3], lnM[3], sc[3], cst, tbd, pts, inv_ek, inv_ee, err, total;
+  size_t F[3], lnM[3], sc[3], cst, tbd, pts, inv_ek, inv_ee, gpts, err, total;
 };
 
 std::string validate(const lb_params* p) {
@@ -141,6 +141,8 @@ Layout layout(const lb_params* p) {
   off = align_up(off + (size_t)kInvPoints * 8);
   L.inv_ee = off;
   off = align_up(off + (size_t)kInvPoints * 8);
+  L.gpts = off;
+  off = align_up(off + (size_t)kGPoints * kGFields * 8);
   L.err = off;
   off = align_up(off + 256);
   L.total = off;
@@ -490,17 +492,20 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
   double* d_pts = (double*)(c->ws + L.pts);
   double* d_iek = (double*)(c->ws + L.inv_ek);
   double* d_iee = (double*)(c->ws + L.inv_ee);
+  double* d_gpts = (double*)(c->ws + L.gpts);
   c->err = (int*)(c->ws + L.err);
   c->tb = T.desc;
   c->tb.pts = d_pts;
   c->tb.inv_ek = d_iek;
   c->tb.inv_ee = d_iee;
+  c->tb.gpts = d_gpts;
   hipError_t e;
   if ((e = hipGetDevice(&c->device)) != hipSuccess) { delete c; return hip_fail(e, "hipGetDevice"); }
   // synchronous copies: the host staging buffers die with this call
   if ((e = hipMemcpy(d_pts, T.pts.data(), T.pts.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_iek, T.inv_ek.data(), T.inv_ek.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_iee, T.inv_ee.data(), T.inv_ee.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_gpts, T.gpts.data(), T.gpts.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(c->tbd, &c->tb, sizeof(EosTable), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemsetAsync(c->err, 0, sizeof(int), c->stream)) != hipSuccess) {
     delete c;
@@ -877,7 +882,7 @@ namespace {
 constexpr int kBatchGraphSteps = 48;  // steps per captured graph (a multiple of 3)
 
 struct BatchLayout {
-  size_t cst, tbd, pts, inv_ek, inv_ee, err, ev, tile_event, times, total;
+  size_t cst, tbd, pts, inv_ek, inv_ee, gpts, err, ev, tile_event, times, total;
   std::vector<size_t> F, lnM, sc;  // [event * 3 + i]
 };
 
@@ -919,6 +924,8 @@ BatchLayout batch_layout(const lb_params* p, const lb_event* ev, int32_t n) {
   off = align_up(off + (size_t)kInvPoints * 8);
   L.inv_ee = off;
   off = align_up(off + (size_t)kInvPoints * 8);
+  L.gpts = off;
+  off = align_up(off + (size_t)kGPoints * kGFields * 8);
   L.err = off;
   off = align_up(off + 256);
   L.ev = off;
@@ -1182,6 +1189,7 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
   b->tb.pts = (double*)(b->ws + L.pts);
   b->tb.inv_ek = (double*)(b->ws + L.inv_ek);
   b->tb.inv_ee = (double*)(b->ws + L.inv_ee);
+  b->tb.gpts = (double*)(b->ws + L.gpts);
   b->ev.resize(n_events);
   for (int i = 0; i < n_events; ++i) {
     BatchEvent& E = b->ev[i];
@@ -1211,6 +1219,7 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
           hipSuccess ||
       (e = hipMemcpy((void*)b->tb.inv_ee, T.inv_ee.data(), T.inv_ee.size() * 8, hipMemcpyHostToDevice)) !=
           hipSuccess ||
+      (e = hipMemcpy((void*)b->tb.gpts, T.gpts.data(), T.gpts.size() * 8, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(b->tbd, &b->tb, sizeof(EosTable), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemsetAsync(b->err, 0, sizeof(int), b->stream)) != hipSuccess) {
     lb_batch_destroy(b);

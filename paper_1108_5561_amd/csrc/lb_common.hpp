@@ -23,6 +23,10 @@ enum EosField : int {
   kFields = 8   // 64 bytes per point
 };
 
+// Fields of one point of the table on a uniform grid in g = ln(eps - B),
+// read by the stage kernels' matching: no root finding on the device.
+enum EosGField : int { kGT = 0, kGZ = 1, kGBeta = 2, kGQ = 3, kGBt4 = 4, kGFields = 8 };
+
 struct EosTable {
   const double* pts;     // [n][kFields]
   const double* inv_ek;  // [n_inv]: u with lnEk(u) = gk0 + i gk_h
@@ -32,6 +36,9 @@ struct EosTable {
   double gk0, gk_h, gk_inv_h;
   double ge0, ge_h, ge_inv_h;
   double u_lo, u_hi;     // accepted range ln T_min .. ln T_max
+  const double* gpts;    // [gn][kGFields]: T, M/T, beta, q, B/T^4 at g_i = gg0 + i gg_h
+  int32_t gn, gpad_;
+  double gg0, gg_h, gg_inv_h;
 };
 
 // 4-point Lagrange weights on nodes -1, 0, 1, 2 at t in [0, 1), and their

@@ -263,6 +263,12 @@ __device__ __forceinline__ EosTable load_table(const EosTable* p) {
   t.ge_inv_h = q->ge_inv_h;
   t.u_lo = q->u_lo;
   t.u_hi = q->u_hi;
+  t.gpts = q->gpts;
+  t.gn = q->gn;
+  t.gpad_ = 0;
+  t.gg0 = q->gg0;
+  t.gg_h = q->gg_h;
+  t.gg_inv_h = q->gg_inv_h;
   return t;
 }
 // ---- weak-form 3-D mass-gradient force ---------------------------------
@@ -558,7 +564,7 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
     const double n = G / M * (u[0] * s_mom[7][t] - u[1] * s_mom[8][t] - u[2] * s_mom[9][t]);
     eos_ok = eos_mu(tb, lam, n, &E, &alpha);
   } else {
-    eos_ok = eos_cell(tb, lam, &E);
+    eos_ok = eos_g(tb, lam, &E);
   }
   if (!finite) flag(err, kErrNonfinite);
   else if (!matched) flag(err, kErrMatch);
