@@ -241,7 +241,9 @@ __device__ __forceinline__ CPtr<R> const_ptr(const StageConst<R>* p) {
   return (CPtr<R>)v;
 }
 // The EoS table descriptor from its device copy, with scalar loads at the
-// point of use.
+// point of use.  Field by field: a field added to EosTable must be added
+// here too (the size check below fails until it is).
+static_assert(sizeof(EosTable) == 160, "EosTable changed: update load_table");
 __device__ __forceinline__ EosTable load_table(const EosTable* p) {
   uint64_t v = (uint64_t)p;
   asm volatile("" : "+s"(v));
