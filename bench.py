@@ -95,6 +95,39 @@ def run_gpu(lb, wl, torch, precision, steps, warmup, force=0):
     return dict(ms=ms, wall=wall, n_sites=n_sites, pred_ms=ms_pred, corr_ms=ms_corr, obs=obs, e0=e0, dtau=dtau)
 
 
+def run_dram(lb, wl, torch, steps=100, warmup=10):
+    """The FP32 step on the 512 x 512 hot-spot workload (40 spots on the
+    floor eps_EoS(0.25 GeV), eta/s 0.16): three state buffers of 210 MB
+    exceed the 256 MB last-level cache, so the stages stream from DRAM
+    (large-grid mode).  Throughput and the corrector's algorithmic HBM rate
+    from HIP events around 100 back-to-back launches."""
+    w = wl.WORKLOADS["spots"]
+    n, dx = w["nx"], w["dx"]
+    p = lb.make_params(n, n, dx, tau0_fm=w["tau0"], eta_over_s=w["eta_over_s"], precision=lb.LB_FP32_FP64MATCH)
+    e_floor = lb.eos_eval(p, [0.25])[0, 0] / lb.HBARC ** 3
+    e0 = e_floor + wl.hot_spots(n, n, dx, seed=3)
+    c = lb.Context(p, torch.from_numpy(e0).to("cuda:0"))
+    dtau = (w["tau1"] - w["tau0"]) / w["steps"]
+    c.step(warmup, dtau)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    c.step(steps, dtau)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    corr = c.profile_stage(1, 100, dtau)
+    pred = c.profile_stage(0, 100, dtau)
+    if c.status() != lb.LB_OK:
+        raise RuntimeError(lb.last_error())
+    sites = n * n
+    gbs = site_bytes("fp32", 1) * sites / (corr / 1e3) / 1e9
+    return {"workload": "512x512 hot spots, dx 0.03 fm, eta/s 0.16 (state above the last-level cache)",
+            "value": steps * sites / (ms / 1e3), "unit": "site-updates/s", "ms_per_step": ms / steps,
+            "pred_ms": pred, "corr_ms": corr, "corr_algorithmic_GBps": gbs, "corr_frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+            "step_algorithmic_GBps": (site_bytes("fp32", 0) + site_bytes("fp32", 1)) * sites * steps / (ms / 1e3) / 1e9}
+
+
 def run_force3d(lb, wl, torch, steps=200, warmup=10):
     """The plain FP32 step with the weak-form 3-D mass-gradient force
     (LB_FORCE_WEAK3D) on the same 256 x 256 workload: throughput, stage
@@ -317,6 +350,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiable-form measurement")
     ap.add_argument("--no-force3d", action="store_true", help="skip the weak-form 3-D force measurement")
     ap.add_argument("--no-number", action="store_true", help="skip the conserved-particle-number measurement")
+    ap.add_argument("--no-dram", action="store_true", help="skip the 512 x 512 (DRAM-regime) measurement")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the differentiable-form measurement (one JSON object)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -372,6 +406,7 @@ def main():
     adjoint = None if args.no_adjoint else optional(run_adjoint)
     force3d = None if args.no_force3d else optional(run_force3d)
     number = None if args.no_number else optional(run_number)
+    dram = None if args.no_dram else optional(run_dram)
 
     out = {
         "metric": "site-updates/s & HBM GB/s: FP32+FP64-match vs FP64 step at 1e-5 rel err",
@@ -402,6 +437,7 @@ def main():
         "force3d": force3d if force3d is None or "error" in force3d else dict(
             force3d, vs_feq_force_step=force3d["value"] / sups32),
         "conserved_n": number,
+        "dram_regime": dram,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
