@@ -103,6 +103,43 @@ def test_one_step_fp32(lat, eos):
     assert tmunu_rel_err(cpu(c.moments()), st.observables(lat, eos, prm, Fo, lo)) < 1e-5
 
 
+@pytest.mark.parametrize("precision", [lb.LB_FP64, lb.LB_FP32_FP64MATCH])
+def test_one_step_with_3d_force(eos, precision):
+    # both kernel flags together (n matching and the weak-form 3-D force);
+    # ln M is perturbed so that the force, proportional to its gradient, does
+    # not vanish on the constant-mass gas
+    lat3 = Lattice(5, 5, 4, 1.0, force="weak3d")
+    nx, ny, dx, dtau, eta = 17, 11, 0.2, 0.01, 0.1
+    e0 = _e0(nx, ny, dx)
+    ux, uy = wl.random_flow(nx, ny, 0.15, seed=9)
+    F, l = st.init_state(lat3, eos, e0, ux, uy, alpha0=0.3)
+    rng = np.random.default_rng(9)
+    F = F * (1 + 0.05 * rng.random(F.shape))
+    l = l + 0.02 * rng.standard_normal(l.shape)
+    print(f"mu mode with the 3-D force, precision {precision}, {nx}x{ny}", flush=True)
+    out = {}
+    for force in (lb.LB_FORCE_WEAK3D, lb.LB_FORCE_FEQ):
+        p = _params(nx, ny, dx, precision, eta, 0.3)
+        p.force_form = force
+        c = lb.Context(p, gpu(e0))
+        c.set_state(gpu(F), gpu(l), 0.7)
+        c.step(1, dtau)
+        assert c.status() == lb.LB_OK
+        out[force] = (cpu(c.get_state()[0]), cpu(c.moments()))
+    prm = st.Params(dx=dx, eta_over_s=eta, conserve_n=True)
+    Fin = F if precision == lb.LB_FP64 else F.astype(np.float32).astype(np.float64)
+    Fo, lo = st.heun_step(lat3, eos, prm, Fin, l, 0.7, dtau)
+    Fg, obs = out[lb.LB_FORCE_WEAK3D]
+    ref = st.observables(lat3, eos, prm, Fo, lo)
+    if precision == lb.LB_FP64:
+        assert np.max(np.abs(Fg - Fo)) < 1e-10 * Fo.max()
+        assert tmunu_rel_err(obs, ref) < 1e-10
+    else:
+        assert tmunu_rel_err(obs, ref) < 1e-5
+    # the F_eq force gives another step, far beyond the bar
+    assert np.max(np.abs(out[lb.LB_FORCE_FEQ][0] - Fg)) > 1e-4 * np.max(np.abs(Fg))
+
+
 def test_run_conserves_particle_number(lat, eos):
     # Minkowski metric, periodic box: 30 FP64 steps against the oracle, and
     # the total N^tau kept to the equilibrium quadrature error with the n
