@@ -139,8 +139,10 @@ typedef struct lb_params {
    *   nodes).  Energy, momentum and particle-number moments of the force
    *   then follow the balance laws exactly for any F.  It mixes the phi
    *   slices (a real Fourier transform over them), so the stage does about
-   *   twice the arithmetic.  lb_step and the batched form; the adjoint
-   *   entry points return LB_E_NOTIMPL for it. */
+   *   twice the arithmetic.  lb_step, the batched form and the adjoint
+   *   entry points (the FP64 adjoint applies the operators as two dense
+   *   N x N matrices, built at lb_init from the stage kernels' own code;
+   *   the context's workspace holds them, 2 N^2 doubles). */
   int32_t force_form;
   /* LB_N_FREE: the equilibrium is matched to the energy density only (mu = 0,
    * as in the paper's runs).  LB_N_CONSERVED: also to the particle density
@@ -224,7 +226,8 @@ int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_f
  * The step differentiated is the FP64 Heun step of Sec. IV.D as lb_step
  * computes it for an LB_FP64 context (same right-hand side: streaming,
  * Milne term, BGK of eq. (bgk) with the equilibrium of eq. (feq) and the
- * mass-gradient force, mass evolution of eqs. (edchange), (masschange); T, u
+ * mass-gradient force of either force_form, mass evolution of eqs.
+ * (edchange), (masschange); T, u
  * and M_eq from the Landau matching of eq. (sanity) and the EoS inversion
  * of Sec. III.A, whose derivatives are taken by the implicit-function
  * theorem).  States and adjoints are in the canonical order of
@@ -236,6 +239,7 @@ int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_f
  * The adjoint workspace is caller-owned device memory, 256-byte aligned, of
  * at least lb_adjoint_workspace_bytes(p) bytes, not touched by anyone else
  * during a call.  Calls are asynchronous on the context's stream.
+ * LB_E_NOTIMPL for a context with particle_number LB_N_CONSERVED.
  */
 
 /* Adjoint workspace size for these parameters (0 on invalid parameters). */

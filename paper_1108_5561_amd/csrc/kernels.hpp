@@ -98,21 +98,28 @@ hipError_t launch_get_state(int precision, const void* F, double* Fc, int n_q, i
 hipError_t launch_set_state(int precision, const double* Fc, void* F, int n_q, int n_sites,
                             hipStream_t s);
 
+// Dense weak-form force operators G [2][200][200] (canonical node order,
+// G_i[n][m]) from the stage kernels' weak_force, given a device
+// StageConst<double> with the force constants.
+hipError_t launch_force_columns(const void* cst64, double* G, hipStream_t s);
+
 // Adjoint of the FP64 step (lb_adjoint.hip), canonical layout F[n][site].
+// g3 is the dense force operator of launch_force_columns for the weak-form
+// 3-D force, or nullptr for the force on F_eq.
 // One stage of the step: stage 0 Fout = Fin + dtau K(Fin), stage 1
 // Fout = (Fbase + Fin)/2 + dtau/2 K(Fin), ln M likewise; lc points to the
 // context's LatticeConst<double, 5, 5>.
 hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const double* Fbase, const double* Lbase,
-                                double* Fout, double* Lout, int stage, const void* lc, const EosTable& tb,
-                                const StageArgs& a, int* err, hipStream_t s);
+                                double* Fout, double* Lout, int stage, const void* lc, const double* g3,
+                                const EosTable& tb, const StageArgs& a, int* err, hipStream_t s);
 // Reverse sweep of one right-hand side at (F, ln M), time a.tau, with
 // K_bar = scale seedF, X_bar = scale seedL, into (outF, outL) (written, or
 // added with accumulate = 1), plus the per-site eta/s adjoint; Rb
 // ([N][sites]) and gb ([2][sites]) are scratch.
 hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF, const double* seedL,
                           double scale, double* outF, double* outL, double* Rb, double* gb, double* eta_part,
-                          int accumulate, const void* lc, const EosTable& tb, const StageArgs& a, int* err,
-                          hipStream_t s);
+                          int accumulate, const void* lc, const double* g3, const EosTable& tb,
+                          const StageArgs& a, int* err, hipStream_t s);
 // y += c x, then z *= cz (z may be null), n values.
 hipError_t launch_adj_axpy(double* y, const double* x, double c, double* z, double cz, size_t n, hipStream_t s);
 // *out += sum of v[0..n), deterministic order.

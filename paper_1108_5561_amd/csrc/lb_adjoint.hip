@@ -159,11 +159,14 @@ struct SliceAux {
   double cu, Gl, gu;
   double Eeq[5], al[5], be[5], ga[5];
 };
-__device__ __forceinline__ void slice_aux(const SiteFwd& s, const SliceGeom& gm, const LC& C, SliceAux* o) {
+// With the weak-form 3-D force (f3) the force acts on F instead (force_row)
+// and the polynomial on F_eq vanishes: Gl = gu = 0.
+__device__ __forceinline__ void slice_aux(const SiteFwd& s, const SliceGeom& gm, const LC& C, bool f3,
+                                          SliceAux* o) {
   const double ut = s.u[0], ux = s.u[1], uy = s.u[2], Meq = s.E.M_eq, M = s.M;
   o->cu = ux * gm.cl + uy * gm.sl;
-  o->Gl = s.gx * gm.cl + s.gy * gm.sl;
-  o->gu = s.gx * ux + s.gy * uy;
+  o->Gl = f3 ? 0.0 : s.gx * gm.cl + s.gy * gm.sl;
+  o->gu = f3 ? 0.0 : s.gx * ux + s.gy * uy;
   for (int k = 0; k < 5; ++k) {
     o->Eeq[k] = sqrt(Meq * Meq + M * M * C.sh2[k]);
     o->al[k] = s.MT * o->Gl * ut * M * C.x[k] / o->Eeq[k];
@@ -182,10 +185,28 @@ __device__ __forceinline__ void node_terms(const SiteFwd& s, const SliceAux& o, 
   *poly = o.al[k] * sg - o.be[k] * C.sig2[q] - o.ga[k];
 }
 
+// Row n of the weak-form 3-D force operators applied to the site's state:
+// (G_x F)_n and (G_y F)_n, with g3 = G [2][kN][kN] (canonical node order)
+// and F in the canonical layout.
+constexpr int kN = kQ * kL;  // nodes per site
+__device__ __forceinline__ void force_row(const double* __restrict__ g3, const double* __restrict__ F, int site,
+                                          int ns, int n, double* gxf, double* gyf) {
+  const double* rx = g3 + (size_t)n * kN;
+  const double* ry = rx + (size_t)kN * kN;
+  double ax = 0, ay = 0;
+  for (int m = 0; m < kN; ++m) {
+    const double fm = F[(size_t)m * ns + site];
+    ax += rx[m] * fm;
+    ay += ry[m] * fm;
+  }
+  *gxf = ax;
+  *gyf = ay;
+}
+
 // R0 and S2 of the thread's slice and its parts of the three site sums.
 __device__ void slice_rhs(const double* __restrict__ F, const double f[kQ], const Lane& g, const SliceGeom& gm,
-                          const SiteFwd& s, const SliceAux& o, const LC& C, const StageArgs& a, double R0[kQ],
-                          double S2[kQ], double sums[3]) {
+                          const SiteFwd& s, const SliceAux& o, const LC& C, const StageArgs& a,
+                          const double* __restrict__ g3, double R0[kQ], double S2[kQ], double sums[3]) {
   const int ns = a.n_sites, x = g.x, y = g.y, l = g.l;
   // streaming (3 F_i - 4 F_{i-1} + F_{i-2}) |cos phi| / (2 dx), periodic
   const int x1 = wrap(x - gm.dxr, a.nx), x2 = wrap(x - 2 * gm.dxr, a.nx);
@@ -211,6 +232,12 @@ __device__ void slice_rhs(const double* __restrict__ F, const double f[kQ], cons
       S2[k * 5 + j] = s2;
       if (milne) R0[k * 5 + j] += (C.mu2[j] * s1r - s1p) * itau;
     }
+  if (g3)  // weak-form 3-D force on F: g_x G_x F + g_y G_y F
+    for (int q = 0; q < kQ; ++q) {
+      double gxf, gyf;
+      force_row(g3, F, g.site, ns, q * kL + l, &gxf, &gyf);
+      R0[q] += s.gx * gxf + s.gy * gyf;
+    }
   sums[0] = sums[1] = sums[2] = 0;
   for (int q = 0; q < kQ; ++q) {
     double feq, uvg, poly;
@@ -234,8 +261,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_fwd_kernel(const double* __re
                                                               const double* __restrict__ Lbase,
                                                               double* __restrict__ Fout,
                                                               double* __restrict__ Lout, int stage, const LC C,
-                                                              const EosTable tb, const StageArgs a,
-                                                              int* __restrict__ err) {
+                                                              const double* __restrict__ g3, const EosTable tb,
+                                                              const StageArgs a, int* __restrict__ err) {
   __shared__ RedBuf red;
   const Lane g = lane_of(a);
   const int ns = a.n_sites;
@@ -245,9 +272,9 @@ __global__ __launch_bounds__(kAdjThreads) void adj_fwd_kernel(const double* __re
   site_fwd(f, Lin, g, C, tb, a, red, &s, err);
   const SliceGeom gm = slice_geom(C, a, g.l);
   SliceAux o;
-  slice_aux(s, gm, C, &o);
+  slice_aux(s, gm, C, g3 != nullptr, &o);
   double R0[kQ], S2[kQ], sums[3];
-  slice_rhs(Fin, f, g, gm, s, o, C, a, R0, S2, sums);
+  slice_rhs(Fin, f, g, gm, s, o, C, a, g3, R0, S2, sums);
   slice_sum<3>(sums, red, g);
   const double X = -s.beta * sums[0] / (sums[2] + s.beta * sums[1]);
   if (!g.valid) return;
@@ -275,7 +302,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
     const double* __restrict__ F, const double* __restrict__ Lm, const double* __restrict__ seedF,
     const double* __restrict__ seedL, double scale, double* __restrict__ outF, double* __restrict__ outL,
     double* __restrict__ Rb, double* __restrict__ gb, double* __restrict__ eta_part, int accumulate,
-    const LC C, const EosTable tb, const StageArgs a, int* __restrict__ err) {
+    const LC C, const double* __restrict__ g3, const EosTable tb, const StageArgs a, int* __restrict__ err) {
   __shared__ RedBuf red;
   const Lane g = lane_of(a);
   const int ns = a.n_sites, l = g.l;
@@ -285,10 +312,10 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   site_fwd(f, Lm, g, C, tb, a, red, &s, err);
   const SliceGeom gm = slice_geom(C, a, l);
   SliceAux o;
-  slice_aux(s, gm, C, &o);
+  slice_aux(s, gm, C, g3 != nullptr, &o);
   double R0[kQ], S2[kQ], Kb[kQ];
   double sums[4];
-  slice_rhs(F, f, g, gm, s, o, C, a, R0, S2, sums);
+  slice_rhs(F, f, g, gm, s, o, C, a, g3, R0, S2, sums);
   sums[3] = 0;
   for (int q = 0; q < kQ; ++q) {
     Kb[q] = scale * seedF[cix(q, l, g.site, ns)];
@@ -308,12 +335,19 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   double cub = 0, Glb = 0, gub = 0, utb = 0, Mb = 0, invTb = 0, rateb = 0;
   double alb[5] = {0, 0, 0, 0, 0}, beb[5] = {0, 0, 0, 0, 0}, gab[5] = {0, 0, 0, 0, 0};
   double Eeqb[5] = {0, 0, 0, 0, 0};
+  double g3xb = 0, g3yb = 0;  // 3-D force: this slice's part of d/d g_x, d/d g_y
   for (int q = 0; q < kQ; ++q) {
     const int k = q / 5;
     double feq, uv, poly;
     node_terms(s, o, C, a, q, &feq, &uv, &poly);
     const double wuv2 = C.wx2[q] * uv * uv;
     R0b[q] = Kb[q] + wuv2 * nb;
+    if (g3) {
+      double gxf, gyf;
+      force_row(g3, F, g.site, ns, q * kL + l, &gxf, &gyf);
+      g3xb += R0b[q] * gxf;
+      g3yb += R0b[q] * gyf;
+    }
     S2b[q] = X * Kb[q] + wuv2 * dsb;
     const double ru = s.rate * uv;
     fb[q] = 4.0 * wuv2 * dsb + C.w[q] * wsb - ru * R0b[q];
@@ -368,8 +402,13 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
     Meqb += Eeqb[k] * Meq / o.Eeq[k];
     Mb += Eeqb[k] * M * C.sh2[k] / o.Eeq[k];
   }
-  // cu = u_perp.(cos, sin), Gl = grad ln M.(cos, sin), gu = grad ln M.u_perp;
-  // then the site totals over the eight slices
+  // cu = u_perp.(cos, sin), Gl = grad ln M.(cos, sin), gu = grad ln M.u_perp
+  // (zero with the 3-D force, whose gradient adjoint is g3xb, g3yb); then
+  // the site totals over the eight slices
+  if (g3) {
+    Glb = 0;
+    gub = 0;
+  }
   double v[kRed] = {utb,
                     cub * gm.cl + gub * s.gx,
                     cub * gm.sl + gub * s.gy,
@@ -378,8 +417,8 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
                     MTb,
                     rateb,
                     Meqb,
-                    Glb * gm.cl + gub * s.u[1],
-                    Glb * gm.sl + gub * s.u[2]};
+                    Glb * gm.cl + gub * s.u[1] + g3xb,
+                    Glb * gm.sl + gub * s.u[2] + g3yb};
   slice_sum<kRed>(v, red, g);
   utb = v[0];
   const double uxb = v[1], uyb = v[2];
@@ -455,10 +494,15 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
 // Transposed streaming stencil and transposed centred ln M gradient:
 // outF_n(s) += sum over the sites s' whose stencil reads s of the stencil
 // weight times Rb_n(s'); outL(s) += (gb_x(s - 1) - gb_x(s + 1) + ...)/(2 dx).
+// With the weak-form 3-D force (g3) also the transposed force:
+// outF_m(s) += sum_n Rb_n(s) (g_x G_x[n][m] + g_y G_y[n][m]) at the site's
+// own ln M gradient (Lm, the state of the right-hand side).
 __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const double* __restrict__ Rb,
                                                                  const double* __restrict__ gb,
                                                                  double* __restrict__ outF,
                                                                  double* __restrict__ outL, const LC C,
+                                                                 const double* __restrict__ Lm,
+                                                                 const double* __restrict__ g3,
                                                                  const StageArgs a) {
   const Lane g = lane_of(a);
   if (!g.valid) return;
@@ -471,6 +515,19 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const double* _
                      gm.ax * Rb[cix(q, l, s2, ns)] - 4.0 * gm.ay * Rb[cix(q, l, s3, ns)] +
                      gm.ay * Rb[cix(q, l, s4, ns)];
     outF[cix(q, l, site, ns)] -= C.sigi[q] * t;
+  }
+  if (g3) {
+    const double gx = (Lm[y * a.nx + wrap(x + 1, a.nx)] - Lm[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
+    const double gy = (Lm[wrap(y + 1, a.ny) * a.nx + x] - Lm[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
+    const double* gxc = g3;
+    const double* gyc = g3 + (size_t)kN * kN;
+    for (int q = 0; q < kQ; ++q) {
+      const int m = q * kL + l;
+      double acc = 0;
+      for (int n = 0; n < kN; ++n)
+        acc += Rb[(size_t)n * ns + site] * (gx * gxc[(size_t)n * kN + m] + gy * gyc[(size_t)n * kN + m]);
+      outF[cix(q, l, site, ns)] += acc;
+    }
   }
   if (l == 0) {
     const int xm = y * a.nx + wrap(x - 1, a.nx), xp = y * a.nx + wrap(x + 1, a.nx);
@@ -552,23 +609,24 @@ dim3 sites_grid(int n) { return dim3((unsigned)((n + kSites - 1) / kSites)); }
 }  // namespace
 
 hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const double* Fbase, const double* Lbase,
-                                double* Fout, double* Lout, int stage, const void* lc, const EosTable& tb,
-                                const StageArgs& a, int* err, hipStream_t s) {
+                                double* Fout, double* Lout, int stage, const void* lc, const double* g3,
+                                const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
   hipLaunchKernelGGL(adj_fwd_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout,
-                     Lout, stage, *static_cast<const LC*>(lc), tb, a, err);
+                     Lout, stage, *static_cast<const LC*>(lc), g3, tb, a, err);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF, const double* seedL,
                           double scale, double* outF, double* outL, double* Rb, double* gb, double* eta_part,
-                          int accumulate, const void* lc, const EosTable& tb, const StageArgs& a, int* err,
-                          hipStream_t s) {
+                          int accumulate, const void* lc, const double* g3, const EosTable& tb,
+                          const StageArgs& a, int* err, hipStream_t s) {
   const LC& C = *static_cast<const LC*>(lc);
   hipLaunchKernelGGL(adj_local_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL, scale,
-                     outF, outL, Rb, gb, eta_part, accumulate, C, tb, a, err);
+                     outF, outL, Rb, gb, eta_part, accumulate, C, g3, tb, a, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adj_gather_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Rb, gb, outF, outL, C, a);
+  hipLaunchKernelGGL(adj_gather_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Rb, gb, outF, outL, C, Lm,
+                     g3, a);
   return hipGetLastError();
 }
 

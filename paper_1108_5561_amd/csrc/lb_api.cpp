@@ -31,6 +31,7 @@ struct lb_ctx {
   HostLattice lat;
   LatticeConst<float, 5, 5> cf{};
   LatticeConst<double, 5, 5> cd{};
+  double* g3 = nullptr;  // dense weak-form force operators [2][N][N] (3-D force only)
   double tau = 0;
   bool initialised = false;
   // profiling
@@ -54,7 +55,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t F[3], lnM[3], sc[3], cst, tbd, pts, inv_ek, inv_ee, gpts, err, total;
+  size_t F[3], lnM[3], sc[3], cst, tbd, pts, inv_ek, inv_ee, gpts, err, cst64, g3, total;
 };
 
 std::string validate(const lb_params* p) {
@@ -145,6 +146,16 @@ Layout layout(const lb_params* p) {
   off = align_up(off + (size_t)kGPoints * kGFields * 8);
   L.err = off;
   off = align_up(off + 256);
+  // the weak-form 3-D force: FP64 stage constants and the dense operators
+  // [2][N][N] of the FP64 adjoint
+  L.cst64 = L.g3 = 0;
+  if (p->force_form == LB_FORCE_WEAK3D) {
+    const size_t nodes = (size_t)p->n_xi * p->n_theta * 2 * p->n_phi;
+    L.cst64 = off;
+    off = align_up(off + sizeof(StageConst<double>));
+    L.g3 = off;
+    off = align_up(off + 2 * nodes * nodes * sizeof(double));
+  }
   L.total = off;
   return L;
 }
@@ -399,7 +410,6 @@ struct AdjBufs {
 };
 int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBufs* B) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
-  if (c->p.force_form != LB_FORCE_FEQ) return fail(LB_E_NOTIMPL, "the adjoint step has the F_eq force only");
   if (c->p.particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the adjoint step has mu = 0 only");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
   if (!std::isfinite(tau) || (c->p.metric == LB_METRIC_MILNE && !(tau > 0)))
@@ -527,6 +537,18 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
       delete c;
       return hip_fail(e, "upload of stage constants");
     }
+    if (p->force_form == LB_FORCE_WEAK3D) {
+      // the dense operators that the FP64 adjoint applies, from the same
+      // device code as the stage kernels (FP64 constants for either precision)
+      fill_stage_const(c->lat, &sd);
+      c->g3 = (double*)(c->ws + L.g3);
+      e = hipMemcpy(c->ws + L.cst64, &sd, sizeof(sd), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = launch_force_columns(c->ws + L.cst64, c->g3, c->stream);
+      if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "dense force operators");
+      }
+    }
   }
   c->tau = p->tau0_fm;
   c->cur = 0;
@@ -649,10 +671,10 @@ int lb_adjoint_forward_step(lb_ctx* c, double tau_fm, double dtau_fm, const doub
   if (d_F_out == d_F || d_lnM_out == d_lnM) return fail(LB_E_ARG, "outputs must not alias the inputs");
   StageArgs a = stage_args(c, tau_fm, dtau_fm);
   hipError_t e =
-      launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->tb, a, c->err, c->stream);
+      launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->g3, c->tb, a, c->err, c->stream);
   if (e == hipSuccess) {
     set_tau(&a, c, tau_fm + dtau_fm);
-    e = launch_adj_stage_fwd(B.Fp, B.Lp, d_F, d_lnM, d_F_out, d_lnM_out, 1, &c->cd, c->tb, a, c->err, c->stream);
+    e = launch_adj_stage_fwd(B.Fp, B.Lp, d_F, d_lnM, d_F_out, d_lnM_out, 1, &c->cd, c->g3, c->tb, a, c->err, c->stream);
   }
   return e == hipSuccess ? LB_OK : hip_fail(e, "adjoint forward step");
 }
@@ -671,19 +693,19 @@ int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F,
   set_tau(&a1, c, tau_fm + dtau_fm);
   hipStream_t st = c->stream;
   // predictor state F* = F + dtau K(F)
-  hipError_t e = launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->tb, a0, c->err, st);
+  hipError_t e = launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->g3, c->tb, a0, c->err, st);
   // corrector F_new = (F + F*)/2 + dtau/2 K(F*): adjoint of F*, and F's share
   if (e == hipSuccess)
     e = launch_adj_rhs(B.Fp, B.Lp, d_adj_F, d_adj_lnM, 0.5 * dtau_fm, B.aF1, B.aL1, B.Rb, B.gb, B.eta, 0, &c->cd,
-                       c->tb, a1, c->err, st);
+                       c->g3, c->tb, a1, c->err, st);
   if (e == hipSuccess) e = launch_adj_axpy(B.aF1, d_adj_F, 0.5, d_adj_F, 0.5, nF, st);
   if (e == hipSuccess) e = launch_adj_axpy(B.aL1, d_adj_lnM, 0.5, d_adj_lnM, 0.5, ns, st);
   // predictor: F* = F + dtau K(F)
   if (e == hipSuccess) e = launch_adj_axpy(d_adj_F, B.aF1, 1.0, nullptr, 1.0, nF, st);
   if (e == hipSuccess) e = launch_adj_axpy(d_adj_lnM, B.aL1, 1.0, nullptr, 1.0, ns, st);
   if (e == hipSuccess)
-    e = launch_adj_rhs(d_F, d_lnM, B.aF1, B.aL1, dtau_fm, d_adj_F, d_adj_lnM, B.Rb, B.gb, B.eta, 1, &c->cd, c->tb,
-                       a0, c->err, st);
+    e = launch_adj_rhs(d_F, d_lnM, B.aF1, B.aL1, dtau_fm, d_adj_F, d_adj_lnM, B.Rb, B.gb, B.eta, 1, &c->cd, c->g3,
+                       c->tb, a0, c->err, st);
   if (e == hipSuccess) e = launch_adj_sum(B.eta, (int)ns, d_grad_eta_over_s, st);
   return e == hipSuccess ? LB_OK : hip_fail(e, "adjoint step");
 }

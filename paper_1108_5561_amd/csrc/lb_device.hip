@@ -463,6 +463,32 @@ __device__ __forceinline__ void weak_force(const R f[25], CPtr<R> C, R gx, R gy,
   }
 }
 
+// Dense form of the weak-form force operators, for the FP64 adjoint:
+// G_i[n][m] = (G_i e_m)_n over the canonical node index n = q 8 + l, from
+// weak_force applied to unit vectors, so that the adjoint differentiates
+// the same operator as the stage kernels.  One wave per block: eight probe
+// sites of eight slices, probe site = column m = 8 blockIdx.x + t / 8
+// (gridDim.x = 25), component i = blockIdx.y (0: x, 1: y); G holds
+// [2][200][200].
+__global__ __launch_bounds__(64) void force_columns_kernel(const StageConst<double>* __restrict__ Cg,
+                                                           double* __restrict__ G) {
+  __shared__ __attribute__((aligned(16))) double s_force[25 * 64];
+  const int t = threadIdx.x, l = t & 7;
+  const int m = (int)blockIdx.x * 8 + (t >> 3);
+  const int comp = (int)blockIdx.y;
+  const CPtr<double> C = const_ptr(Cg);
+  double f[25], r0[25];
+#pragma unroll
+  for (int q = 0; q < 25; ++q) {
+    f[q] = (q * 8 + l == m) ? 1.0 : 0.0;
+    r0[q] = 0.0;
+  }
+  weak_force<double>(f, C, comp == 0 ? 1.0 : 0.0, comp == 1 ? 1.0 : 0.0, l, 1.0, r0, s_force, t);
+  double* Gi = G + (size_t)comp * 200 * 200;
+#pragma unroll
+  for (int q = 0; q < 25; ++q) Gi[(size_t)(q * 8 + l) * 200 + m] = r0[q];
+}
+
 // Partial moments of one slice over the mirror pairs: w gamma^2, w gamma
 // |v_perp|, w |v_perp|^2 and w, summed over the 25 nodes (eq. (emtnew)).
 template <typename R>
@@ -876,6 +902,12 @@ hipError_t stage_launch_t(int stage, dim3 g, dim3 b, const void* Fin, const void
   return hipGetLastError();
 }
 }  // namespace
+
+hipError_t launch_force_columns(const void* cst64, double* G, hipStream_t s) {
+  hipLaunchKernelGGL(force_columns_kernel, dim3(25, 2), dim3(64), 0, s,
+                     static_cast<const StageConst<double>*>(cst64), G);
+  return hipGetLastError();
+}
 
 hipError_t launch_stage(int precision, int stage, const void* Fin, const void* Fbase, void* Fout,
                         const double* lnMin, const double* lnMbase, double* lnMout, const double* scin,

@@ -62,7 +62,7 @@ def objective(p, F, lnM, tau_f, nodes):
 
 def run_objective(p, e0, eta, n, dtau, nodes):
     q = lb.make_params(p.nx, p.ny, p.dx_fm, tau0_fm=p.tau0_fm, eta_over_s=eta, precision=lb.LB_FP64,
-                       metric=p.metric)
+                       metric=p.metric, force_form=p.force_form)
     c = lb.Context(q, e0)
     c.step(n, dtau)
     F, L, tau = c.get_state()
@@ -70,10 +70,14 @@ def run_objective(p, e0, eta, n, dtau, nodes):
     return float(objective(q, F, L, tau, nodes))
 
 
-@pytest.mark.parametrize("metric", [lb.LB_METRIC_MILNE, lb.LB_METRIC_MINKOWSKI])
-def test_forward_step_equals_lb_step(metric):
+@pytest.mark.parametrize("metric,force", [(lb.LB_METRIC_MILNE, lb.LB_FORCE_FEQ),
+                                          (lb.LB_METRIC_MINKOWSKI, lb.LB_FORCE_FEQ),
+                                          (lb.LB_METRIC_MILNE, lb.LB_FORCE_WEAK3D)])
+def test_forward_step_equals_lb_step(metric, force):
+    # with the weak-form 3-D force the adjoint applies the dense operators
+    # built from the stage kernels' factored form: other summation order
     nx, ny, dx, dtau = 14, 11, 0.15, 0.01
-    p = lb.make_params(nx, ny, dx, eta_over_s=0.1, metric=metric)
+    p = lb.make_params(nx, ny, dx, eta_over_s=0.1, metric=metric, force_form=force)
     ux, uy = wl.random_flow(nx, ny, 0.2, seed=3)
     c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, 7)), gpu(ux), gpu(uy))
     c.step(3, dtau)
@@ -87,11 +91,14 @@ def test_forward_step_equals_lb_step(metric):
     assert c.status() == lb.LB_OK
 
 
-@pytest.mark.parametrize("metric,part", [(lb.LB_METRIC_MILNE, "F"), (lb.LB_METRIC_MILNE, "lnM"),
-                                         (lb.LB_METRIC_MINKOWSKI, "both")])
-def test_step_adjoint_dot_product(metric, part):
+@pytest.mark.parametrize("metric,part,force", [(lb.LB_METRIC_MILNE, "F", lb.LB_FORCE_FEQ),
+                                               (lb.LB_METRIC_MILNE, "lnM", lb.LB_FORCE_FEQ),
+                                               (lb.LB_METRIC_MINKOWSKI, "both", lb.LB_FORCE_FEQ),
+                                               (lb.LB_METRIC_MILNE, "F", lb.LB_FORCE_WEAK3D),
+                                               (lb.LB_METRIC_MILNE, "lnM", lb.LB_FORCE_WEAK3D)])
+def test_step_adjoint_dot_product(metric, part, force):
     nx, ny, dx, dtau, eta = 12, 10, 0.15, 0.01, 0.12
-    p = lb.make_params(nx, ny, dx, eta_over_s=eta, metric=metric)
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta, metric=metric, force_form=force)
     ux, uy = wl.random_flow(nx, ny, 0.2, seed=5)
     c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, 9)), gpu(ux), gpu(uy))
     c.step(4, dtau)
@@ -115,7 +122,7 @@ def test_step_adjoint_dot_product(metric, part):
     he = 1e-5
     out = []
     for sgn in (1, -1):
-        q = lb.make_params(nx, ny, dx, eta_over_s=eta * (1 + sgn * he), metric=metric)
+        q = lb.make_params(nx, ny, dx, eta_over_s=eta * (1 + sgn * he), metric=metric, force_form=force)
         cq = lb.Context(q, gpu(spots_e0(p, nx, ny, dx, 9)))
         out.append(lib_step(cq, F, L, tau, dtau))
     fd = float(((aF * (out[0][0] - out[1][0])).sum() + (aL * (out[0][1] - out[1][1])).sum()) / (2 * he * eta))
@@ -216,6 +223,33 @@ def test_run_gradient_matches_central_differences():
         assert abs(float(g_e0[y, x]) - fd) <= 1e-6 * abs(fd) + 1e-12 * abs(fd_dir), (site, float(g_e0[y, x]), fd)
 
 
+def test_run_gradient_with_3d_force_matches_central_differences():
+    # the weak-form 3-D force: gradients of a 40-step run against central
+    # differences of lb_step (h = 1e-4 relative)
+    nx = ny = 16
+    dx, dtau, n, eta = 0.12, 0.00375, 40, 0.16
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta, force_form=lb.LB_FORCE_WEAK3D)
+    nodes = lb.node_tensors(p, DEV)
+    e0n = spots_e0(p, nx, ny, dx, 6)
+    e0 = gpu(e0n).requires_grad_(True)
+    et = torch.tensor([eta], dtype=torch.float64, device=DEV, requires_grad=True)
+    print("adjoint with the 3-D force, 16x16, 40 steps", flush=True)
+    F, L = lb.evolve(p, e0, et, n, dtau, checkpoint_every=15)
+    O = objective(p, F, L, p.tau0_fm + n * dtau, nodes)
+    O.backward()
+    g_e0, g_eta = e0.grad.detach(), float(et.grad[0])
+    h = 1e-4
+    fd_eta = (run_objective(p, gpu(e0n), eta * (1 + h), n, dtau, nodes) -
+              run_objective(p, gpu(e0n), eta * (1 - h), n, dtau, nodes)) / (2 * h * eta)
+    assert abs(g_eta - fd_eta) <= 1e-6 * abs(fd_eta), (g_eta, fd_eta)
+    rng = np.random.default_rng(9)
+    d = e0n * rng.standard_normal(e0n.shape)
+    fd_dir = (run_objective(p, gpu(e0n + h * d), eta, n, dtau, nodes) -
+              run_objective(p, gpu(e0n - h * d), eta, n, dtau, nodes)) / (2 * h)
+    ad_dir = float((g_e0 * gpu(d)).sum())
+    assert abs(ad_dir - fd_dir) <= 1e-6 * abs(fd_dir), (ad_dir, fd_dir)
+
+
 def _oracle_objective(lat, eos, e0, eta, nx, ny, dx, n, dtau, tau0=0.5):
     F, L = st.init_state(lat, eos, e0)
     prm = st.Params(dx=dx, eta_over_s=eta)
@@ -227,10 +261,12 @@ def _oracle_objective(lat, eos, e0, eta, nx, ny, dx, n, dtau, tau0=0.5):
     return tau * dx * dx * float(np.sum(Tk[1, 1] - Tk[2, 2])) / HBARC ** 3
 
 
-def test_run_gradient_matches_oracle_central_differences():
+@pytest.mark.parametrize("force", [lb.LB_FORCE_FEQ, lb.LB_FORCE_WEAK3D])
+def test_run_gradient_matches_oracle_central_differences(force):
     nx, ny, dx, dtau, n, eta = 6, 5, 0.2, 0.01, 4, 0.12
-    lat, eos = Lattice(5, 5, 4, 1.0), TanhEntropyEoS()
-    p = lb.make_params(nx, ny, dx, eta_over_s=eta)
+    lat = Lattice(5, 5, 4, 1.0, force="weak3d" if force == lb.LB_FORCE_WEAK3D else "feq")
+    eos = TanhEntropyEoS()
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta, force_form=force)
     nodes = lb.node_tensors(p, DEV)
     e0n = float(eos.eps(0.3)) / HBARC ** 3 * (1.0 + 0.6 * wl.gaussian_shape(nx, ny, dx, 0.4)) * \
         wl.white_noise_factor(nx, ny, 0.05, seed=13)

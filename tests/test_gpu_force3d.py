@@ -132,15 +132,20 @@ def test_hot_spot_run_fp64_and_fp32(lat3, eos):
     assert tmunu_rel_err(o32, o64) < 1e-4
 
 
-def test_adjoint_form_rejects_the_3d_force(eos):
-    nx, ny, dx = 8, 8, 0.2
-    e0 = float(eos.eps(0.3)) / HBARC ** 3 * np.ones((ny, nx))
+def test_adjoint_forward_step_with_the_3d_force(eos):
+    # the FP64 adjoint's own forward step applies the dense operators built
+    # from the stage kernels' weak_force: it equals lb_step to rounding
+    nx, ny, dx, dtau = 9, 7, 0.2, 0.01
+    e0 = float(eos.eps(0.3)) / HBARC ** 3 * (1 + 0.5 * wl.gaussian_shape(nx, ny, dx, 0.4))
     c = _ctx(nx, ny, dx, e0, lb.LB_FP64, 0.1)
+    F, lnM, tau = c.get_state()
     ws = c.adjoint_workspace()
-    F, lnM, _ = c.get_state()
-    with pytest.raises(lb.LbError) as ei:
-        c.adjoint_forward_step(0.5, 0.005, F, lnM, ws)
-    assert ei.value.code == lb.LB_E_NOTIMPL
+    F1, L1 = c.adjoint_forward_step(tau, dtau, F, lnM, ws)
+    c.step(1, dtau)
+    F2, L2, _ = c.get_state()
+    assert c.status() == lb.LB_OK
+    assert float((F1 - F2).abs().max()) <= 1e-12 * float(F2.abs().max())
+    assert float((L1 - L2).abs().max()) <= 1e-12
 
 
 def test_prec_workload_sampled_parity(lat3, eos):
