@@ -306,6 +306,31 @@ const char* lb_last_error(void);
 int64_t lb_lattice_info(const lb_params* p, double* out, int64_t n_out);
 
 /*
+ * Per-node quantities of the momentum lattice in the canonical node order
+ * (Sec. IV.C), for callers that form moments of lb_get_state's output
+ * themselves.  With out == NULL returns the number of doubles needed (5 N);
+ * otherwise fills out with five arrays of N values:
+ *   w_n   the product weight e^{z0 x_k} w^xi_k w^theta_j / (4 n_phi) (the
+ *         radial weight's exp(-z0 cosh xi) divided out, angular weights
+ *         summing to one), so that T^{ab}_kin = M^4/(2 pi^2) sum_n w_n F_n
+ *         V^a_n V^b_n (eq. (emtnew)) and N^a = M^3/(2 pi^2) sum_n w_n F_n V^a_n;
+ *   gamma_n = cosh xi_k, v^x_n, v^y_n = sinh xi_k sin theta_j (cos, sin) phi_l,
+ *   v^Y_n = sinh xi_k cos theta_j (V_n = (gamma, v^x, v^y, v^Y)_n).
+ * Returns the count, or a negative LB_E_* code (n_out too small, invalid
+ * lattice parameters).
+ */
+int64_t lb_node_table(const lb_params* p, double* out, int64_t n_out);
+
+/*
+ * Degeneracy Z of eq. (feq) whose Boltzmann gas has kappa times the
+ * Stefan-Boltzmann pressure of g bosonic degrees of freedom (Sec. III: the
+ * high-temperature limit of the quasiparticle pressure): Z = kappa g pi^4 / 90.
+ * kappa = 1 is the paper's matching; a larger kappa keeps M(T) solvable where
+ * the EoS's entropy exceeds the massless gas's.  Pure function, no errors.
+ */
+double lb_degeneracy(double kappa, double g);
+
+/*
  * Host evaluation of the equation of state at n temperatures T_GeV[i]:
  * out[8 i + 0..7] = eps, p, s (GeV^4, GeV^4, GeV^3), M (GeV), B (GeV^4),
  * eps - B (GeV^4), beta = dB/d(eps - B), tau_R (fm).  table != 0 evaluates

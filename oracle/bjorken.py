@@ -6,9 +6,9 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 No space dependence, so U = (1, 0, 0, 0) and eps is the tau-tau component of
 eq. (emtnew).  State: the distribution on the nodes, ln M and tau.  One step:
 
-* temperature from the energy density through the EoS (Sec. IV.D: "this leads
-  to a prediction for the new temperature"): eps_kin = T^{tau tau}_kin equals
-  eps(T) - B(T);
+* temperature from the energy density through the EoS (Sec. IV.D, eq.
+  (edchange)): the new T is the one at which eps(T) - B(T) equals the
+  evolved eps_kin = T^{tau tau}_kin;
 * f_eq = Z exp(-sqrt(M_eq^2 + M^2 sinh^2 xi)/T) with M_eq = M(T) and M the
   evolved mass (Sec. IV.D, last paragraph);
 * d ln M / d tau = -(dB/deps) sum_n w_n cosh^2 xi_n [S1/tau - (f - f_eq)/tau_R]

@@ -9,7 +9,6 @@ module fails loudly if the library has not been built
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 import re
 
@@ -88,6 +87,8 @@ def _load():
         "lb_destroy": (ctypes.c_int, [vp]),
         "lb_last_error": (ctypes.c_char_p, []),
         "lb_lattice_info": (i64, [P, dp, i64]),
+        "lb_node_table": (i64, [P, dp, i64]),
+        "lb_degeneracy": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
         "lb_eos_eval": (ctypes.c_int, [P, i64, dp, dp, i32]),
         "lb_profile": (ctypes.c_int, [vp, i32]),
         "lb_profile_read": (ctypes.c_int, [vp, dp, ctypes.POINTER(i64)]),
@@ -131,8 +132,9 @@ def check(rc):
 
 
 def degeneracy(kappa, g):
-    """Z = kappa g pi^4/90 (g bosonic-equivalent degrees of freedom)."""
-    return kappa * g * math.pi ** 4 / 90.0
+    """Z of eq. (feq) for kappa times the Stefan-Boltzmann pressure of g
+    degrees of freedom (lb_degeneracy)."""
+    return float(lib.lb_degeneracy(float(kappa), float(g)))
 
 
 def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, metric=LB_METRIC_MILNE,
@@ -410,27 +412,25 @@ class Batch:
             pass
 
 
-def node_tensors(p, device):
-    """Per-node quantities in the canonical node order, as float64 tensors of
-    shape [N]: weight w_n, gamma_n, v^x_n, v^y_n, v^Y_n (Sec. IV.C; the
-    moments are T^{ab}_kin = M^4/(2 pi^2) sum_n w_n F_n V^a_n V^b_n)."""
+def node_table(p):
+    """(5, N) float64 array of the per-node quantities in the canonical node
+    order (lb_node_table): w_n, gamma_n, v^x_n, v^y_n, v^Y_n."""
     import numpy as np
+    n = lib.lb_node_table(ctypes.byref(p), None, 0)
+    if n < 0:
+        raise LbError(int(n), last_error())
+    buf = np.zeros(n, dtype=np.float64)
+    r = lib.lb_node_table(ctypes.byref(p), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n)
+    if r < 0:
+        raise LbError(int(r), last_error())
+    return buf.reshape(5, -1)
+
+
+def node_tensors(p, device):
+    """The node table of lb_node_table as five float64 tensors of shape [N]
+    on device: w_n, gamma_n, v^x_n, v^y_n, v^Y_n."""
     import torch
-    info = lattice_info(p)
-    x, wxi, mu, wth, c, s_ = info["x"], info["w_xi"], info["mu"], info["w_th"], info["cos"], info["sin"]
-    nphi2 = 2 * p.n_phi
-    w, g, vx, vy, vY = [], [], [], [], []
-    for k in range(p.n_xi):
-        sh = math.sqrt(x[k] * x[k] - 1.0)
-        for j in range(p.n_theta):
-            sig = sh * math.sqrt(1.0 - mu[j] * mu[j])
-            for l in range(nphi2):
-                w.append(math.exp(p.z0 * x[k]) * wxi[k] * wth[j] / (2.0 * nphi2))
-                g.append(x[k])
-                vx.append(sig * c[l])
-                vy.append(sig * s_[l])
-                vY.append(sh * mu[j])
-    return tuple(torch.tensor(np.array(a), dtype=torch.float64, device=device) for a in (w, g, vx, vy, vY))
+    return tuple(torch.tensor(row, dtype=torch.float64, device=device) for row in node_table(p))
 
 
 class _Evolve:

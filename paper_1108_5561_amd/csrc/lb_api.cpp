@@ -823,6 +823,43 @@ int64_t lb_lattice_info(const lb_params* p, double* out, int64_t n_out) {
   return need;
 }
 
+int64_t lb_node_table(const lb_params* p, double* out, int64_t n_out) {
+  if (!p) return fail(LB_E_ARG, "params is NULL");
+  if (p->n_xi < 1 || p->n_theta < 1 || p->n_phi < 1 || !(p->z0 > 0))
+    return fail(LB_E_ARG, "need n_xi, n_theta, n_phi >= 1 and z0 > 0");
+  const int64_t nph = 2 * (int64_t)p->n_phi, N = (int64_t)p->n_xi * p->n_theta * nph;
+  const int64_t need = 5 * N;
+  if (!out) return need;
+  if (n_out < need) return fail(LB_E_ARG, "output too small");
+  HostLattice L;
+  std::string m = build_lattice(*p, &L);
+  if (!m.empty()) return fail(LB_E_ARG, m);
+  // Sec. IV.C: the product rule over (xi, theta, phi) with the radial
+  // weight's exp(-z0 cosh xi) divided out, normalised so that the angular
+  // weights sum to one (4 n_phi = 2 x the number of azimuths)
+  for (int k = 0; k < p->n_xi; ++k) {
+    const double x = L.x[k], sh = std::sqrt(std::max(x * x - 1.0, 0.0));
+    for (int j = 0; j < p->n_theta; ++j) {
+      const double st = std::sqrt(std::max(1.0 - L.mu[j] * L.mu[j], 0.0));
+      for (int l = 0; l < nph; ++l) {
+        const int64_t n = ((int64_t)k * p->n_theta + j) * nph + l;
+        out[n] = std::exp(p->z0 * x) * L.wxi[k] * L.wth[j] / (2.0 * (double)nph);
+        out[N + n] = x;
+        out[2 * N + n] = sh * st * L.cosl[l];
+        out[3 * N + n] = sh * st * L.sinl[l];
+        out[4 * N + n] = sh * L.mu[j];
+      }
+    }
+  }
+  return need;
+}
+
+double lb_degeneracy(double kappa, double g) {
+  // Stefan-Boltzmann limit of the Boltzmann gas: p = Z T^4/pi^2 against
+  // g pi^2 T^4/90, times the factor kappa
+  return kappa * g * kPi * kPi * kPi * kPi / 90.0;
+}
+
 int lb_eos_eval(const lb_params* p, int64_t n, const double* T, double* out, int32_t table) {
   std::string m = validate(p);
   if (!m.empty()) return fail(LB_E_ARG, m);
@@ -1035,7 +1072,12 @@ hipError_t batch_step_direct(lb_batch* b, double dtau) {
   return hipSuccess;
 }
 
+// Destroys the captured graphs.  A replay of them may still run on the
+// caller's stream, so the stream is drained first.
 void drop_graphs(lb_batch* b) {
+  bool any = false;
+  for (auto g : b->graph) any = any || g != nullptr;
+  if (any) hipStreamSynchronize(b->stream);
   for (auto& g : b->graph)
     if (g) {
       hipGraphExecDestroy(g);

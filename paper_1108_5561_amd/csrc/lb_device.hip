@@ -5,12 +5,15 @@
 // Work mapping: eight lanes per lattice site, lane l owning the phi_l slice
 // (N_xi x N_theta nodes) of that site.  The weak-form operators S1, S2 act
 // within one phi slice, so they are lane-local; the moments and the mass
-// evolution sums are reduced over the eight lanes with xor shuffles (all
-// lanes end with bitwise-identical sums, so the per-site FP64 work they
-// repeat gives identical results).
+// evolution sums are reduced over the eight lanes with DPP moves (sum8:
+// all lanes end with bitwise-identical sums).  The per-site FP64 matching
+// of a state runs once per site, in the first wave of the block that
+// produced the state (match_tile).
 //
-// Distribution layout in HBM: F[q][site][l], q = k * N_theta + j, so a wave
-// (8 sites x 8 slices) reads and writes 64 consecutive values per node.
+// Distribution layout in HBM (NodeLayout): the 25 nodes of a slice in
+// 16-byte groups, group g in plane g as [site][l][V], so a lane moves its
+// slice with a few 16-byte loads and a wave (8 sites x 8 slices) reads and
+// writes 1 KB contiguous per group.
 #include <hip/hip_runtime.h>
 
 #include "../../include/lb.h"

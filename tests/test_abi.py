@@ -103,6 +103,33 @@ def test_host_lattice_matches_oracle(z0):
     assert np.allclose(info["sin"], s, rtol=0, atol=3e-16)
 
 
+@pytest.mark.parametrize("shape", [(5, 5, 4, 1.0), (3, 4, 3, 2.6), (7, 5, 5, 1.0)])
+def test_node_table_matches_oracle(shape):
+    # lb_node_table (the library's weights and node momenta) against the
+    # oracle's lattice, canonical node order
+    nxi, nth, nph, z0 = shape
+    p = lb.make_params(8, 8, 0.2, z0=z0, n_xi=nxi, n_theta=nth, n_phi=nph)
+    t = lb.node_table(p)
+    lat = Lattice(nxi, nth, nph, z0)
+    assert t.shape == (5, lat.N)
+    assert np.allclose(t[0], lat.w, rtol=1e-12, atol=0)
+    assert np.allclose(t[1], lat.gamma, rtol=1e-14, atol=0)
+    for row, ref in zip(t[2:], (lat.V[1], lat.V[2], lat.V[3])):
+        assert np.allclose(row, ref, rtol=0, atol=1e-13 * np.max(np.abs(ref)))
+    n = lb.lib.lb_node_table(ctypes.byref(p), None, 0)
+    assert n == 5 * lat.N
+    buf = (ctypes.c_double * 4)()
+    assert lb.lib.lb_node_table(ctypes.byref(p), buf, 4) == lb.LB_E_ARG
+
+
+def test_degeneracy():
+    # Z T^4/pi^2 (massless Boltzmann gas) = kappa g pi^2 T^4/90
+    for kappa, g in [(1.0, 37.0), (2.0, 37.0), (1.5, 16.0)]:
+        Z = lb.degeneracy(kappa, g)
+        assert abs(Z / math.pi ** 2 - kappa * g * math.pi ** 2 / 90.0) < 1e-14 * Z
+    assert lb.make_params(4, 4, 0.1).Z == lb.degeneracy(2.0, 37.0)
+
+
 @pytest.mark.parametrize("z0", [1.0, 2.6])
 def test_factored_operators_equal_oracle_dense_operators(z0):
     # The device applies S1, S2 as mu^2 (A1 x) - (Ath x) and (A2 x) on each

@@ -159,11 +159,34 @@ def test_large_grid_mode_equals_cached_tiles():
     assert c.status() == lb.LB_OK and b.status() == lb.LB_OK
 
 
+def test_graph_replays_after_step_size_change():
+    """48 steps replayed at one dtau, then 48 at another (the graphs are
+    re-captured; the first replay may still be running when they are
+    dropped), equal the same steps taken one by one."""
+    p, e0s = _setup(lb.LB_FP32_FP64MATCH)
+    a = lb.Batch(p, EVENTS, e0s)
+    b = lb.Batch(p, EVENTS, e0s)
+    a.set_variant(1)
+    b.set_variant(1)
+    for dt in (DTAU, 0.6 * DTAU, DTAU):
+        a.step(48, dt)
+        for _ in range(48):
+            b.step(1, dt)
+    assert a.status() == lb.LB_OK and b.status() == lb.LB_OK
+    for e in range(len(EVENTS)):
+        Fa, la, ta = a.get_state(e)
+        Fb, lb_, tb = b.get_state(e)
+        assert ta == tb and torch.equal(Fa, Fb) and torch.equal(la, lb_)
+
+
 def test_full_batch_workload_sampled_events():
     """The 64-event batched workload at the bench's launch configuration
     (tuned variant, 96 steps as two 48-step graph replays): the smallest,
     the largest and two random events equal the same events advanced alone
-    with lb_step, bit for bit."""
+    with lb_step, bit for bit; and one further batched step of the smallest
+    and the largest event agrees with the FP64 oracle at sampled sites
+    (9 x 9 periodic windows: the corrector reaches 4 sites) to the FP32
+    one-step bar 1e-5."""
     w = wl.WORKLOADS["batch"]
     events = wl.batch_events(w["n_events"], w["n_min"], w["n_max"], w["box"])
     p = lb.make_params(8, 8, 0.1, tau0_fm=w["tau0"], precision=lb.LB_FP32_FP64MATCH)
@@ -188,4 +211,27 @@ def test_full_batch_workload_sampled_events():
         assert tb == t and torch.equal(Fb, F) and torch.equal(lb_, l), f"event {e} ({nx}x{ny})"
         assert c.status() == lb.LB_OK
         c.close()
+    # oracle contact: one more batched step from the replayed state
+    from oracle import step as st
+    from oracle.eos import TanhEntropyEoS
+    from oracle.lattice import Lattice
+    from _helpers import patch, tmunu_rel_err
+    lat, eos = Lattice(5, 5, 4, 1.0), TanhEntropyEoS()
+    small, large = int(np.argmin(sizes)), int(np.argmax(sizes))
+    before = {e: b.get_state(e) for e in (small, large)}
+    b.step(1, dtau)
+    assert b.status() == lb.LB_OK
+    for e in (small, large):
+        nx, ny, dx, eta = events[e]
+        F0, l0, tau = (x.cpu().numpy() if torch.is_tensor(x) else x for x in before[e])
+        obs = b.moments(e).cpu().numpy()
+        prm = st.Params(dx=dx, eta_over_s=eta)
+        hot = np.unravel_index(np.argmax(e0s[e].cpu().numpy()), (ny, nx))
+        rs = np.random.default_rng(100 + e)
+        for (cy, cx) in [hot, (0, 0), (ny - 1, nx - 1)] + [tuple(rs.integers(0, min(nx, ny), 2)) for _ in range(3)]:
+            Fp, lp = patch(F0, cy, cx, 4), patch(l0, cy, cx, 4)
+            Fo, lo = st.heun_step(lat, eos, prm, Fp, lp, tau, dtau)
+            ref = st.observables(lat, eos, prm, Fo, lo)[:, 4:5, 4:5]
+            err = tmunu_rel_err(obs[:, cy:cy + 1, cx:cx + 1], ref)
+            assert err < 1e-5, (e, cy, cx, err)
     b.close()
