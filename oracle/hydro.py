@@ -7,11 +7,6 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 * first-order (Navier-Stokes) with the Chapman-Enskog eta and zeta of the
   BGK quasiparticle gas (Sec. IV.A):
            d eps/d tau = -(eps + p)/tau + (4 eta/3 + zeta)/tau^2
-* second order, eq. (hydroeq), with tau_pi = 5 eta/(eps + P) and
-  lambda_1 = (5/7) eta tau_pi:
-           d eps/d tau = -(eps + P)/tau + Phi/tau
-           d Phi/d tau = -Phi/tau_pi + 4 eta/(3 tau_pi tau) - 4 Phi/(3 tau)
-                         - lambda_1 Phi^2 / (2 tau_pi eta^2)
 
 The state variable is T (eps(T) is monotone for a stable EoS); tau in fm,
 so eta/(eps + p) etc. carry a factor hbar c.
@@ -71,21 +66,3 @@ def navier_stokes(eos, T0, tau0, taus, eta_over_s, taur_rule="ce"):
     sol = solve_ivp(f, (tau0, taus[-1]), [T0], t_eval=taus, rtol=1e-10, atol=1e-13, method="DOP853")
     return sol.y[0]
 
-
-def second_order(eos, T0, tau0, taus, eta_over_s, Phi0=0.0):
-    """eq. (hydroeq) with the massless-gas tau_pi, lambda_1 the paper uses."""
-    def f(tau, y):
-        T, Phi = y
-        Ta = np.array([T])
-        e, p, s = float(eos.eps(Ta)[0]), float(eos.p(Ta)[0]), float(eos.s(Ta)[0])
-        eta = eta_over_s * s                       # GeV^3
-        tau_pi = 5 * eta / (e + p) * HBARC         # fm
-        lam1 = 5.0 / 7.0 * eta * tau_pi            # GeV^3 fm
-        de = -(e + p) / tau + Phi / tau
-        dPhi = (-Phi / tau_pi + 4 * eta * HBARC / (3 * tau_pi * tau) - 4 * Phi / (3 * tau)
-                - lam1 * Phi ** 2 / (2 * tau_pi * eta ** 2 * HBARC))
-        return [_dT_from_deps(eos, T, de), dPhi]
-
-    sol = solve_ivp(f, (tau0, taus[-1]), [T0, Phi0], t_eval=taus, rtol=1e-10, atol=1e-13,
-                    method="DOP853")
-    return sol.y[0]

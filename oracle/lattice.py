@@ -48,6 +48,21 @@ from . import quadrature as quad
 PI2 = np.pi ** 2
 
 
+def weak_brackets(x, mu, Lm, dLm, R, dR):
+    """The brackets b_1, b_2 of the coefficients s_1^{ml}, s_2^{ml} (Sec. IV.D)
+    for the test function psi = L_m(mu) R(x), at points (x = cosh xi, mu =
+    cos theta), given L_m, L_m', R, R' there.  They are what integration by
+    parts against the measure sinh^2 xi d xi d mu leaves on psi:
+        int psi (S F) = -int F b[psi]   for S1 = p^Y d/dp^Y, S2 = p . d/dp,
+    with t^2 = tanh^2 xi = (x^2 - 1)/x^2:
+        b_1 = (L_m R' x - L_m R) mu^2 t^2 + R (L_m + L_m' (mu - mu^3)),
+        b_2 = L_m R (2 + 1/x^2) + L_m R' x t^2."""
+    t2 = (x * x - 1.0) / (x * x)
+    b1 = (Lm * dR * x - Lm * R) * mu ** 2 * t2 + R * (Lm + dLm * (mu - mu ** 3))
+    b2 = Lm * R * (2.0 + 1.0 / x ** 2) + Lm * dR * x * t2
+    return b1, b2
+
+
 class Lattice:
     def __init__(self, n_xi=5, n_theta=5, n_phi=4, z0=1.0, form="weak", force="feq"):
         """form = "weak": the paper's weak-form S1, S2 (Sec. IV.D); "strong":
@@ -106,7 +121,6 @@ class Lattice:
         kq, jq = q // nt, q % nt
         x = self.x_k[kq]
         mu = self.mu_j[jq]
-        t2 = (x * x - 1.0) / (x * x)
         wslice = np.exp(z0 * x) * self.w_xi[kq] * self.w_th[jq] / 2.0
 
         Rv, dRv = quad.radial_values(z0, nx, self.x_k)       # (l, k)
@@ -125,8 +139,7 @@ class Lattice:
                 dR = dRv[l, kq]
                 col = m * nx + l
                 Phi[:, col] = np.exp(-z0 * x) * Lm * R
-                b1 = (Lm * dR * x - Lm * R) * mu ** 2 * t2 + R * (Lm + dLm * (mu - mu ** 3))
-                b2 = Lm * R * (2.0 + 1.0 / x ** 2) + Lm * dR * x * t2
+                b1, b2 = weak_brackets(x, mu, Lm, dLm, R, dR)
                 pref = -(2 * m + 1) / I[l]
                 B1[col, :] = pref * wslice * b1
                 B2[col, :] = pref * wslice * b2

@@ -90,3 +90,32 @@ def test_requires_constant_mass(lat):
     F, lnM = st.init_state(lat, eos, e0)
     with pytest.raises(ValueError):
         st.heun_step(lat, eos, prm, F, lnM, 0.5, 0.01)
+
+
+@pytest.mark.parametrize("alpha", [0.8, -0.5, 0.0])
+def test_relaxation_time_at_chemical_potential(eos, alpha):
+    # Chapman-Enskog relaxation time with a chemical potential (reading of
+    # Sec. IV.A at mu != 0): eta = (eta/s) s(T, mu) and eta / tau_R = h(T, mu).
+    # Pinned independently of the oracle's closed forms:
+    #  * s(T, mu) as the finite-difference derivative dp/dT at fixed mu of
+    #    the Boltzmann-gas pressure p = exp(mu/T) Z M^2 T^2 K_2(M/T)/(2 pi^2)
+    #    (Sec. II.A, eq. (epsp));
+    #  * h(T, mu) = (1/15T) int d^3p/(2pi)^3 p^4/E^2 f_eq with the fugacity
+    #    in f_eq = Z exp(mu/T - E/T), by adaptive quadrature.
+    from scipy.integrate import quad
+    from scipy.special import kv
+    eta_s = 0.12
+    for T in (0.25, 0.4, 0.7):
+        mu = alpha * T
+        M, Z = eos.M0, eos.Z
+
+        def p_at(TT):
+            return np.exp(mu / TT) * Z * M ** 2 * TT ** 2 * kv(2, M / TT) / (2 * np.pi ** 2)
+
+        h = 1e-4 * T
+        s_fd = (-p_at(T + 2 * h) + 8 * p_at(T + h) - 8 * p_at(T - h) + p_at(T - 2 * h)) / (12 * h)
+        integ = lambda q: q ** 6 / (M * M + q * q) * np.exp(mu / T - np.sqrt(M * M + q * q) / T)
+        I, _ = quad(integ, 0.0, 80 * T + 10 * M, epsabs=0, epsrel=1e-13, limit=400)
+        h_mu = Z * I / (2 * np.pi ** 2) / (15 * T)
+        tau_R = float(eos.tau_R_mu(np.array([T]), np.array([alpha]), eta_s)[0])   # fm
+        assert abs(tau_R * h_mu / (eta_s * s_fd * HBARC) - 1) < 1e-9, (T, alpha)
