@@ -67,6 +67,7 @@ enum { LB_EOS_TANH_P = 0, LB_EOS_CONST_MASS = 1, LB_EOS_TANH_S = 2, LB_EOS_TABLE
 enum { LB_OPS_WEAK = 0, LB_OPS_STRONG = 1 };  /* momentum-derivative operators S1, S2 */
 enum { LB_FORCE_FEQ = 0, LB_FORCE_WEAK3D = 1 };  /* mass-gradient force of eq. (Bmilne) */
 enum { LB_N_FREE = 0, LB_N_CONSERVED = 1 };      /* particle number, eq. (sanity) */
+enum { LB_GRAD_CENTRED = 0, LB_GRAD_UPWIND = 1 };  /* d_i ln M of the mass-gradient force */
 
 /*
  * Problem statement (Sec. IV.D: an initial condition is the distribution plus
@@ -160,6 +161,20 @@ typedef struct lb_params {
   /* mu/T of the initial state (uniform; lb_init): eps(T0, mu0) = e0 and
    * F = Z exp(mu0/T0 - u.P/T0).  Must be 0 unless LB_N_CONSERVED. */
   double mu_over_T0;
+  /* The transverse gradient d_i ln M in the mass-gradient force on F_eq:
+   * LB_GRAD_CENTRED, (ln M_{i+1} - ln M_{i-1}) / (2 dx); or LB_GRAD_UPWIND,
+   * per node the same second-order upwind difference the streaming of that
+   * node uses, (3 ln M_i - 4 ln M_{i-1} + ln M_{i-2}) / (2 dx) along the
+   * node's direction of motion (centred along an axis the node does not
+   * move on).  The streaming and the force are the two halves of the
+   * transport term P^mu d_mu at fixed v = p/M of eq. (Bmilne); with one
+   * difference operator for both, ln M modes near the grid scale, which a
+   * centred difference does not see, are held by the force (a white-noise
+   * initial state at eta/s 0.2 on a 0.025 fm grid keeps its ln M spread
+   * bounded instead of growing).  Requires force_form LB_FORCE_FEQ;
+   * lb_step, lb_moments and the batched form; the adjoint entry points
+   * return LB_E_NOTIMPL for it. */
+  int32_t gradient_form;
 } lb_params;
 
 /*

@@ -25,7 +25,9 @@ Right-hand side at (F, ln M, tau), per site (step numbers used below):
     periodic boundaries;
  8. mass-gradient force of eq. (Bmilne), (1/2) d_i M^2 d^i_(p), at fixed v:
     Gr = sum_i (g_i/gamma) [v^i (v . d_v F_eq) + d_{v^i} F_eq], g_i = d_i ln M
-    by centred differences, derivatives of F_eq taken analytically (lattice
+    by centred differences (or, with Params.grad = "upwind", per node by the
+    same upwind difference as its streaming in step 7, centred along an
+    axis the node does not move on), derivatives of F_eq taken analytically (lattice
     force "feq"); or Gr = sum_i g_i G_i F with the weak-form operators of
     force3d acting on F itself (lattice force "weak3d");
  9. R0 = A + S1/tau + Gr - C (the S1/tau term is the Milne Christoffel term and
@@ -67,6 +69,7 @@ class Params:
     T_lo: float = 0.05
     T_hi: float = 3.0
     conserve_n: bool = False  # match n = u_a N^a as well: T and mu/T per site
+    grad: str = "centred"     # d_i ln M of the force: "centred" or "upwind" (the streaming's stencil per node)
 
 
 def landau(Tk3):
@@ -162,6 +165,19 @@ def rhs(lat, eos, prm: Params, F, lnM, tau):
     # 8. mass-gradient force on F_eq
     gx = (np.roll(lnM, -1, 1) - np.roll(lnM, 1, 1)) / (2 * prm.dx)
     gy = (np.roll(lnM, -1, 0) - np.roll(lnM, 1, 0)) / (2 * prm.dx)
+    if prm.grad == "upwind":
+        # per node, the transport's own second-order upwind difference along
+        # its direction of motion (centred along an axis it does not move on)
+        if lat.force != "feq":
+            raise ValueError("the upwind ln M gradient is defined for the force on F_eq")
+        sx = np.sign(np.round(lat.V[1], 12))[bc]
+        sy = np.sign(np.round(lat.V[2], 12))[bc]
+        ux_p, ux_m = upwind_derivative(lnM, 1, True), upwind_derivative(lnM, 1, False)
+        uy_p, uy_m = upwind_derivative(lnM, 0, True), upwind_derivative(lnM, 0, False)
+        gx = np.where(sx > 0, ux_p / prm.dx, np.where(sx < 0, ux_m / prm.dx, gx))
+        gy = np.where(sy > 0, uy_p / prm.dx, np.where(sy < 0, uy_m / prm.dx, gy))
+    elif prm.grad != "centred":
+        raise ValueError(f"unknown gradient {prm.grad!r}")
     gv = gx * vx + gy * vy
     gu = gx * ux + gy * uy
     # d F_eq / d v^i = -(F_eq/T)(u^tau M^2 v^i / E_eq - M u^i), i = x, y

@@ -24,6 +24,7 @@ LB_EOS_TANH_P, LB_EOS_CONST_MASS, LB_EOS_TANH_S, LB_EOS_TABLE = 0, 1, 2, 3
 LB_OPS_WEAK, LB_OPS_STRONG = 0, 1
 LB_FORCE_FEQ, LB_FORCE_WEAK3D = 0, 1
 LB_N_FREE, LB_N_CONSERVED = 0, 1
+LB_GRAD_CENTRED, LB_GRAD_UPWIND = 0, 1
 HBARC = 0.1973269804  # GeV fm
 N_OBS = 14
 OBS_NAMES = ("Ttt", "Ttx", "Tty", "Txx", "Txy", "Tyy", "TYY", "Nt", "Nx", "Ny", "T", "ux", "uy", "M")
@@ -52,6 +53,7 @@ class lb_params(ctypes.Structure):
         ("eos_p0_GeV4", ctypes.c_double), ("eos_n", ctypes.c_int32),
         ("operator_form", ctypes.c_int32), ("force_form", ctypes.c_int32),
         ("particle_number", ctypes.c_int32), ("mu_over_T0", ctypes.c_double),
+        ("gradient_form", ctypes.c_int32),
     ]
 
 
@@ -141,7 +143,8 @@ def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, 
                 taur_rule=LB_TAUR_CE, eos_kind=LB_EOS_TANH_S, eos_g=37.0, eos_Tc_GeV=0.17, eos_width_GeV=0.02,
                 eos_mass_GeV=0.0, kappa=2.0, Z=None, z0=1.0, n_xi=5, n_theta=5, n_phi=4,
                 T_min_GeV=0.05, T_max_GeV=3.0, eos_table=None, operator_form=LB_OPS_WEAK,
-                force_form=LB_FORCE_FEQ, particle_number=LB_N_FREE, mu_over_T0=0.0):
+                force_form=LB_FORCE_FEQ, particle_number=LB_N_FREE, mu_over_T0=0.0,
+                gradient_form=LB_GRAD_CENTRED):
     """Parameters of a run.  eos_table = (T [GeV], s [GeV^3], p(T[0]) [GeV^4])
     selects LB_EOS_TABLE with the caller's entropy density (the arrays are
     kept alive by the returned object)."""
@@ -164,6 +167,7 @@ def make_params(nx, ny, dx_fm, tau0_fm=0.5, eta_over_s=0.08, precision=LB_FP64, 
     p.operator_form = operator_form
     p.force_form = force_form
     p.particle_number, p.mu_over_T0 = particle_number, mu_over_T0
+    p.gradient_form = gradient_form
     return p
 
 

@@ -67,7 +67,9 @@ __device__ inline bool landau3(const double t[6], double* lam_out, double u[3]) 
   for (int it = 0; it < 40; ++it) {
     const double p = ((lam - c2) * lam + c1) * lam - c0;
     const double dp = (3.0 * lam - 2.0 * c2) * lam + c1;
-    const double d = p / dp;
+    // Newton step; the update needs no correctly rounded quotient (the
+    // residual p is evaluated exactly), so the hardware reciprocal serves
+    const double d = p * __builtin_amdgcn_rcp(dp);
     lam -= d;
     if (!(fabs(d) > 4e-16 * fabs(lam))) break;
   }
@@ -165,15 +167,15 @@ __device__ inline bool eos_mu(const EosTable& tb, double lam, double n, EosAt* o
   return ok;
 }
 
-// EoS at lambda = eps - B for the stage kernels' matching: one read of the
-// 4-point stencil of the table on the uniform g = ln(lambda) grid and a cubic
-// interpolation of T, M_eq/T, beta, q and B/T^4 (the table holds the
-// u-table's inversion at its nodes, so the two agree to the interpolation
-// error).  False if lambda is outside the accepted range.
-__device__ inline bool eos_g(const EosTable& tb, double lam, EosAt* o) {
-  const double g = log(lam);
+// EoS at lambda = eps - B for the stage kernels' matching, given
+// g = ln(lambda) (lam_pos: lambda > 0): one read of the 4-point stencil of
+// the table on the uniform g grid and a cubic interpolation of T, M_eq/T,
+// beta, q and B/T^4 (the table holds the u-table's inversion at its nodes,
+// so the two agree to the interpolation error).  False if lambda is outside
+// the accepted range.
+__device__ inline bool eos_g(const EosTable& tb, double g, bool lam_pos, EosAt* o) {
   double s = (g - tb.gg0) * tb.gg_inv_h;
-  const bool ok = (lam > 0.0) && (s >= 0.0) && (s <= (double)(tb.gn - 1));
+  const bool ok = lam_pos && (s >= 0.0) && (s <= (double)(tb.gn - 1));
   if (!ok) s = (s > 0.0) ? (double)(tb.gn - 1) : 0.0;
   int i = (int)s;
   if (i < 1) i = 1;

@@ -21,6 +21,7 @@ struct StageArgs {
   int32_t metric;
   int32_t force_form;    // LB_FORCE_FEQ or LB_FORCE_WEAK3D (lb_step only)
   int32_t mu_mode;       // 1: conserved particle number (n matching; record slot beta holds mu/T)
+  int32_t grad_form;     // LB_GRAD_CENTRED or LB_GRAD_UPWIND: d_i ln M of the force on F_eq
   double inv2dx;         // 1/(2 dx)    [fm^-1]
   double inv_dx;         // 1/dx
   double tau;            // time of this stage [fm]

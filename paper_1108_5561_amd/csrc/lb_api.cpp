@@ -111,6 +111,9 @@ std::string validate(const lb_params* p) {
     return "mu_over_T0 must be finite and within +-20";
   if (p->mu_over_T0 != 0.0 && p->particle_number != LB_N_CONSERVED)
     return "mu_over_T0 needs particle_number LB_N_CONSERVED";
+  if (p->gradient_form != LB_GRAD_CENTRED && p->gradient_form != LB_GRAD_UPWIND) return "unknown gradient_form";
+  if (p->gradient_form == LB_GRAD_UPWIND && p->force_form != LB_FORCE_FEQ)
+    return "gradient_form LB_GRAD_UPWIND needs force_form LB_FORCE_FEQ";
   return "";
 }
 
@@ -356,6 +359,7 @@ StageArgs params_args(const lb_params& p, double tau, double dtau) {
   a.force_form = p.force_form;
   a.mu_mode = p.particle_number == LB_N_CONSERVED ? 1 : 0;
   a.alpha0 = p.mu_over_T0;
+  a.grad_form = p.gradient_form;
   a.inv2dx = 0.5 / p.dx_fm;
   a.inv_dx = 1.0 / p.dx_fm;
   a.dtau = dtau;
@@ -411,6 +415,7 @@ struct AdjBufs {
 int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBufs* B) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   if (c->p.particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the adjoint step has mu = 0 only");
+  if (c->p.gradient_form != LB_GRAD_CENTRED) return fail(LB_E_NOTIMPL, "the adjoint step has the centred ln M gradient only");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
   if (!std::isfinite(tau) || (c->p.metric == LB_METRIC_MILNE && !(tau > 0)))
     return fail(LB_E_ARG, "tau must be finite (and > 0 for the Milne metric)");
@@ -1216,6 +1221,8 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
   *out = nullptr;
   std::string m = validate_batch(p, events, n_events);
   if (!m.empty()) return fail(LB_E_ARG, m);
+  if (p->gradient_form != LB_GRAD_CENTRED)
+    return fail(LB_E_NOTIMPL, "the batched form takes gradient_form LB_GRAD_CENTRED");
   if (p->force_form != LB_FORCE_FEQ && p->particle_number != LB_N_FREE)
     return fail(LB_E_NOTIMPL, "the batched form has the 3-D force or the conserved particle number, not both");
   if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(LB_E_ARG, "workspace NULL or not 256-byte aligned");

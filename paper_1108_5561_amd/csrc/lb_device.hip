@@ -276,6 +276,22 @@ __device__ __forceinline__ EosTable load_table(const EosTable* p) {
   t.gg_inv_h = q->gg_inv_h;
   return t;
 }
+// Entry l (0..7, this lane's phi slice) of an 8-value table in the stage
+// constants: the table is read with scalar loads (uniform addresses) and the
+// lane's value selected in registers, so that no per-lane memory read (whose
+// completion the in-order vector-memory counter would tie to the loads
+// issued before it) sits in front of the streaming loads that depend on it.
+template <typename R>
+__device__ __forceinline__ R lane_entry(const __attribute__((address_space(4))) R* tab, int l) {
+  R v[8];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) v[d] = tab[d];
+  R r = v[7];
+#pragma unroll
+  for (int d = 6; d >= 0; --d) r = (l == d) ? v[d] : r;
+  return r;
+}
+
 // ---- weak-form 3-D mass-gradient force ---------------------------------
 // Value of lane (lane ^ 1) (the cos/sin partner mode) of the 8-lane group.
 template <typename R>
@@ -342,7 +358,7 @@ template <typename R>
 __device__ __forceinline__ void weak_force(const R f[25], CPtr<R> C, R gx, R gy, int l, R scale, R r0[25], R* sw,
                                            int lw) {
   const int sb = lw & 56;  // first lane of this site in the wave
-  const R cl = C->cosl[l], sl = C->sinl[l];
+  const R cl = lane_entry<R>(C->cosl, l), sl = lane_entry<R>(C->sinl, l);
   const R gr = gx * cl + gy * sl;  // g . (cos phi, sin phi)
   // this lane's mode (as a mode index r = l): 0, 4, 1c, 1s, 2c, 2s, 3c, 3s
   const int m = l < 2 ? 4 * l : (l >> 1);
@@ -548,7 +564,7 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   R p0, p1, p2, p3;
   slice_moments(f, C, &p0, &p1, &p2, &p3);
   (void)p3;
-  const R cl = C->cosl[l], sl = C->sinl[l];
+  const R cl = lane_entry<R>(C->cosl, l), sl = lane_entry<R>(C->sinl, l);
   const R m00 = sum8(p0), m01 = sum8(p1 * cl), m02 = sum8(p1 * sl);
   const R m11 = sum8(p2 * cl * cl), m12 = sum8(p2 * cl * sl), m22 = sum8(p2 * sl * sl);
   if (l == 0) {
@@ -575,27 +591,38 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   const int sx = bx * kTX + (t % kTX), sy = by * kTY + (t / kTX);
   if (sx >= a.nx || sy >= a.ny) return;
   const int ss = sy * a.nx + sx;
-  const double M = exp(s_mom[6][t]);
-  const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
+  const double lnMs = s_mom[6][t];
+  // The mixed tensor T_kin g = G (sum w F V V) g with G = M^4/(2 pi^2): its
+  // timelike eigenvector does not depend on G, and its eigenvalue is
+  // lambda = G lambda', so the matching runs on the sums themselves and
+  // ln lambda = ln lambda' + 4 ln M - ln(2 pi^2) (no exp of ln M in FP64)
   double tk[6];
   bool finite = true;
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    tk[i] = G * s_mom[i][t];
+    tk[i] = s_mom[i][t];
     finite = finite && isfinite(tk[i]);
   }
-  double lam, u[3];
-  const bool matched = landau3(tk, &lam, u);
+  finite = finite && isfinite(lnMs);
+  double lamp, u[3];
+  const bool matched = landau3(tk, &lamp, u);
+  const double ln2pi2 = 2.9826069522587457;  // ln(2 pi^2)
+  const double glam = log(lamp) + 4.0 * lnMs - ln2pi2;
   EosAt E;
   const EosTable tb = load_table(tbg);  // read here, where it is used
   bool eos_ok;
   double alpha = 0.0;
+  double M;
   if constexpr (kMu) {
+    M = exp(lnMs);
+    const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
     // n = u_a N^a with N^a = M^3/(2 pi^2) sum w F V^a (eq. (NTdisc))
     const double n = G / M * (u[0] * s_mom[7][t] - u[1] * s_mom[8][t] - u[2] * s_mom[9][t]);
-    eos_ok = eos_mu(tb, lam, n, &E, &alpha);
+    eos_ok = eos_mu(tb, G * lamp, n, &E, &alpha);
   } else {
-    eos_ok = eos_g(tb, lam, &E);
+    // the record holds M in the node precision: FP32 needs no FP64 exp
+    M = sizeof(R) == 4 ? (double)__expf((float)lnMs) : exp(lnMs);
+    eos_ok = eos_g(tb, glam, lamp > 0.0, &E);
   }
   if (!finite) flag(err, kErrNonfinite);
   else if (!matched) flag(err, kErrMatch);
@@ -611,7 +638,7 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   rec.v[kScMinvT] = (R)(M * invT);
   rec.v[kScL2invT] = (R)(1.4426950408889634 * invT);  // log2(e)/T
   rec.beta = kMu ? alpha : E.beta;  // beta = 0 for the constant mass of the mu mode
-  rec.lnM = s_mom[6][t];
+  rec.lnM = lnMs;
   store_record<R>(buf_rsrc(sc, (uint32_t)a.n_sites * SiteRecord<R>::kBytes), ss, rec);
 }
 
@@ -650,7 +677,8 @@ __device__ __forceinline__ LaneSite lane_site(int tile, int tiles_x, int ts, int
 // XCD-aware tile order of xcd_tile.  kStream = kNT streams the new state
 // past the caches (stores, and the corrector's base slice, read once) for
 // states larger than the last-level cache; 0 keeps them cached.
-template <typename R, int STAGE, int kTY = TileRows<R>::v, int kStream = 0, int kForce = 0, int kMu = 0>
+template <typename R, int STAGE, int kTY = TileRows<R>::v, int kStream = 0, int kForce = 0, int kMu = 0,
+          int kGrad = 0>
 __global__ __launch_bounds__(kTX * kTY * kSl, (kForce ? ForceWaves<R>::v : (kMu ? MuWaves<R>::v : MinWaves<R, STAGE>::v))) void stage_kernel(
     const R* __restrict__ Fin, const R* __restrict__ Fbase, R* __restrict__ Fout,
     const double* __restrict__ lnMin, const double* __restrict__ lnMbase, double* __restrict__ lnMout,
@@ -677,6 +705,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
     int* __restrict__ err) {
   __shared__ double s_mom[kMomRows][kTX * kTY];
   __shared__ __attribute__((aligned(16))) R s_force[kForce ? kTY * 25 * 64 : 1];
+  constexpr int kGrad = 0;  // the batched form takes the centred ln M gradient
   const int tile = xcd_tile(n_tiles);
   if (tile >= n_tiles) return;  // whole block
   // the event, its buffers and the stage time through constant-address
@@ -890,18 +919,18 @@ inline dim3 grid_for(int n_sites) { return dim3((unsigned)(((size_t)n_sites * kS
 
 namespace {
 // one stage of the single-event kernel with the given template flags
-template <typename R, int kTY, int kStream, int kForce, int kMu>
+template <typename R, int kTY, int kStream, int kForce, int kMu, int kGrad = 0>
 hipError_t stage_launch_t(int stage, dim3 g, dim3 b, const void* Fin, const void* Fbase, void* Fout,
                           const double* lnMin, const double* lnMbase, double* lnMout, const double* scin,
                           double* scout, const void* sc, const EosTable* tb, const StageArgs& a, int* err,
                           hipStream_t s) {
   const auto* C = static_cast<const StageConst<R>*>(sc);
   if (stage == 0)
-    hipLaunchKernelGGL((stage_kernel<R, 0, kTY, kStream, kForce, kMu>), g, b, 0, s, (const R*)Fin, (const R*)Fbase,
-                       (R*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+    hipLaunchKernelGGL((stage_kernel<R, 0, kTY, kStream, kForce, kMu, kGrad>), g, b, 0, s, (const R*)Fin,
+                       (const R*)Fbase, (R*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
   else
-    hipLaunchKernelGGL((stage_kernel<R, 1, kTY, kStream, kForce, kMu>), g, b, 0, s, (const R*)Fin, (const R*)Fbase,
-                       (R*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
+    hipLaunchKernelGGL((stage_kernel<R, 1, kTY, kStream, kForce, kMu, kGrad>), g, b, 0, s, (const R*)Fin,
+                       (const R*)Fbase, (R*)Fout, lnMin, lnMbase, lnMout, scin, scout, C, tb, a, err);
   return hipGetLastError();
 }
 }  // namespace
@@ -922,6 +951,7 @@ hipError_t launch_stage(int precision, int stage, const void* Fin, const void* F
   // weak-form 3-D force and the conserved particle number run with the
   // default tiles and cached stores
   const bool force3d = a.force_form == LB_FORCE_WEAK3D, mu = a.mu_mode != 0;
+  const bool upwind = a.grad_form == LB_GRAD_UPWIND;  // force on F_eq only (host check)
   const bool big = !force3d && !mu && precision == LB_FP32_FP64MATCH &&
                    (size_t)a.n_sites * kSl * 25 * sizeof(float) * 3 > kMallBytes;
   const int ty = precision == LB_FP32_FP64MATCH ? (big ? kBigTileRows : TileRows<float>::v) : TileRows<double>::v;
@@ -931,12 +961,17 @@ hipError_t launch_stage(int precision, int stage, const void* Fin, const void* F
 #define LB_STAGE_ARGS stage, g, b, Fin, Fbase, Fout, lnMin, lnMbase, lnMout, scin, scout, sc, tb, a, err, s
   if (precision == LB_FP32_FP64MATCH) {
     constexpr int TY = TileRows<float>::v;
-    if (big) return stage_launch_t<float, kBigTileRows, kNT, 0, 0>(LB_STAGE_ARGS);
+    if (big) return upwind ? stage_launch_t<float, kBigTileRows, kNT, 0, 0, 1>(LB_STAGE_ARGS)
+                           : stage_launch_t<float, kBigTileRows, kNT, 0, 0>(LB_STAGE_ARGS);
+    if (upwind)
+      return mu ? stage_launch_t<float, TY, 0, 0, 1, 1>(LB_STAGE_ARGS) : stage_launch_t<float, TY, 0, 0, 0, 1>(LB_STAGE_ARGS);
     if (force3d)
       return mu ? stage_launch_t<float, TY, 0, 1, 1>(LB_STAGE_ARGS) : stage_launch_t<float, TY, 0, 1, 0>(LB_STAGE_ARGS);
     return mu ? stage_launch_t<float, TY, 0, 0, 1>(LB_STAGE_ARGS) : stage_launch_t<float, TY, 0, 0, 0>(LB_STAGE_ARGS);
   }
   constexpr int TY = TileRows<double>::v;
+  if (upwind)
+    return mu ? stage_launch_t<double, TY, 0, 0, 1, 1>(LB_STAGE_ARGS) : stage_launch_t<double, TY, 0, 0, 0, 1>(LB_STAGE_ARGS);
   if (force3d)
     return mu ? stage_launch_t<double, TY, 0, 1, 1>(LB_STAGE_ARGS) : stage_launch_t<double, TY, 0, 1, 0>(LB_STAGE_ARGS);
   return mu ? stage_launch_t<double, TY, 0, 0, 1>(LB_STAGE_ARGS) : stage_launch_t<double, TY, 0, 0, 0>(LB_STAGE_ARGS);

@@ -67,6 +67,21 @@ def test_unstable_or_massless_eos_is_rejected():
     assert rc == lb.LB_E_EOS and "mass" in lb.last_error()
 
 
+def test_upwind_gradient_validation():
+    # gradient_form LB_GRAD_UPWIND is defined for the force on F_eq only;
+    # the adjoint and the batched form take the centred gradient
+    p = lb.make_params(8, 8, 0.2, gradient_form=lb.LB_GRAD_UPWIND)
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(p)) > 0
+    q = lb.make_params(8, 8, 0.2, gradient_form=lb.LB_GRAD_UPWIND, force_form=lb.LB_FORCE_WEAK3D)
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(q)) == 0 and "gradient_form" in lb.last_error()
+    q = lb.make_params(8, 8, 0.2, gradient_form=5)
+    assert lb.lib.lb_workspace_bytes(ctypes.byref(q)) == 0
+    ev = (lb.lb_event * 1)(lb.lb_event(8, 8, 0.2, 0.1))
+    out = ctypes.c_void_p()
+    e0 = (ctypes.c_void_p * 1)(512)
+    assert lb.lib.lb_batch_init(ctypes.byref(out), ctypes.byref(p), ev, 1, 256, 1 << 40, e0, None) == lb.LB_E_NOTIMPL
+
+
 def test_calls_without_context():
     assert lb.lib.lb_step(None, 1, 0.01) == lb.LB_E_STATE
     assert lb.lib.lb_moments(None, None) == lb.LB_E_STATE

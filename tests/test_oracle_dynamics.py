@@ -326,3 +326,33 @@ def test_energy_balance_with_flow_and_mass_evolution(lat, eos):
 
     rp = [_flowing_box_energy_residual(lat, eos, dt, planted_rhs) for dt in (0.002, 0.001)]
     assert min(abs(x) for x in rp) > 1e-4 and abs(rp[1] / rp[0]) > 0.7, rp
+
+
+def test_grid_scale_mass_modes_need_the_upwind_gradient():
+    # White noise (5% per 0.025 fm cell, the precision workload's) on a
+    # uniform T = 0.4 GeV state at eta/s 0.2: with the centred ln M
+    # gradient of the force, modes near the grid scale, which a centred
+    # difference barely sees (sin(k dx) -> 0), grow in ln M (spread 0.02 ->
+    # 0.09 in 100 steps, 0.41 in 120); a spectral gradient or the streaming's
+    # own upwind difference per node (Params.grad = "upwind") keeps them
+    # bounded (0.006 -> 0.002).  The two parts of the fixed-v transport,
+    # streaming and force, then use one difference operator.
+    eos = TanhEntropyEoS()
+    lat = Lattice(5, 5, 4, 1.0)
+    n, dx, dt = 16, 0.025, 0.0075
+    from paper_1108_5561_amd import workloads as wl
+    e0 = float(eos.eps(0.4)) / HBARC ** 3 * wl.white_noise_factor(n, n)
+    spread = {}
+    for grad in ("centred", "upwind"):
+        prm = st.Params(dx=dx, eta_over_s=0.2, grad=grad)
+        F, l = st.init_state(lat, eos, e0)
+        s0 = None
+        tau = 0.5
+        for k in range(100):
+            F, l = st.heun_step(lat, eos, prm, F, l, tau, dt)
+            tau += dt
+            if k == 19:
+                s0 = l.max() - l.min()
+        spread[grad] = (s0, l.max() - l.min())
+    assert spread["centred"][1] > 3 * spread["centred"][0], spread
+    assert spread["upwind"][1] < spread["upwind"][0] and spread["upwind"][1] < 0.01, spread
