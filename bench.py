@@ -38,7 +38,7 @@ def site_bytes(precision, stage):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_prec256_hbm_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1108_5561_amd", "csrc", f) for f in ("lb_device.hip", "stage_body.inc")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1108_5561_amd", "csrc", f) for f in ("lb_device.hip", "stage_body.inc", "device_common.hpp")]
 
 
 def measured_traffic(kernel):
@@ -502,7 +502,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": bytes_launch, "kernel": kname,
-                     "kernel_avg_us": kms * 1e3},
+                     "kernel_avg_us": kms * 1e3,
+                     # the whole Heun step (both stage kernels, as timed by
+                     # the step loop) against the same peak
+                     "step_achieved": step_bytes * args.steps / (r32["ms"] / 1e3) / 1e9,
+                     "step_frac": step_bytes * args.steps / (r32["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

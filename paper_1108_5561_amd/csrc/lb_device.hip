@@ -358,7 +358,7 @@ template <typename R>
 __device__ __forceinline__ void weak_force(const R f[25], CPtr<R> C, R gx, R gy, int l, R scale, R r0[25], R* sw,
                                            int lw) {
   const int sb = lw & 56;  // first lane of this site in the wave
-  const R cl = lane_entry<R>(C->cosl, l), sl = lane_entry<R>(C->sinl, l);
+  const R cl = C->cosl[l], sl = C->sinl[l];
   const R gr = gx * cl + gy * sl;  // g . (cos phi, sin phi)
   // this lane's mode (as a mode index r = l): 0, 4, 1c, 1s, 2c, 2s, 3c, 3s
   const int m = l < 2 ? 4 * l : (l >> 1);
