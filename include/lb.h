@@ -286,6 +286,22 @@ int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F,
                     size_t adj_ws_bytes);
 
 /*
+ * lb_adjoint_step without the adjoint workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the scratch lives in a static device
+ * array of the library, 80 MiB per device (held from the library's load
+ * until the process ends), enough for grids of up to about 17000 sites
+ * (4840 bytes per site; the 128 x 128 gradient workload fits).  Arguments,
+ * results and errors as lb_adjoint_step; LB_E_ARG with a message if the
+ * grid needs more scratch than that.  Calls on one device share its array,
+ * so calls that overlap on one device (other streams, other threads) race;
+ * each call writes every scratch value before reading it.  Allocates
+ * nothing (the array's address is looked up once per device).
+ */
+int lb_adjoint_step_noalloc(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F, const double* d_lnM,
+                            double* d_adj_F, double* d_adj_lnM, double* d_grad_eta_over_s);
+
+/*
  * Reverse mode of the initial state of lb_init (T0 from eps_EoS(T0) = e0,
  * M = M(T0), F_n = Z exp(-(u . P_n)/T0), the flow held fixed): writes
  * d_grad_e0[ny][nx] = dL/d e0 (per GeV/fm^3) given (d_adj_F, d_adj_lnM) =

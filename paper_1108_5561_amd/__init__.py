@@ -84,6 +84,7 @@ def _load():
         "lb_adjoint_workspace_bytes": (sz, [P]),
         "lb_adjoint_forward_step": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp, sz]),
         "lb_adjoint_step": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp, vp, sz]),
+        "lb_adjoint_step_noalloc": (ctypes.c_int, [vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp]),
         "lb_adjoint_init": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "lb_status": (ctypes.c_int, [vp]),
         "lb_destroy": (ctypes.c_int, [vp]),
@@ -313,6 +314,13 @@ class Context:
         check(lib.lb_adjoint_step(self._ctx, float(tau_fm), float(dtau_fm), F.data_ptr(), lnM.data_ptr(),
                                   adj_F.data_ptr(), adj_lnM.data_ptr(), grad_eta.data_ptr(), ws.data_ptr(),
                                   ws.numel()))
+
+    def adjoint_step_noalloc(self, tau_fm, dtau_fm, F, lnM, adj_F, adj_lnM, grad_eta):
+        """As adjoint_step, with the library's static device scratch instead
+        of a workspace (lb_adjoint_step_noalloc; allocates nothing)."""
+        self._state_check(F, lnM, adj_F, adj_lnM)
+        check(lib.lb_adjoint_step_noalloc(self._ctx, float(tau_fm), float(dtau_fm), F.data_ptr(), lnM.data_ptr(),
+                                          adj_F.data_ptr(), adj_lnM.data_ptr(), grad_eta.data_ptr()))
 
     def adjoint_init(self, e0, adj_F, adj_lnM, ux0=None, uy0=None):
         """dL/d e0 [ny, nx] from the adjoint of the initial state."""

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbmi.so")
-SOURCES = ["lb_device.hip", "lb_adjoint.hip", "lb_api.cpp", "host_setup.cpp"]
+SOURCES = ["lb_device.hip", "lb_adjoint.hip", "lb_noalloc.hip", "lb_api.cpp", "host_setup.cpp"]
 
 # packed FP32 instructions are disabled: the compiler would otherwise emit
 # v_pk_* FP32 forms for ordinary float code

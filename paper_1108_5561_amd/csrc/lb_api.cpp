@@ -687,6 +687,7 @@ int lb_adjoint_forward_step(lb_ctx* c, double tau_fm, double dtau_fm, const doub
 int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F, const double* d_lnM,
                     double* d_adj_F, double* d_adj_lnM, double* d_grad_eta_over_s, void* d_adj_workspace,
                     size_t adj_ws_bytes) {
+  g_err.clear();
   AdjBufs B;
   int rc = adj_check(c, tau_fm, dtau_fm, d_adj_workspace, adj_ws_bytes, &B);
   if (rc != LB_OK) return rc;
@@ -908,6 +909,14 @@ int lb_eos_eval(const lb_params* p, int64_t n, const double* T, double* out, int
 }
 
 }  // extern "C"
+
+// Internal hooks for the entry point without allocation (lb_noalloc.hip),
+// which brings its own device scratch in place of the adjoint workspace.
+namespace lbmi {
+int set_error(int code, const char* msg) { return fail(code, msg); }
+int context_device(const lb_ctx* c) { return c ? c->device : -1; }
+size_t context_adjoint_bytes(const lb_ctx* c) { return c && c->initialised ? adj_layout(c->p).total : 0; }
+}  // namespace lbmi
 
 // ---------------------------------------------------------------------------
 // Batched form: many events advanced together (lb_batch_* in lb.h).
