@@ -365,7 +365,7 @@ def cpu_oracle_worker(n_steps, warmup, window):
     print(json.dumps({"wall_s": wall, "cpu_s": cpu_s, "site_updates": n_steps * window * window}), flush=True)
 
 
-def cpu_baseline(n_steps=10, warmup=2, window=48):
+def cpu_baseline(n_steps=12, warmup=2, window=64):
     """The oracle as it stands (FP64 numpy, vectorised over sites) on the
     host cores: a bounded sample of the 256 x 256 workload (a window x window
     periodic window of its initial state, 2 warm-up and n_steps timed Heun

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/lb.h"
+#include "generic.hpp"
 #include "host_setup.hpp"
 #include "kernels.hpp"
 
@@ -34,6 +35,7 @@ struct lb_ctx {
   double* g3 = nullptr;  // dense weak-form force operators [2][N][N] (3-D force only)
   double tau = 0;
   bool initialised = false;
+  bool generic = false;  // momentum lattice other than 5 x 5 x 8: FP64 kernels of lb_generic.hip
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> ev;  // 3 per step
@@ -60,8 +62,14 @@ struct Layout {
 
 std::string validate(const lb_params* p) {
   if (!p) return "params is NULL";
-  if (p->n_xi != 5 || p->n_theta != 5 || p->n_phi != 4)
-    return "this build supports n_xi = n_theta = 5 and n_phi = 4";
+  if (!(p->n_xi == 5 && p->n_theta == 5 && p->n_phi == 4)) {
+    // other lattices run on the generic FP64 kernels
+    if (!gen_supported(p->n_xi, p->n_theta, p->n_phi))
+      return "momentum lattice: n_xi and n_theta in {3, 5, 7}, n_phi in {3, 4, 5}";
+    if (p->precision != LB_FP64) return "a momentum lattice other than 5 x 5 x 8 runs in precision LB_FP64";
+    if (p->force_form != LB_FORCE_FEQ) return "a momentum lattice other than 5 x 5 x 8 takes force_form LB_FORCE_FEQ";
+    if (p->particle_number != LB_N_FREE) return "a momentum lattice other than 5 x 5 x 8 takes particle_number LB_N_FREE";
+  }
   if (!(p->z0 > 0) || !std::isfinite(p->z0)) return "z0 must be finite and > 0";
   if (!(p->Z > 0) || !std::isfinite(p->Z)) return "Z must be finite and > 0";
   if (p->nx < 1 || p->ny < 1) return "nx and ny must be >= 1";
@@ -136,7 +144,7 @@ Layout layout(const lb_params* p) {
     off = align_up(off + site_scalar_bytes(sites, elt));
   }
   L.cst = off;
-  off = align_up(off + sizeof(StageConst<double>));
+  off = align_up(off + std::max(sizeof(StageConst<double>), sizeof(GenConst)));
   L.tbd = off;
   off = align_up(off + sizeof(EosTable));
   L.pts = off;
@@ -198,6 +206,43 @@ void fill_const(const HostLattice& L, LatticeConst<R, 5, 5>* C) {
   for (int l = 0; l < 8; ++l) {
     C->cosl[l] = (R)L.cosl[l];
     C->sinl[l] = (R)L.sinl[l];
+  }
+}
+
+// Constants of the generic-lattice kernels (lb_generic.hip).
+void fill_gen_const(const HostLattice& L, GenConst* C) {
+  *C = GenConst{};
+  const int nxi = L.nxi, nth = L.nth, nl = 2 * L.nphi;
+  for (int k = 0; k < nxi; ++k) {
+    C->x[k] = L.x[k];
+    C->sh2[k] = L.x[k] * L.x[k] - 1.0;
+  }
+  for (int j = 0; j < nth; ++j) C->mu2[j] = L.mu[j] * L.mu[j];
+  for (int k = 0; k < nxi; ++k)
+    for (int j = 0; j < nth; ++j) {
+      const int q = k * nth + j;
+      const double sh = std::sqrt(L.x[k] * L.x[k] - 1.0), sth = std::sqrt(1.0 - L.mu[j] * L.mu[j]);
+      const double sig = sh * sth, vY = sh * L.mu[j];
+      const double w = std::exp(L.z0 * L.x[k]) * L.wxi[k] * L.wth[j] / (4.0 * L.nphi);
+      C->w[q] = w;
+      C->sig[q] = sig;
+      C->sigi[q] = sig / L.x[k];
+      C->sig2[q] = sig * sig;
+      C->wx2[q] = w * L.x[k] * L.x[k];
+      C->wxs[q] = w * L.x[k] * sig;
+      C->ws2[q] = w * sig * sig;
+      C->wvY2[q] = w * vY * vY;
+      C->wx[q] = w * L.x[k];
+      C->wsig[q] = w * sig;
+    }
+  for (int i = 0; i < nxi * nxi; ++i) {
+    C->A1[i] = L.A1[i];
+    C->A2[i] = L.A2[i];
+  }
+  for (int i = 0; i < nth * nth; ++i) C->Ath[i] = L.Ath[i];
+  for (int l = 0; l < nl; ++l) {
+    C->cosl[l] = L.cosl[l];
+    C->sinl[l] = L.sinl[l];
   }
 }
 
@@ -338,6 +383,7 @@ StageArgs stage_args(const lb_ctx* c, double tau, double dtau);
 
 // Site scalars of the current state (after lb_init / lb_set_state).
 hipError_t prime_site_scalars(lb_ctx* c) {
+  if (c->generic) return hipSuccess;  // the generic kernels match at the start of each stage
   const StageArgs a = stage_args(c, c->tau, 0.0);
   const int cur = c->cur;
   return launch_site(c->p.precision, c->F[cur], c->lnM[cur], c->sc[cur], c->cst, c->tbd, a, c->err, c->stream);
@@ -416,6 +462,7 @@ int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBuf
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   if (c->p.particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the adjoint step has mu = 0 only");
   if (c->p.gradient_form != LB_GRAD_CENTRED) return fail(LB_E_NOTIMPL, "the adjoint step has the centred ln M gradient only");
+  if (c->generic) return fail(LB_E_NOTIMPL, "the adjoint step has the 5 x 5 x 8 momentum lattice only");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
   if (!std::isfinite(tau) || (c->p.metric == LB_METRIC_MILNE && !(tau > 0)))
     return fail(LB_E_ARG, "tau must be finite (and > 0 for the Milne metric)");
@@ -526,7 +573,15 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
     delete c;
     return hip_fail(e, "upload of EoS tables");
   }
-  {
+  c->generic = !(p->n_xi == 5 && p->n_theta == 5 && p->n_phi == 4);
+  if (c->generic) {
+    GenConst gc;
+    fill_gen_const(c->lat, &gc);
+    if ((e = hipMemcpy(c->cst, &gc, sizeof(gc), hipMemcpyHostToDevice)) != hipSuccess) {
+      delete c;
+      return hip_fail(e, "upload of lattice constants");
+    }
+  } else {
     StageConst<float> sf;
     StageConst<double> sd;
     if (p->precision == LB_FP32_FP64MATCH) {
@@ -558,8 +613,14 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
   c->tau = p->tau0_fm;
   c->cur = 0;
   StageArgs a = stage_args(c, c->tau, 0.0);
-  if ((e = launch_init(p->precision, d_e0, d_ux0, d_uy0, c->F[0], c->lnM[0], lat_const(c), c->tb, a, c->err,
-                       c->stream)) != hipSuccess) {
+  if (c->generic) {
+    e = launch_gen_init(p->n_xi, p->n_theta, 2 * p->n_phi, d_e0, d_ux0, d_uy0, (double*)c->F[0], c->lnM[0],
+                        (const GenConst*)c->cst, c->tbd, a, c->err, c->stream);
+  } else {
+    e = launch_init(p->precision, d_e0, d_ux0, d_uy0, c->F[0], c->lnM[0], lat_const(c), c->tb, a, c->err,
+                    c->stream);
+  }
+  if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "init kernel launch");
   }
@@ -601,8 +662,25 @@ int lb_step(lb_ctx* c, int32_t n_steps, double dtau) {
       hipEventRecord(e0, c->stream);
     }
     StageArgs a = stage_args(c, c->tau, dtau);
-    hipError_t e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], c->sc[i0],
-                                c->sc[i1], c->cst, c->tbd, a, c->err, c->stream);
+    hipError_t e;
+    if (c->generic) {
+      const int nxi = c->p.n_xi, nth = c->p.n_theta, nl = 2 * c->p.n_phi;
+      const GenConst* gc = (const GenConst*)c->cst;
+      e = launch_gen_stage(nxi, nth, nl, 0, (const double*)c->F[i0], c->lnM[i0], nullptr, nullptr, (double*)c->F[i1],
+                           c->lnM[i1], gc, c->tbd, a, c->err, c->stream);
+      if (e != hipSuccess) return hip_fail(e, "predictor launch");
+      if (c->prof) hipEventRecord(e1, c->stream);
+      set_tau(&a, c, c->tau + dtau);
+      e = launch_gen_stage(nxi, nth, nl, 1, (const double*)c->F[i1], c->lnM[i1], (const double*)c->F[i0], c->lnM[i0],
+                           (double*)c->F[i2], c->lnM[i2], gc, c->tbd, a, c->err, c->stream);
+      if (e != hipSuccess) return hip_fail(e, "corrector launch");
+      if (c->prof) hipEventRecord(e2, c->stream);
+      c->cur = i2;
+      c->tau += dtau;
+      continue;
+    }
+    e = launch_stage(prec, 0, c->F[i0], nullptr, c->F[i1], c->lnM[i0], nullptr, c->lnM[i1], c->sc[i0],
+                     c->sc[i1], c->cst, c->tbd, a, c->err, c->stream);
     if (e != hipSuccess) return hip_fail(e, "predictor launch");
     if (c->prof) hipEventRecord(e1, c->stream);
     set_tau(&a, c, c->tau + dtau);
@@ -621,8 +699,11 @@ int lb_moments(lb_ctx* c, double* d_out) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   if (!d_out) return fail(LB_E_ARG, "out is NULL");
   StageArgs a = stage_args(c, c->tau, 0.0);
-  hipError_t e = launch_moments(c->p.precision, c->F[c->cur], c->lnM[c->cur], d_out, lat_const(c), c->tb, a,
-                                c->err, c->stream);
+  hipError_t e = c->generic ? launch_gen_moments(c->p.n_xi, c->p.n_theta, 2 * c->p.n_phi, (const double*)c->F[c->cur],
+                                                 c->lnM[c->cur], d_out, (const GenConst*)c->cst, c->tbd, a, c->err,
+                                                 c->stream)
+                            : launch_moments(c->p.precision, c->F[c->cur], c->lnM[c->cur], d_out, lat_const(c), c->tb,
+                                             a, c->err, c->stream);
   if (e != hipSuccess) return hip_fail(e, "moments launch");
   return LB_OK;
 }
@@ -631,7 +712,10 @@ int lb_get_state(lb_ctx* c, double* d_F, double* d_lnM, double* tau_fm) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   const int n_sites = c->p.nx * c->p.ny, n_q = c->p.n_xi * c->p.n_theta;
   if (d_F) {
-    hipError_t e = launch_get_state(c->p.precision, c->F[c->cur], d_F, n_q, n_sites, c->stream);
+    // the generic kernels keep the canonical FP64 layout
+    hipError_t e = c->generic ? hipMemcpyAsync(d_F, c->F[c->cur], (size_t)n_sites * n_q * 2 * c->p.n_phi * 8,
+                                               hipMemcpyDeviceToDevice, c->stream)
+                              : launch_get_state(c->p.precision, c->F[c->cur], d_F, n_q, n_sites, c->stream);
     if (e != hipSuccess) return hip_fail(e, "get_state launch");
   }
   if (d_lnM) {
@@ -648,7 +732,9 @@ int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_f
   if (!std::isfinite(tau_fm) || (c->p.metric == LB_METRIC_MILNE && !(tau_fm > 0)))
     return fail(LB_E_ARG, "tau must be finite (and > 0 for Milne)");
   const int n_sites = c->p.nx * c->p.ny, n_q = c->p.n_xi * c->p.n_theta;
-  hipError_t e = launch_set_state(c->p.precision, d_F, c->F[c->cur], n_q, n_sites, c->stream);
+  hipError_t e = c->generic ? hipMemcpyAsync(c->F[c->cur], d_F, (size_t)n_sites * n_q * 2 * c->p.n_phi * 8,
+                                             hipMemcpyDeviceToDevice, c->stream)
+                            : launch_set_state(c->p.precision, d_F, c->F[c->cur], n_q, n_sites, c->stream);
   if (e != hipSuccess) return hip_fail(e, "set_state launch");
   e = hipMemcpyAsync(c->lnM[c->cur], d_lnM, (size_t)n_sites * 8, hipMemcpyDeviceToDevice, c->stream);
   if (e != hipSuccess) return hip_fail(e, "copy of ln M");
@@ -722,6 +808,7 @@ int lb_adjoint_init(lb_ctx* c, const double* d_e0, const double* d_ux0, const do
   if (!d_e0 || !d_adj_F || !d_adj_lnM || !d_grad_e0) return fail(LB_E_ARG, "pointer is NULL");
   if ((d_ux0 == nullptr) != (d_uy0 == nullptr)) return fail(LB_E_ARG, "give both ux0 and uy0 or neither");
   if (c->p.particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the adjoint of lb_init has mu = 0 only");
+  if (c->generic) return fail(LB_E_NOTIMPL, "the adjoint of lb_init has the 5 x 5 x 8 momentum lattice only");
   const StageArgs a = stage_args(c, c->p.tau0_fm, 0.0);
   hipError_t e = launch_adj_init(d_e0, d_ux0, d_uy0, d_adj_F, d_adj_lnM, d_grad_e0, &c->cd, c->tb, a, c->err,
                                  c->stream);
@@ -780,6 +867,7 @@ int lb_profile_read(lb_ctx* c, double* ms_out, int64_t* count_out) {
 int lb_profile_stage(lb_ctx* c, int32_t stage, int32_t n, double dtau_fm, double* ms_out) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   if ((stage != 0 && stage != 1) || n < 1 || !ms_out) return fail(LB_E_ARG, "need stage 0 or 1, n >= 1, ms_out");
+  if (c->generic) return fail(LB_E_NOTIMPL, "stage timing has the 5 x 5 x 8 momentum lattice only");
   if (!(dtau_fm > 0) || !std::isfinite(dtau_fm)) return fail(LB_E_ARG, "dtau must be finite and > 0");
   const int prec = c->p.precision;
   const int i0 = c->cur, i1 = (c->cur + 1) % 3, i2 = (c->cur + 2) % 3;
@@ -971,6 +1059,7 @@ lb_params event_params(const lb_params& p, const lb_event& e) {
 std::string validate_batch(const lb_params* p, const lb_event* ev, int32_t n) {
   if (!p) return "params is NULL";
   if (!ev || n < 1) return "need at least one event";
+  if (!(p->n_xi == 5 && p->n_theta == 5 && p->n_phi == 4)) return "the batched form has the 5 x 5 x 8 momentum lattice only";
   int64_t tiles = 0;
   for (int i = 0; i < n; ++i) {
     const lb_params q = event_params(*p, ev[i]);

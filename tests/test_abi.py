@@ -28,7 +28,7 @@ def test_workspace_bytes_and_validation():
     p32 = lb.make_params(32, 32, 0.2, precision=lb.LB_FP32_FP64MATCH)
     assert lb.workspace_bytes(p32) < n
     for bad in [dict(nx=0), dict(ny=-1), dict(dx_fm=0.0), dict(dx_fm=float("nan")), dict(eta_over_s=0.0),
-                dict(n_xi=3), dict(n_phi=3), dict(z0=-1.0), dict(T_min_GeV=0.0), dict(eos_width_GeV=0.0),
+                dict(n_xi=4), dict(n_phi=6), dict(n_theta=9), dict(z0=-1.0), dict(T_min_GeV=0.0), dict(eos_width_GeV=0.0),
                 dict(tau0_fm=0.0), dict(precision=7), dict(metric=5), dict(taur_rule=3), dict(Z=0.0)]:
         q = lb.make_params(32, 32, 0.2)
         for k, v in bad.items():
@@ -65,6 +65,21 @@ def test_unstable_or_massless_eos_is_rejected():
     p = lb.make_params(8, 8, 0.2, eos_kind=lb.LB_EOS_TANH_P, eos_width_GeV=0.03, kappa=1.0)
     rc, _ = _init_rc(p)
     assert rc == lb.LB_E_EOS and "mass" in lb.last_error()
+
+
+def test_momentum_lattice_choices():
+    # n_xi, n_theta in {3, 5, 7} and n_phi in {3, 4, 5}; lattices other than
+    # 5 x 5 x 8 run on the generic FP64 kernels (force on F_eq, mu = 0)
+    for nxi, nth, nph in [(3, 5, 4), (7, 5, 5), (5, 3, 3), (5, 7, 4), (3, 3, 3)]:
+        p = lb.make_params(8, 8, 0.2, n_xi=nxi, n_theta=nth, n_phi=nph)
+        n = lb.lib.lb_workspace_bytes(ctypes.byref(p))
+        assert n >= 3 * nxi * nth * 2 * nph * 64 * 8, (nxi, nth, nph)
+        for bad in (dict(precision=lb.LB_FP32_FP64MATCH), dict(force_form=lb.LB_FORCE_WEAK3D),
+                    dict(particle_number=lb.LB_N_CONSERVED, eos_kind=lb.LB_EOS_CONST_MASS, eos_mass_GeV=0.4)):
+            q = lb.make_params(8, 8, 0.2, n_xi=nxi, n_theta=nth, n_phi=nph, **bad)
+            assert lb.lib.lb_workspace_bytes(ctypes.byref(q)) == 0 and "momentum lattice" in lb.last_error()
+    p = lb.make_params(8, 8, 0.2, n_xi=3)
+    assert lb.lib.lb_batch_workspace_bytes(ctypes.byref(p), (lb.lb_event * 1)(lb.lb_event(8, 8, 0.2, 0.1)), 1) == 0
 
 
 def test_upwind_gradient_validation():
