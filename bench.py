@@ -257,6 +257,35 @@ def run_adjoint(lb, wl, torch):
     fd = (run64(e0n, eta * (1 + h)) - run64(e0n, eta * (1 - h))) / (2 * h * eta)
     g = float(et.grad[0])
     sites_steps = nx * ny * n
+
+    # kernel-level rates on the same grid: one FP64 forward step (lb_step)
+    # and one adjoint step of the FP32 context (lb_adjoint_step), HIP events
+    # over back-to-back calls on the stream the library uses
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_.record()
+        for _ in range(reps):
+            fn()
+        b_.record()
+        torch.cuda.synchronize()
+        return a_.elapsed_time(b_) / reps
+
+    c64 = lb.Context(p64, torch.from_numpy(e0n).to("cuda:0"))
+    c64.step(50, dtau)
+    fwd64_ms = timed(lambda: c64.step(1, dtau), 50)
+    c32 = lb.Context(p32, torch.from_numpy(e0n).to("cuda:0"))
+    c32.step(50, dtau)
+    Fs, Ls, taus = c32.get_state()
+    aF, aL = torch.ones_like(Fs) * 1e-3, torch.ones_like(Ls) * 1e-3
+    g_e = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    ws = c32.adjoint_workspace()
+    adj_ms = timed(lambda: c32.adjoint_step(taus, dtau, Fs, Ls, aF, aL, g_e, ws), 20)
+    if c64.status() != lb.LB_OK or c32.status() != lb.LB_OK:
+        raise RuntimeError(lb.last_error())
+    c64.close()
+    c32.close()
     return {"workload": f"{nx}x{ny} hot spots (rng {w['seed']}) on eps_EoS(0.25 GeV), dx {dx} fm, eta/s {eta}, "
                         f"{n} steps of {dtau} fm/c, FP32 forward, checkpoints every {w['checkpoint_every']} steps; "
                         "objective tau_f dx^2 sum (T^xx - T^yy)",
@@ -264,7 +293,9 @@ def run_adjoint(lb, wl, torch):
             "adjoint_ms_per_step": (t2 - t1) * 1e3 / n,
             "gradient_site_updates_per_s": sites_steps / ((t1 - t0) + (t2 - t1)),
             "dO_deta": g, "dO_deta_fd_fp64": fd, "rel_err": abs(g - fd) / abs(fd),
-            "e0_grad_norm": float(e0.grad.norm())}
+            "e0_grad_norm": float(e0.grad.norm()),
+            "adjoint_step_ms": adj_ms, "fp64_forward_step_ms": fwd64_ms,
+            "adjoint_step_over_fp64_step": adj_ms / fwd64_ms}
 
 
 def tmunu_rel_err(a, b):

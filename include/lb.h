@@ -246,10 +246,12 @@ int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_f
  * and M_eq from the Landau matching of eq. (sanity) and the EoS inversion
  * of Sec. III.A, whose derivatives are taken by the implicit-function
  * theorem).  States and adjoints are in the canonical order of
- * lb_get_state, FP64: F [N][ny][nx], ln M [ny][nx].  The adjoint arithmetic
- * is FP64 for either precision of the context; for an LB_FP32_FP64MATCH
- * context it is the FP64 step's adjoint evaluated on the states the caller
- * passes (e.g. the FP32 trajectory).  The calls only read the context's
+ * lb_get_state, FP64: F [N][ny][nx], ln M [ny][nx].  The adjoint is that of
+ * the FP64 step, evaluated on the states the caller passes (e.g. the FP32
+ * trajectory of an LB_FP32_FP64MATCH context).  For an LB_FP64 context all
+ * of its arithmetic is FP64; for an LB_FP32_FP64MATCH context the reverse
+ * sweep's per-node arithmetic is FP32 (the per-site chain through the
+ * matching and the EoS, and the site sums, stay FP64), as the forward.  The calls only read the context's
  * parameters, lattice and EoS tables; its state is not used or changed.
  * The adjoint workspace is caller-owned device memory, 256-byte aligned, of
  * at least lb_adjoint_workspace_bytes(p) bytes, not touched by anyone else

@@ -112,19 +112,21 @@ hipError_t launch_force_columns(const void* cst64, double* G, hipStream_t s);
 // context's LatticeConst<double, 5, 5>.
 hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const double* Fbase, const double* Lbase,
                                 double* Fout, double* Lout, int stage, const void* lc, const double* g3,
-                                const EosTable& tb, const StageArgs& a, int* err, hipStream_t s);
+                                const EosTable& tb, const StageArgs& a, int* err, hipStream_t s,
+                                int fp32_nodes = 0);
 // Reverse sweep of one right-hand side at (F, ln M), time a.tau, with
 // K_bar = scale seedF, X_bar = scale seedL, into (outF, outL) (written, or
 // added with accumulate = 1), plus the per-site eta/s adjoint; Rb
-// ([N][sites]) and gb ([2][sites]) are scratch.
+// ([N][sites]) and gb ([2][sites]) are scratch.  fp32_nodes: the per-node
+// arithmetic in FP32 (site chain FP64, once per site).
 hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF, const double* seedL,
                           double scale, double* outF, double* outL, double* Rb, double* gb, double* eta_part,
                           int accumulate, const void* lc, const double* g3, const EosTable& tb,
-                          const StageArgs& a, int* err, hipStream_t s);
-// y += c x, then z *= cz (z may be null), n values.
-hipError_t launch_adj_axpy(double* y, const double* x, double c, double* z, double cz, size_t n, hipStream_t s);
+                          const StageArgs& a, int* err, hipStream_t s, int fp32_nodes = 0);
 // *out += sum of v[0..n), deterministic order.
 hipError_t launch_adj_sum(const double* v, int n, double* out, hipStream_t s);
+// a1 <- a1 + a/2, then a <- a/2 + a1, n values (the step adjoint's Heun combination).
+hipError_t launch_adj_combine(double* a1, double* a, size_t n, hipStream_t s);
 // d/d e0 of (aF . F0 + aL . ln M0) for the initial state of lb_init.
 hipError_t launch_adj_init(const double* e0, const double* ux0, const double* uy0, const double* aF,
                            const double* aL, double* grad_e0, const void* lc, const EosTable& tb,

@@ -491,6 +491,496 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   }
 }
 
+// The reverse sweep of adj_local_kernel for contexts whose forward runs in
+// FP32: the same arithmetic with the per-node arrays (slice values, R0, S2,
+// their adjoints) in FP32, the site sums reduced in FP64, and the per-site
+// FP64 chain (moments -> Landau matching -> EoS, and its reverse through
+// the implicit-function adjoints) done once per site, by the thread of
+// slice 0, and handed to the site's other seven threads through LDS.  With
+// FP32 arrays the seven slice arrays fit the register file (the FP64 form
+// spills), and three of the block's four waves skip the FP64 chain.
+struct SiteLds {
+  double m[6];  // sum w F V^a V^b: tau tau, tau x, tau y, xx, xy, yy
+  double M, G, lam, u[3];
+  double T, Meq, beta, q, invT, MT, rate;
+  double du_dlam, dz, dbeta, dq;
+  double gx, gy;
+  double mb[6];  // the moments' adjoint: 00, 01 + 10, 02 + 20, 11, 12 + 21, 22
+};
+
+__global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
+    const double* __restrict__ F, const double* __restrict__ Lm, const double* __restrict__ seedF,
+    const double* __restrict__ seedL, double scale, double* __restrict__ outF, double* __restrict__ outL,
+    double* __restrict__ Rb, double* __restrict__ gb, double* __restrict__ eta_part, int accumulate,
+    const LC C, const double* __restrict__ g3, const EosTable tb, const StageArgs a, int* __restrict__ err) {
+  typedef float R;
+  __shared__ RedBuf red;
+  __shared__ SiteLds sd[kSites];
+  const Lane g = lane_of(a);
+  const int ns = a.n_sites, l = g.l;
+  R f[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) f[q] = (R)F[cix(q, l, g.site, ns)];
+  const SliceGeom gm = slice_geom(C, a, l);
+  // moments (eq. (emtnew)), reduced over the slices in FP64
+  {
+    R q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      q0 += (R)C.wx2[q] * f[q];
+      q1 += (R)C.wxs[q] * f[q];
+      q2 += (R)C.ws2[q] * f[q];
+    }
+    double v[6] = {(double)q0, (double)q1 * gm.cl, (double)q1 * gm.sl, (double)q2 * gm.cl * gm.cl,
+                   (double)q2 * gm.cl * gm.sl, (double)q2 * gm.sl * gm.sl};
+    slice_sum<6>(v, red, g);
+    if (l == 0) {
+      // the site's forward chain, once: Landau matching (eq. (sanity)) and EoS
+      SiteLds& S = sd[g.sl];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) S.m[i] = v[i];
+      S.M = exp(Lm[g.site]);
+      S.G = S.M * S.M * S.M * S.M * (1.0 / (2.0 * kPi * kPi));
+      const double tk[6] = {S.G * v[0], S.G * v[1], S.G * v[2], S.G * v[3], S.G * v[4], S.G * v[5]};
+      double u[3], lam;
+      const bool matched = landau3(tk, &lam, u);
+      EosAt E;
+      EosDer D;
+      const bool eos_ok = eos_cell(tb, lam, &E, &D);
+      bool finite = true;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
+      if (g.valid) {
+        if (!finite) flag(err, kErrNonfinite);
+        else if (!matched) flag(err, kErrMatch);
+        else if (!eos_ok) flag(err, kErrEos);
+      }
+      S.lam = lam;
+      S.u[0] = u[0];
+      S.u[1] = u[1];
+      S.u[2] = u[2];
+      S.T = E.T;
+      S.Meq = E.M_eq;
+      S.beta = E.beta;
+      S.q = E.q;
+      S.invT = 1.0 / E.T;
+      S.MT = S.M * S.invT;
+      S.rate = E.T * a.inv_eta_hbarc / E.q;
+      S.du_dlam = D.du_dlam;
+      S.dz = D.dz;
+      S.dbeta = D.dbeta;
+      S.dq = D.dq;
+      const int x = g.x, y = g.y;
+      S.gx = (Lm[y * a.nx + wrap(x + 1, a.nx)] - Lm[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
+      S.gy = (Lm[wrap(y + 1, a.ny) * a.nx + x] - Lm[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
+    }
+    __syncthreads();
+  }
+  const SiteLds& S = sd[g.sl];
+  const bool f3 = g3 != nullptr;
+  const R ut = (R)S.u[0], ux = (R)S.u[1], uy = (R)S.u[2], M = (R)S.M, Meq = (R)S.Meq;
+  const R invT = (R)S.invT, MT = (R)S.MT, rate = (R)S.rate;
+  const R cl = (R)gm.cl, sl = (R)gm.sl;
+  const R cu = ux * cl + uy * sl;
+  const R Gl = f3 ? (R)0 : (R)(S.gx * gm.cl + S.gy * gm.sl);
+  const R gu = f3 ? (R)0 : (R)(S.gx * S.u[1] + S.gy * S.u[2]);
+  R Eeq[5], al[5], be[5], ga[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    Eeq[k] = sqrtf(Meq * Meq + M * M * (R)C.sh2[k]);
+    al[k] = MT * Gl * ut * M * (R)C.x[k] / Eeq[k];
+    be[k] = MT * Gl * cu * (R)C.inv_x[k];
+    ga[k] = MT * gu * (R)C.inv_x[k];
+  }
+  // forward right-hand side of the slice: R0, S2 and the three site sums
+  R R0[kQ], S2[kQ];
+  double sums[4];
+  {
+    const int x = g.x, y = g.y;
+    const int s_x1 = y * a.nx + wrap(x - gm.dxr, a.nx), s_x2 = y * a.nx + wrap(x - 2 * gm.dxr, a.nx);
+    const int s_y1 = wrap(y - gm.dyr, a.ny) * a.nx + x, s_y2 = wrap(y - 2 * gm.dyr, a.ny) * a.nx + x;
+    const R ax = (R)gm.ax, ay = (R)gm.ay;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const R tr = (R)3 * (ax + ay) * f[q] - (R)4 * ax * (R)F[cix(q, l, s_x1, ns)] + ax * (R)F[cix(q, l, s_x2, ns)] -
+                   (R)4 * ay * (R)F[cix(q, l, s_y1, ns)] + ay * (R)F[cix(q, l, s_y2, ns)];
+      R0[q] = -(R)C.sigi[q] * tr;
+    }
+    const bool milne = a.metric == LB_METRIC_MILNE;
+    const R itau = (R)(1.0 / a.tau);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        R s2 = 0, s1r = 0, s1p = 0;
+#pragma unroll
+        for (int kp = 0; kp < 5; ++kp) {
+          s2 += (R)C.A2[k * 5 + kp] * f[kp * 5 + j];
+          s1r += (R)C.A1[k * 5 + kp] * f[kp * 5 + j];
+        }
+#pragma unroll
+        for (int jp = 0; jp < 5; ++jp) s1p += (R)C.Ath[j * 5 + jp] * f[k * 5 + jp];
+        S2[k * 5 + j] = s2;
+        if (milne) R0[k * 5 + j] += ((R)C.mu2[j] * s1r - s1p) * itau;
+      }
+    if (f3)
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        double gxf, gyf;
+        force_row(g3, F, g.site, ns, q * kL + l, &gxf, &gyf);
+        R0[q] += (R)(S.gx * gxf + S.gy * gyf);
+      }
+    R s0 = 0, s1 = 0, s2s = 0, s3 = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int k = q / 5;
+      const R sg = (R)C.sig[q];
+      const R feq = (R)a.Z * expf((sg * M * cu - ut * Eeq[k]) * invT);
+      const R uvg = ut - (R)C.sigi[q] * cu;
+      const R poly = al[k] * sg - be[k] * (R)C.sig2[q] - ga[k];
+      const R ru = rate * uvg;
+      R0[q] += feq * (ru - poly) - ru * f[q];
+      const R wuv2 = (R)C.wx2[q] * uvg * uvg;
+      s0 += wuv2 * R0[q];
+      s1 += wuv2 * ((R)4 * f[q] + S2[q]);
+      s2s += (R)C.w[q] * f[q];
+      s3 += (R)(scale * seedF[cix(q, l, g.site, ns)]) * S2[q];
+    }
+    sums[0] = s0;
+    sums[1] = s1;
+    sums[2] = s2s;
+    sums[3] = s3;
+  }
+  slice_sum<4>(sums, red, g);
+  const double nsum = sums[0], dsum = sums[1], wsum = sums[2];
+  const double beta = S.beta, Dd = wsum + beta * dsum, Xd = -beta * nsum / Dd;
+  const double Xb = scale * seedL[g.site] + sums[3];
+  const double nbd = -beta * Xb / Dd;
+  const double Db = -Xd * Xb / Dd;
+  const double betab = -nsum * Xb / Dd + Db * dsum;
+  const R nb = (R)nbd, wsb = (R)Db, dsb = (R)(beta * Db), X = (R)Xd;
+  // the slice's adjoint
+  R R0b[kQ], S2b[kQ], fb[kQ];
+  R cub = 0, Glb = 0, gub = 0, utb = 0, Mb = 0, invTb = 0, rateb = 0;
+  R alb[5] = {0, 0, 0, 0, 0}, beb[5] = {0, 0, 0, 0, 0}, gab[5] = {0, 0, 0, 0, 0}, Eeqb[5] = {0, 0, 0, 0, 0};
+  double g3xb = 0, g3yb = 0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int k = q / 5;
+    const R sg = (R)C.sig[q];
+    const R feq = (R)a.Z * expf((sg * M * cu - ut * Eeq[k]) * invT);
+    const R uv = ut - (R)C.sigi[q] * cu;
+    const R poly = al[k] * sg - be[k] * (R)C.sig2[q] - ga[k];
+    const R wuv2 = (R)C.wx2[q] * uv * uv;
+    const R Kb = (R)(scale * seedF[cix(q, l, g.site, ns)]);
+    R0b[q] = Kb + wuv2 * nb;
+    if (f3) {
+      double gxf, gyf;
+      force_row(g3, F, g.site, ns, q * kL + l, &gxf, &gyf);
+      g3xb += (double)R0b[q] * gxf;
+      g3yb += (double)R0b[q] * gyf;
+    }
+    S2b[q] = X * Kb + wuv2 * dsb;
+    const R ru = rate * uv;
+    fb[q] = (R)4 * wuv2 * dsb + (R)C.w[q] * wsb - ru * R0b[q];
+    const R uvb = (R)2 * (R)C.wx2[q] * uv * (((R)4 * f[q] + S2[q]) * dsb + R0[q] * nb) + rate * (feq - f[q]) * R0b[q];
+    rateb += uv * (feq - f[q]) * R0b[q];
+    const R feqb = (ru - poly) * R0b[q];
+    const R polyb = -feq * R0b[q];
+    alb[k] += sg * polyb;
+    beb[k] -= (R)C.sig2[q] * polyb;
+    gab[k] -= polyb;
+    const R e = feq * feqb;
+    Mb += e * sg * cu * invT;
+    cub += e * sg * M * invT;
+    invTb += e * (sg * M * cu - ut * Eeq[k]);
+    utb -= e * Eeq[k] * invT;
+    Eeqb[k] -= e * ut * invT;
+    utb += uvb;
+    cub -= (R)C.sigi[q] * uvb;
+  }
+  // transposed operators
+  {
+    const bool milne = a.metric == LB_METRIC_MILNE;
+    const R itau = (R)(1.0 / a.tau);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        R acc = 0;
+#pragma unroll
+        for (int kk = 0; kk < 5; ++kk) {
+          acc += (R)C.A2[kk * 5 + k] * S2b[kk * 5 + j];
+          if (milne) acc += (R)C.mu2[j] * (R)C.A1[kk * 5 + k] * R0b[kk * 5 + j] * itau;
+        }
+        if (milne)
+#pragma unroll
+          for (int jj = 0; jj < 5; ++jj) acc -= (R)C.Ath[jj * 5 + j] * R0b[k * 5 + jj] * itau;
+        fb[k * 5 + j] += acc;
+      }
+  }
+  R MTb = 0, Meqb = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const R c = (R)C.x[k] / Eeq[k];
+    MTb += alb[k] * Gl * ut * M * c;
+    Glb += alb[k] * MT * ut * M * c;
+    utb += alb[k] * MT * Gl * M * c;
+    Mb += alb[k] * MT * Gl * ut * c;
+    Eeqb[k] -= alb[k] * al[k] / Eeq[k];
+    MTb += beb[k] * Gl * cu * (R)C.inv_x[k] + gab[k] * gu * (R)C.inv_x[k];
+    Glb += beb[k] * MT * cu * (R)C.inv_x[k];
+    cub += beb[k] * MT * Gl * (R)C.inv_x[k];
+    gub += gab[k] * MT * (R)C.inv_x[k];
+    Meqb += Eeqb[k] * Meq / Eeq[k];
+    Mb += Eeqb[k] * M * (R)C.sh2[k] / Eeq[k];
+  }
+  if (f3) {
+    Glb = 0;
+    gub = 0;
+  }
+  double v[kRed] = {(double)utb,
+                    (double)cub * gm.cl + (double)gub * S.gx,
+                    (double)cub * gm.sl + (double)gub * S.gy,
+                    (double)Mb,
+                    (double)invTb,
+                    (double)MTb,
+                    (double)rateb,
+                    (double)Meqb,
+                    (double)Glb * gm.cl + (double)gub * S.u[1] + g3xb,
+                    (double)Glb * gm.sl + (double)gub * S.u[2] + g3yb};
+  slice_sum<kRed>(v, red, g);
+  if (l == 0) {
+    // the site's reverse chain, once (FP64): as adj_local_kernel
+    SiteLds& W = sd[g.sl];
+    const double utbd = v[0], uxb = v[1], uyb = v[2];
+    double Mbd = v[3], invTbd = v[4];
+    const double MTbd = v[5], ratebd = v[6], Meqbd = v[7], gxb = v[8], gyb = v[9];
+    Mbd += MTbd * W.invT;
+    invTbd += MTbd * W.M;
+    const double T = W.T, qv = W.q;
+    const double Tb = -invTbd * W.invT * W.invT + ratebd * a.inv_eta_hbarc / qv;
+    const double qb = -ratebd * W.rate / qv;
+    const double etab = -ratebd * W.rate * a.inv_eta_hbarc * kHbarC;
+    const double z = W.Meq / T;
+    const double uub = Tb * T + Meqbd * (W.dz * T + z * T) + betab * W.dbeta + qb * W.dq;
+    const double lamb = uub * W.du_dlam;
+    const double ub[3] = {utbd, uxb, uyb};
+    const double ul[3] = {W.u[0], -W.u[1], -W.u[2]};
+    const double gsg[3] = {1.0, -1.0, -1.0};
+    const double mm[3][3] = {{W.m[0], W.m[1], W.m[2]}, {W.m[1], W.m[3], W.m[4]}, {W.m[2], W.m[4], W.m[5]}};
+    const double al_ = ub[0] * W.u[0] + ub[1] * W.u[1] + ub[2] * W.u[2];
+    double rhs[3], Bt[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rhs[i] = ub[i] - al_ * ul[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Bt[j][i] = W.G * mm[i][j] * gsg[j] - (i == j ? W.lam : 0.0) + W.u[i] * ul[j];
+    const double det = Bt[0][0] * (Bt[1][1] * Bt[2][2] - Bt[1][2] * Bt[2][1]) -
+                       Bt[0][1] * (Bt[1][0] * Bt[2][2] - Bt[1][2] * Bt[2][0]) +
+                       Bt[0][2] * (Bt[1][0] * Bt[2][1] - Bt[1][1] * Bt[2][0]);
+    double w[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double Mx[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Mx[i][j] = (j == c) ? rhs[i] : Bt[i][j];
+      w[c] = (Mx[0][0] * (Mx[1][1] * Mx[2][2] - Mx[1][2] * Mx[2][1]) -
+              Mx[0][1] * (Mx[1][0] * Mx[2][2] - Mx[1][2] * Mx[2][0]) +
+              Mx[0][2] * (Mx[1][0] * Mx[2][1] - Mx[1][1] * Mx[2][0])) / det;
+    }
+    const double wu = w[0] * W.u[0] + w[1] * W.u[1] + w[2] * W.u[2] + lamb;
+    double mb[3][3], Gb = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const double tb_ = -w[i] * ul[j] + wu * ul[i] * ul[j];
+        mb[i][j] = W.G * tb_;
+        Gb += tb_ * mm[i][j];
+      }
+    Mbd += Gb * 4.0 * W.G / W.M;
+    W.mb[0] = mb[0][0];
+    W.mb[1] = mb[0][1] + mb[1][0];
+    W.mb[2] = mb[0][2] + mb[2][0];
+    W.mb[3] = mb[1][1];
+    W.mb[4] = mb[1][2] + mb[2][1];
+    W.mb[5] = mb[2][2];
+    if (g.valid) {
+      const double lb = Mbd * W.M;
+      outL[g.site] = accumulate ? outL[g.site] + lb : lb;
+      gb[g.site] = gxb;
+      gb[ns + g.site] = gyb;
+      eta_part[g.site] = accumulate ? eta_part[g.site] + etab : etab;
+    }
+  }
+  __syncthreads();
+  if (!g.valid) return;
+  const double c00 = S.mb[0], c01 = S.mb[1] * gm.cl + S.mb[2] * gm.sl;
+  const double c11 = S.mb[3] * gm.cl * gm.cl + S.mb[4] * gm.cl * gm.sl + S.mb[5] * gm.sl * gm.sl;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const size_t i = cix(q, l, g.site, ns);
+    const double v_ = (double)fb[q] + c00 * C.wx2[q] + c01 * C.wxs[q] + c11 * C.ws2[q];
+    outF[i] = accumulate ? outF[i] + v_ : v_;
+    Rb[i] = (double)R0b[q];
+  }
+}
+
+// adj_fwd_kernel for contexts whose forward runs in FP32: the same stage
+// with the node arithmetic in FP32, the site sums in FP64 and the site's
+// matching and EoS once per site (slice-0 thread, LDS), as adj_local32_kernel.
+__global__ __launch_bounds__(kAdjThreads) void adj_fwd32_kernel(const double* __restrict__ Fin,
+                                                                const double* __restrict__ Lin,
+                                                                const double* __restrict__ Fbase,
+                                                                const double* __restrict__ Lbase,
+                                                                double* __restrict__ Fout,
+                                                                double* __restrict__ Lout, int stage, const LC C,
+                                                                const double* __restrict__ g3, const EosTable tb,
+                                                                const StageArgs a, int* __restrict__ err) {
+  typedef float R;
+  __shared__ RedBuf red;
+  __shared__ double sdv[kSites][12];  // M, u[3], Meq, invT, MT, rate, beta, gx, gy, spare
+  const Lane g = lane_of(a);
+  const int ns = a.n_sites, l = g.l;
+  R f[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) f[q] = (R)Fin[cix(q, l, g.site, ns)];
+  const SliceGeom gm = slice_geom(C, a, l);
+  {
+    R q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      q0 += (R)C.wx2[q] * f[q];
+      q1 += (R)C.wxs[q] * f[q];
+      q2 += (R)C.ws2[q] * f[q];
+    }
+    double v[6] = {(double)q0, (double)q1 * gm.cl, (double)q1 * gm.sl, (double)q2 * gm.cl * gm.cl,
+                   (double)q2 * gm.cl * gm.sl, (double)q2 * gm.sl * gm.sl};
+    slice_sum<6>(v, red, g);
+    if (l == 0) {
+      const double M = exp(Lin[g.site]);
+      const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
+      const double tk[6] = {G * v[0], G * v[1], G * v[2], G * v[3], G * v[4], G * v[5]};
+      double u[3], lam;
+      const bool matched = landau3(tk, &lam, u);
+      EosAt E;
+      EosDer D;
+      const bool eos_ok = eos_cell(tb, lam, &E, &D);
+      bool finite = true;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
+      if (g.valid) {
+        if (!finite) flag(err, kErrNonfinite);
+        else if (!matched) flag(err, kErrMatch);
+        else if (!eos_ok) flag(err, kErrEos);
+      }
+      double* d = sdv[g.sl];
+      d[0] = M;
+      d[1] = u[0];
+      d[2] = u[1];
+      d[3] = u[2];
+      d[4] = E.M_eq;
+      d[5] = 1.0 / E.T;
+      d[6] = M / E.T;
+      d[7] = E.T * a.inv_eta_hbarc / E.q;
+      d[8] = E.beta;
+      const int x = g.x, y = g.y;
+      d[9] = (Lin[y * a.nx + wrap(x + 1, a.nx)] - Lin[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
+      d[10] = (Lin[wrap(y + 1, a.ny) * a.nx + x] - Lin[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
+    }
+    __syncthreads();
+  }
+  const double* d = sdv[g.sl];
+  const bool f3 = g3 != nullptr;
+  const R M = (R)d[0], ut = (R)d[1], ux = (R)d[2], uy = (R)d[3], Meq = (R)d[4], invT = (R)d[5], MT = (R)d[6];
+  const R rate = (R)d[7];
+  const double beta = d[8], gxd = d[9], gyd = d[10];
+  const R cl = (R)gm.cl, sl = (R)gm.sl;
+  const R cu = ux * cl + uy * sl;
+  const R Gl = f3 ? (R)0 : (R)(gxd * gm.cl + gyd * gm.sl);
+  const R gu = f3 ? (R)0 : (R)(gxd * d[2] + gyd * d[3]);
+  R R0[kQ], S2[kQ];
+  double sums[3];
+  {
+    const int x = g.x, y = g.y;
+    const int s_x1 = y * a.nx + wrap(x - gm.dxr, a.nx), s_x2 = y * a.nx + wrap(x - 2 * gm.dxr, a.nx);
+    const int s_y1 = wrap(y - gm.dyr, a.ny) * a.nx + x, s_y2 = wrap(y - 2 * gm.dyr, a.ny) * a.nx + x;
+    const R ax = (R)gm.ax, ay = (R)gm.ay;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const R tr = (R)3 * (ax + ay) * f[q] - (R)4 * ax * (R)Fin[cix(q, l, s_x1, ns)] +
+                   ax * (R)Fin[cix(q, l, s_x2, ns)] - (R)4 * ay * (R)Fin[cix(q, l, s_y1, ns)] +
+                   ay * (R)Fin[cix(q, l, s_y2, ns)];
+      R0[q] = -(R)C.sigi[q] * tr;
+    }
+    const bool milne = a.metric == LB_METRIC_MILNE;
+    const R itau = (R)(1.0 / a.tau);
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        R s2 = 0, s1r = 0, s1p = 0;
+#pragma unroll
+        for (int kp = 0; kp < 5; ++kp) {
+          s2 += (R)C.A2[k * 5 + kp] * f[kp * 5 + j];
+          s1r += (R)C.A1[k * 5 + kp] * f[kp * 5 + j];
+        }
+#pragma unroll
+        for (int jp = 0; jp < 5; ++jp) s1p += (R)C.Ath[j * 5 + jp] * f[k * 5 + jp];
+        S2[k * 5 + j] = s2;
+        if (milne) R0[k * 5 + j] += ((R)C.mu2[j] * s1r - s1p) * itau;
+      }
+    if (f3)
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        double gxf, gyf;
+        force_row(g3, Fin, g.site, ns, q * kL + l, &gxf, &gyf);
+        R0[q] += (R)(gxd * gxf + gyd * gyf);
+      }
+    R s0 = 0, s1 = 0, s2s = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const R Eeq = sqrtf(Meq * Meq + M * M * (R)C.sh2[k]);
+      const R al = MT * Gl * ut * M * (R)C.x[k] / Eeq, be = MT * Gl * cu * (R)C.inv_x[k], ga = MT * gu * (R)C.inv_x[k];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const int q = k * 5 + j;
+        const R sg = (R)C.sig[q];
+        const R feq = (R)a.Z * expf((sg * M * cu - ut * Eeq) * invT);
+        const R uvg = ut - (R)C.sigi[q] * cu;
+        const R poly = al * sg - be * (R)C.sig2[q] - ga;
+        const R ru = rate * uvg;
+        R0[q] += feq * (ru - poly) - ru * f[q];
+        const R wuv2 = (R)C.wx2[q] * uvg * uvg;
+        s0 += wuv2 * R0[q];
+        s1 += wuv2 * ((R)4 * f[q] + S2[q]);
+        s2s += (R)C.w[q] * f[q];
+      }
+    }
+    sums[0] = s0;
+    sums[1] = s1;
+    sums[2] = s2s;
+  }
+  slice_sum<3>(sums, red, g);
+  const double X = -beta * sums[0] / (sums[2] + beta * sums[1]);
+  if (!g.valid) return;
+  const R Xr = (R)X, dt = (R)a.dtau;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const R K = R0[q] + Xr * S2[q];
+    const size_t i = cix(q, l, g.site, ns);
+    Fout[i] = stage == 0 ? (double)(f[q] + dt * K) : (double)((R)0.5 * ((R)Fbase[i] + f[q]) + (R)0.5 * dt * K);
+  }
+  if (l == 0) {
+    const double lm = Lin[g.site];
+    Lout[g.site] = stage == 0 ? lm + a.dtau * X : 0.5 * (Lbase[g.site] + lm) + 0.5 * a.dtau * X;
+  }
+}
+
 // Transposed streaming stencil and transposed centred ln M gradient:
 // outF_n(s) += sum over the sites s' whose stencil reads s of the stencil
 // weight times Rb_n(s'); outL(s) += (gb_x(s - 1) - gb_x(s + 1) + ...)/(2 dx).
@@ -536,24 +1026,32 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const double* _
   }
 }
 
-// y += c x and, if z != nullptr, z *= cz, over n values.
-__global__ __launch_bounds__(256) void adj_axpy_kernel(double* __restrict__ y, const double* __restrict__ x,
-                                                       double c, double* __restrict__ z, double cz, size_t n) {
+// The Heun combination of the step's adjoint: with a1 the corrector's
+// adjoint of the predictor state and a the incoming adjoint of the new
+// state, a1 <- a1 + a/2 and a <- a/2 + a1 (new), over n values.
+__global__ __launch_bounds__(256) void adj_combine_kernel(double* __restrict__ a1, double* __restrict__ a, size_t n) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  y[i] += c * x[i];
-  if (z) z[i] *= cz;
+  const double t = a1[i] + 0.5 * a[i];
+  a1[i] = t;
+  a[i] = 0.5 * a[i] + t;
 }
 
-// *out += sum of v[0..n) (one block, fixed order: deterministic).
-__global__ __launch_bounds__(256) void adj_sum_kernel(const double* __restrict__ v, int n,
-                                                      double* __restrict__ out) {
-  __shared__ double part[256];
-  double acc = 0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
-  part[threadIdx.x] = acc;
+// *out += sum of v[0..n) (one block of 1024 threads, four accumulators per
+// thread, fixed order: deterministic).
+__global__ __launch_bounds__(1024) void adj_sum_kernel(const double* __restrict__ v, int n,
+                                                       double* __restrict__ out) {
+  __shared__ double part[1024];
+  double acc[4] = {0, 0, 0, 0};
+  int i = threadIdx.x;
+  for (; i + 3 * 1024 < n; i += 4 * 1024) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += v[i + k * 1024];
+  }
+  for (; i < n; i += 1024) acc[0] += v[i];
+  part[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = 512; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
     __syncthreads();
   }
@@ -610,19 +1108,27 @@ dim3 sites_grid(int n) { return dim3((unsigned)((n + kSites - 1) / kSites)); }
 
 hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const double* Fbase, const double* Lbase,
                                 double* Fout, double* Lout, int stage, const void* lc, const double* g3,
-                                const EosTable& tb, const StageArgs& a, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(adj_fwd_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout,
-                     Lout, stage, *static_cast<const LC*>(lc), g3, tb, a, err);
+                                const EosTable& tb, const StageArgs& a, int* err, hipStream_t s, int fp32_nodes) {
+  if (fp32_nodes)
+    hipLaunchKernelGGL(adj_fwd32_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase,
+                       Fout, Lout, stage, *static_cast<const LC*>(lc), g3, tb, a, err);
+  else
+    hipLaunchKernelGGL(adj_fwd_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout,
+                       Lout, stage, *static_cast<const LC*>(lc), g3, tb, a, err);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF, const double* seedL,
                           double scale, double* outF, double* outL, double* Rb, double* gb, double* eta_part,
                           int accumulate, const void* lc, const double* g3, const EosTable& tb,
-                          const StageArgs& a, int* err, hipStream_t s) {
+                          const StageArgs& a, int* err, hipStream_t s, int fp32_nodes) {
   const LC& C = *static_cast<const LC*>(lc);
-  hipLaunchKernelGGL(adj_local_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL, scale,
-                     outF, outL, Rb, gb, eta_part, accumulate, C, g3, tb, a, err);
+  if (fp32_nodes)
+    hipLaunchKernelGGL(adj_local32_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL,
+                       scale, outF, outL, Rb, gb, eta_part, accumulate, C, g3, tb, a, err);
+  else
+    hipLaunchKernelGGL(adj_local_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL, scale,
+                       outF, outL, Rb, gb, eta_part, accumulate, C, g3, tb, a, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(adj_gather_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Rb, gb, outF, outL, C, Lm,
@@ -630,14 +1136,14 @@ hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF
   return hipGetLastError();
 }
 
-hipError_t launch_adj_axpy(double* y, const double* x, double c, double* z, double cz, size_t n, hipStream_t s) {
+hipError_t launch_adj_combine(double* a1, double* a, size_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(adj_axpy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x, c, z, cz, n);
+  hipLaunchKernelGGL(adj_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a1, a, n);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_sum(const double* v, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(adj_sum_kernel, dim3(1), dim3(256), 0, s, v, n, out);
+  hipLaunchKernelGGL(adj_sum_kernel, dim3(1), dim3(1024), 0, s, v, n, out);
   return hipGetLastError();
 }
 

@@ -784,20 +784,23 @@ int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F,
   StageArgs a1 = a0;
   set_tau(&a1, c, tau_fm + dtau_fm);
   hipStream_t st = c->stream;
+  // an FP32 context's reverse sweep runs its node arithmetic in FP32
+  const int fp32 = c->p.precision == LB_FP32_FP64MATCH ? 1 : 0;
   // predictor state F* = F + dtau K(F)
-  hipError_t e = launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->g3, c->tb, a0, c->err, st);
+  hipError_t e =
+      launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->g3, c->tb, a0, c->err, st, fp32);
   // corrector F_new = (F + F*)/2 + dtau/2 K(F*): adjoint of F*, and F's share
   if (e == hipSuccess)
     e = launch_adj_rhs(B.Fp, B.Lp, d_adj_F, d_adj_lnM, 0.5 * dtau_fm, B.aF1, B.aL1, B.Rb, B.gb, B.eta, 0, &c->cd,
-                       c->g3, c->tb, a1, c->err, st);
-  if (e == hipSuccess) e = launch_adj_axpy(B.aF1, d_adj_F, 0.5, d_adj_F, 0.5, nF, st);
-  if (e == hipSuccess) e = launch_adj_axpy(B.aL1, d_adj_lnM, 0.5, d_adj_lnM, 0.5, ns, st);
+                       c->g3, c->tb, a1, c->err, st, fp32);
+  // the Heun combination: aF1 += adj_F/2 (the corrector's share through F*),
+  // adj_F <- adj_F/2 + aF1 (F's direct share and the predictor's identity)
+  if (e == hipSuccess) e = launch_adj_combine(B.aF1, d_adj_F, nF, st);
+  if (e == hipSuccess) e = launch_adj_combine(B.aL1, d_adj_lnM, ns, st);
   // predictor: F* = F + dtau K(F)
-  if (e == hipSuccess) e = launch_adj_axpy(d_adj_F, B.aF1, 1.0, nullptr, 1.0, nF, st);
-  if (e == hipSuccess) e = launch_adj_axpy(d_adj_lnM, B.aL1, 1.0, nullptr, 1.0, ns, st);
   if (e == hipSuccess)
     e = launch_adj_rhs(d_F, d_lnM, B.aF1, B.aL1, dtau_fm, d_adj_F, d_adj_lnM, B.Rb, B.gb, B.eta, 1, &c->cd, c->g3,
-                       c->tb, a0, c->err, st);
+                       c->tb, a0, c->err, st, fp32);
   if (e == hipSuccess) e = launch_adj_sum(B.eta, (int)ns, d_grad_eta_over_s, st);
   return e == hipSuccess ? LB_OK : hip_fail(e, "adjoint step");
 }

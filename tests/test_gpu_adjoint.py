@@ -322,3 +322,33 @@ def test_hot_spot_run_fp32_forward_gradient():
               run_objective(p64, gpu(e0n - h * d), eta, n, dtau, nodes)) / (2 * h)
     ad_dir = float((e0.grad * gpu(d)).sum())
     assert abs(ad_dir - fd_dir) <= 1e-3 * abs(fd_dir), (ad_dir, fd_dir)
+
+
+@pytest.mark.parametrize("force", [lb.LB_FORCE_FEQ, lb.LB_FORCE_WEAK3D])
+def test_fp32_context_adjoint_step_against_fp64(force):
+    # an FP32 context's reverse sweep (FP32 node arithmetic, FP64 site chain
+    # once per site) against the FP64 adjoint on the same state and seeds:
+    # the two differ by the FP32 rounding of the node arithmetic, ~1e-6 of
+    # the result (bar 2e-5 relative in the 2-norm, 1e-4 for eta/s)
+    nx, ny, dx, dtau, eta = 21, 17, 0.15, 0.01, 0.12
+    out = {}
+    rng = np.random.default_rng(41)
+    for prec in (lb.LB_FP64, lb.LB_FP32_FP64MATCH):
+        p = lb.make_params(nx, ny, dx, eta_over_s=eta, precision=prec, force_form=force)
+        ux, uy = wl.random_flow(nx, ny, 0.2, seed=5)
+        c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, 9)), gpu(ux), gpu(uy))
+        if prec == lb.LB_FP64:
+            c.step(4, 0.01)
+            F, L, tau = c.get_state()
+            aF = gpu(rng.standard_normal(tuple(F.shape)))
+            aL = gpu(rng.standard_normal(tuple(L.shape)))
+        bF, bL = aF.clone(), aL.clone()
+        g_eta = torch.zeros(1, dtype=torch.float64, device=DEV)
+        c.adjoint_step(tau, dtau, F, L, bF, bL, g_eta, c.adjoint_workspace())
+        assert c.status() == lb.LB_OK
+        out[prec] = (bF, bL, float(g_eta[0]))
+        c.close()
+    (F64, L64, e64), (F32, L32, e32) = out[lb.LB_FP64], out[lb.LB_FP32_FP64MATCH]
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    assert rel(F32, F64) < 2e-5 and rel(L32, L64) < 2e-5, (rel(F32, F64), rel(L32, L64))
+    assert abs(e32 - e64) <= 1e-4 * abs(e64), (e32, e64)
