@@ -109,24 +109,27 @@ hipError_t launch_force_columns(const void* cst64, double* G, hipStream_t s);
 // 3-D force, or nullptr for the force on F_eq.
 // One stage of the step: stage 0 Fout = Fin + dtau K(Fin), stage 1
 // Fout = (Fbase + Fin)/2 + dtau/2 K(Fin), ln M likewise; lc points to the
-// context's LatticeConst<double, 5, 5>.
+// context's LatticeConst<double, 5, 5> (host).  With lc32 (a device
+// LatticeConst<float, 5, 5>) the per-node arithmetic runs in FP32 (site
+// chain FP64, once per site).
 hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const double* Fbase, const double* Lbase,
                                 double* Fout, double* Lout, int stage, const void* lc, const double* g3,
                                 const EosTable& tb, const StageArgs& a, int* err, hipStream_t s,
-                                int fp32_nodes = 0);
+                                const void* lc32 = nullptr);
 // Reverse sweep of one right-hand side at (F, ln M), time a.tau, with
 // K_bar = scale seedF, X_bar = scale seedL, into (outF, outL) (written, or
 // added with accumulate = 1), plus the per-site eta/s adjoint; Rb
-// ([N][sites]) and gb ([2][sites]) are scratch.  fp32_nodes: the per-node
-// arithmetic in FP32 (site chain FP64, once per site).
+// ([N][sites] doubles; FP32 values with lc32) and gb ([2][sites]) are
+// scratch.  lc32 as for launch_adj_stage_fwd.  With combF (combL) the Heun
+// combination follows in the same pass: outF <- outF + combF/2, then
+// combF <- combF/2 + outF.
 hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF, const double* seedL,
                           double scale, double* outF, double* outL, double* Rb, double* gb, double* eta_part,
                           int accumulate, const void* lc, const double* g3, const EosTable& tb,
-                          const StageArgs& a, int* err, hipStream_t s, int fp32_nodes = 0);
+                          const StageArgs& a, int* err, hipStream_t s, const void* lc32 = nullptr,
+                          double* combF = nullptr, double* combL = nullptr);
 // *out += sum of v[0..n), deterministic order.
 hipError_t launch_adj_sum(const double* v, int n, double* out, hipStream_t s);
-// a1 <- a1 + a/2, then a <- a/2 + a1, n values (the step adjoint's Heun combination).
-hipError_t launch_adj_combine(double* a1, double* a, size_t n, hipStream_t s);
 // d/d e0 of (aF . F0 + aL . ln M0) for the initial state of lb_init.
 hipError_t launch_adj_init(const double* e0, const double* ux0, const double* uy0, const double* aF,
                            const double* aL, double* grad_e0, const void* lc, const EosTable& tb,

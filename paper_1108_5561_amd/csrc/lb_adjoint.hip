@@ -29,6 +29,8 @@
 // (adj_gather_kernel).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "../../include/lb.h"
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -92,10 +94,18 @@ struct SliceGeom {
   double cl, sl, ax, ay;
   int dxr, dyr;
 };
-__device__ __forceinline__ SliceGeom slice_geom(const LC& C, const StageArgs& a, int l) {
+template <typename LCT>
+__device__ __forceinline__ SliceGeom slice_geom(const LCT& C, const StageArgs& a, int l) {
   SliceGeom g;
-  g.cl = C.cosl[l];
-  g.sl = C.sinl[l];
+  // cos and sin of phi_l by selects over constant indices: no dynamic
+  // index into the kernel-argument struct (which would put it in scratch)
+  g.cl = C.cosl[0];
+  g.sl = C.sinl[0];
+#pragma unroll
+  for (int i = 1; i < kL; ++i) {
+    g.cl = l == i ? C.cosl[i] : g.cl;
+    g.sl = l == i ? C.sinl[i] : g.sl;
+  }
   g.dxr = (g.cl > 0.0) ? 1 : ((g.cl < 0.0) ? -1 : 0);
   g.dyr = (g.sl > 0.0) ? 1 : ((g.sl < 0.0) ? -1 : 0);
   g.ax = fabs(g.cl) * a.inv2dx;
@@ -492,13 +502,18 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
 }
 
 // The reverse sweep of adj_local_kernel for contexts whose forward runs in
-// FP32: the same arithmetic with the per-node arrays (slice values, R0, S2,
-// their adjoints) in FP32, the site sums reduced in FP64, and the per-site
-// FP64 chain (moments -> Landau matching -> EoS, and its reverse through
-// the implicit-function adjoints) done once per site, by the thread of
-// slice 0, and handed to the site's other seven threads through LDS.  With
-// FP32 arrays the seven slice arrays fit the register file (the FP64 form
-// spills), and three of the block's four waves skip the FP64 chain.
+// FP32: the same arithmetic with the node values in FP32, the site sums
+// reduced in FP64 and the per-site FP64 chain (moments -> Landau matching ->
+// EoS, and its reverse through the implicit-function adjoints) done once
+// per site, by the thread of slice 0, and handed to the site's other seven
+// threads through LDS.  Only F and its adjoint are held per node: the
+// forward values R0 and S2 of a node are evaluated again where the reverse
+// sweep needs them (the stencil neighbours come from cache), and the
+// adjoints of the operators S1 and S2 are scattered into the adjoint of F
+// as each node's R0b and S2b become known, so the register footprint
+// allows several waves per SIMD.  The lattice constants come in FP32
+// (LCf); R0b goes out in FP32 (Rb).
+using LCf = LatticeConst<float, 5, 5>;
 struct SiteLds {
   double m[6];  // sum w F V^a V^b: tau tau, tau x, tau y, xx, xy, yy
   double M, G, lam, u[3];
@@ -508,144 +523,237 @@ struct SiteLds {
   double mb[6];  // the moments' adjoint: 00, 01 + 10, 02 + 20, 11, 12 + 21, 22
 };
 
+// The slice's share of the moments (eq. (emtnew)), summed over the slices
+// in FP64, and the site's Landau matching and EoS by the slice-0 thread.
+__device__ __forceinline__ void site_chain32(const float f[kQ], const double* __restrict__ Lm, const Lane& g,
+                                             const LCf& C, double cl, double sl, const EosTable& tb,
+                                             const StageArgs& a, RedBuf& red, SiteLds* sd,
+                                             int* __restrict__ err) {
+  float q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    q0 += C.wx2[q] * f[q];
+    q1 += C.wxs[q] * f[q];
+    q2 += C.ws2[q] * f[q];
+  }
+  double v[6] = {(double)q0, (double)q1 * cl, (double)q1 * sl, (double)q2 * cl * cl, (double)q2 * cl * sl,
+                 (double)q2 * sl * sl};
+  slice_sum<6>(v, red, g);
+  if (g.l == 0) {
+    SiteLds& S = sd[g.sl];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) S.m[i] = v[i];
+    S.M = exp(Lm[g.site]);
+    S.G = S.M * S.M * S.M * S.M * (1.0 / (2.0 * kPi * kPi));
+    const double tk[6] = {S.G * v[0], S.G * v[1], S.G * v[2], S.G * v[3], S.G * v[4], S.G * v[5]};
+    double u[3], lam;
+    const bool matched = landau3(tk, &lam, u);
+    EosAt E;
+    EosDer D;
+    const bool eos_ok = eos_cell(tb, lam, &E, &D);
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
+    if (g.valid) {
+      if (!finite) flag(err, kErrNonfinite);
+      else if (!matched) flag(err, kErrMatch);
+      else if (!eos_ok) flag(err, kErrEos);
+    }
+    S.lam = lam;
+    S.u[0] = u[0];
+    S.u[1] = u[1];
+    S.u[2] = u[2];
+    S.T = E.T;
+    S.Meq = E.M_eq;
+    S.beta = E.beta;
+    S.q = E.q;
+    S.invT = 1.0 / E.T;
+    S.MT = S.M * S.invT;
+    S.rate = E.T * a.inv_eta_hbarc / E.q;
+    S.du_dlam = D.du_dlam;
+    S.dz = D.dz;
+    S.dbeta = D.dbeta;
+    S.dq = D.dq;
+    const int x = g.x, y = g.y;
+    S.gx = (Lm[y * a.nx + wrap(x + 1, a.nx)] - Lm[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
+    S.gy = (Lm[wrap(y + 1, a.ny) * a.nx + x] - Lm[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
+  }
+  __syncthreads();
+}
+
+// Addressing of the FP32 kernels: node n = q 8 + l of the canonical layout
+// lies in the plane of q (base + q 8 ns, the same for the whole block) at
+// the lane's byte offset (l ns + site) sizeof(T); with ns below 2^26 the
+// offset fits 32 bits, so each access is a uniform base and one 32-bit lane
+// offset rather than a 64-bit address per node.
+template <typename T>
+__device__ __forceinline__ T* qplane(T* base, int q, int ns) {
+  return base + (size_t)(q * kL) * (size_t)ns;
+}
+__device__ __forceinline__ double ld8(const double* plane, uint32_t off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(plane) + off);
+}
+__device__ __forceinline__ double& at8(double* plane, uint32_t off) {
+  return *reinterpret_cast<double*>(reinterpret_cast<char*>(plane) + off);
+}
+__device__ __forceinline__ float& at4(float* plane, uint32_t off) {
+  return *reinterpret_cast<float*>(reinterpret_cast<char*>(plane) + off);
+}
+__device__ __forceinline__ uint32_t lane_off8(int l, int site, int ns) {
+  return ((uint32_t)l * (uint32_t)ns + (uint32_t)site) * 8u;
+}
+
+// Per-slice FP32 view of the site quantities and of the slice geometry
+// (with the byte offsets of the site and of its upwind stencil neighbours).
+struct Slice32 {
+  float ut, M, Meq, invT, MT, rate, cu, Gl, gu, ax, ay, itau;
+  uint32_t o_own, o_x1, o_x2, o_y1, o_y2;
+};
+__device__ __forceinline__ Slice32 slice32(const SiteLds& S, const Lane& g, const SliceGeom& gm, bool f3,
+                                           const StageArgs& a) {
+  Slice32 o;
+  o.ut = (float)S.u[0];
+  o.M = (float)S.M;
+  o.Meq = (float)S.Meq;
+  o.invT = (float)S.invT;
+  o.MT = (float)S.MT;
+  o.rate = (float)S.rate;
+  o.cu = (float)S.u[1] * (float)gm.cl + (float)S.u[2] * (float)gm.sl;
+  o.Gl = f3 ? 0.0f : (float)(S.gx * gm.cl + S.gy * gm.sl);
+  o.gu = f3 ? 0.0f : (float)(S.gx * S.u[1] + S.gy * S.u[2]);
+  o.ax = (float)gm.ax;
+  o.ay = (float)gm.ay;
+  // S1/tau for the Milne metric, none for Minkowski
+  o.itau = a.metric == LB_METRIC_MILNE ? (float)(1.0 / a.tau) : 0.0f;
+  const int x = g.x, y = g.y, ns = a.n_sites;
+  o.o_own = lane_off8(g.l, g.site, ns);
+  o.o_x1 = lane_off8(g.l, y * a.nx + wrap(x - gm.dxr, a.nx), ns);
+  o.o_x2 = lane_off8(g.l, y * a.nx + wrap(x - 2 * gm.dxr, a.nx), ns);
+  o.o_y1 = lane_off8(g.l, wrap(y - gm.dyr, a.ny) * a.nx + x, ns);
+  o.o_y2 = lane_off8(g.l, wrap(y - 2 * gm.dyr, a.ny) * a.nx + x, ns);
+  return o;
+}
+
+// The equilibrium's radial factors at radial node k: E_eq, and the force
+// polynomial's coefficients alpha, beta, gamma.
+struct Radial32 {
+  float Eeq, al, be, ga;
+};
+__device__ __forceinline__ Radial32 radial32(const Slice32& o, const LCf& C, int k) {
+  Radial32 r;
+  r.Eeq = sqrtf(o.Meq * o.Meq + o.M * o.M * C.sh2[k]);
+  r.al = o.MT * o.Gl * o.ut * o.M * C.x[k] / r.Eeq;
+  r.be = o.MT * o.Gl * o.cu * C.inv_x[k];
+  r.ga = o.MT * o.gu * C.inv_x[k];
+  return r;
+}
+
+// The part of R0 of node q = k 5 + j that does not depend on the site's
+// matching: streaming (from the upwind neighbours) and S1/tau.
+template <int k, int j>
+__device__ __forceinline__ float node_r0a(const double* __restrict__ F, const float f[kQ], const Slice32& o,
+                                          const LCf& C, int ns) {
+  constexpr int q = k * 5 + j;
+  const double* P = qplane(F, q, ns);
+  const float tr = 3.0f * (o.ax + o.ay) * f[q] - 4.0f * o.ax * (float)ld8(P, o.o_x1) +
+                   o.ax * (float)ld8(P, o.o_x2) - 4.0f * o.ay * (float)ld8(P, o.o_y1) +
+                   o.ay * (float)ld8(P, o.o_y2);
+  float s1r = 0, s1p = 0;
+#pragma unroll
+  for (int kp = 0; kp < 5; ++kp) s1r += C.A1[k * 5 + kp] * f[kp * 5 + j];
+#pragma unroll
+  for (int jp = 0; jp < 5; ++jp) s1p += C.Ath[j * 5 + jp] * f[k * 5 + jp];
+  return -C.sigi[q] * tr + (C.mu2[j] * s1r - s1p) * o.itau;
+}
+
+// S2 of node q = k 5 + j.
+template <int k, int j>
+__device__ __forceinline__ float node_s2(const float f[kQ], const LCf& C) {
+  float a2 = 0;
+#pragma unroll
+  for (int kp = 0; kp < 5; ++kp) a2 += C.A2[k * 5 + kp] * f[kp * 5 + j];
+  return a2;
+}
+
+// An opaque copy: the compiler cannot prove it equal to its input, so
+// values computed from it are evaluated again rather than kept live from
+// an earlier evaluation (register pressure over recomputation).
+__device__ __forceinline__ float opaque(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Unrolled loop over the nodes of a slice, k-major, with compile-time k, j.
+template <int k, int j, typename Fn>
+__device__ __forceinline__ void for_nodes(Fn&& fn) {
+  fn(std::integral_constant<int, k>{}, std::integral_constant<int, j>{});
+  if constexpr (j < 4) for_nodes<k, j + 1>(fn);
+  else if constexpr (k < 4) for_nodes<k + 1, 0>(fn);
+}
+
 __global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
     const double* __restrict__ F, const double* __restrict__ Lm, const double* __restrict__ seedF,
     const double* __restrict__ seedL, double scale, double* __restrict__ outF, double* __restrict__ outL,
-    double* __restrict__ Rb, double* __restrict__ gb, double* __restrict__ eta_part, int accumulate,
-    const LC C, const double* __restrict__ g3, const EosTable tb, const StageArgs a, int* __restrict__ err) {
-  typedef float R;
+    float* __restrict__ Rb, double* __restrict__ gb, double* __restrict__ eta_part, int accumulate,
+    const LCf* __restrict__ Cg, const double* __restrict__ g3, const EosTable tb, const StageArgs a,
+    int* __restrict__ err) {
+  const LCf& C = *Cg;
   __shared__ RedBuf red;
   __shared__ SiteLds sd[kSites];
   const Lane g = lane_of(a);
   const int ns = a.n_sites, l = g.l;
-  R f[kQ];
+  float f[kQ];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) f[q] = (R)F[cix(q, l, g.site, ns)];
+  for (int q = 0; q < kQ; ++q) f[q] = (float)ld8(qplane(F, q, ns), lane_off8(l, g.site, ns));
   const SliceGeom gm = slice_geom(C, a, l);
-  // moments (eq. (emtnew)), reduced over the slices in FP64
-  {
-    R q0 = 0, q1 = 0, q2 = 0;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      q0 += (R)C.wx2[q] * f[q];
-      q1 += (R)C.wxs[q] * f[q];
-      q2 += (R)C.ws2[q] * f[q];
-    }
-    double v[6] = {(double)q0, (double)q1 * gm.cl, (double)q1 * gm.sl, (double)q2 * gm.cl * gm.cl,
-                   (double)q2 * gm.cl * gm.sl, (double)q2 * gm.sl * gm.sl};
-    slice_sum<6>(v, red, g);
-    if (l == 0) {
-      // the site's forward chain, once: Landau matching (eq. (sanity)) and EoS
-      SiteLds& S = sd[g.sl];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) S.m[i] = v[i];
-      S.M = exp(Lm[g.site]);
-      S.G = S.M * S.M * S.M * S.M * (1.0 / (2.0 * kPi * kPi));
-      const double tk[6] = {S.G * v[0], S.G * v[1], S.G * v[2], S.G * v[3], S.G * v[4], S.G * v[5]};
-      double u[3], lam;
-      const bool matched = landau3(tk, &lam, u);
-      EosAt E;
-      EosDer D;
-      const bool eos_ok = eos_cell(tb, lam, &E, &D);
-      bool finite = true;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
-      if (g.valid) {
-        if (!finite) flag(err, kErrNonfinite);
-        else if (!matched) flag(err, kErrMatch);
-        else if (!eos_ok) flag(err, kErrEos);
-      }
-      S.lam = lam;
-      S.u[0] = u[0];
-      S.u[1] = u[1];
-      S.u[2] = u[2];
-      S.T = E.T;
-      S.Meq = E.M_eq;
-      S.beta = E.beta;
-      S.q = E.q;
-      S.invT = 1.0 / E.T;
-      S.MT = S.M * S.invT;
-      S.rate = E.T * a.inv_eta_hbarc / E.q;
-      S.du_dlam = D.du_dlam;
-      S.dz = D.dz;
-      S.dbeta = D.dbeta;
-      S.dq = D.dq;
-      const int x = g.x, y = g.y;
-      S.gx = (Lm[y * a.nx + wrap(x + 1, a.nx)] - Lm[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
-      S.gy = (Lm[wrap(y + 1, a.ny) * a.nx + x] - Lm[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
-    }
-    __syncthreads();
-  }
+  site_chain32(f, Lm, g, C, gm.cl, gm.sl, tb, a, red, sd, err);
   const SiteLds& S = sd[g.sl];
   const bool f3 = g3 != nullptr;
-  const R ut = (R)S.u[0], ux = (R)S.u[1], uy = (R)S.u[2], M = (R)S.M, Meq = (R)S.Meq;
-  const R invT = (R)S.invT, MT = (R)S.MT, rate = (R)S.rate;
-  const R cl = (R)gm.cl, sl = (R)gm.sl;
-  const R cu = ux * cl + uy * sl;
-  const R Gl = f3 ? (R)0 : (R)(S.gx * gm.cl + S.gy * gm.sl);
-  const R gu = f3 ? (R)0 : (R)(S.gx * S.u[1] + S.gy * S.u[2]);
-  R Eeq[5], al[5], be[5], ga[5];
+  const Slice32 o = slice32(S, g, gm, f3, a);
+  const float sc = (float)scale, Zf = (float)a.Z;
+  // what both sweeps read from memory, once: the part of R0 without the
+  // collision and the equilibrium (streaming, S1/tau, the 3-D force) and
+  // the seed K_bar
+  float r0a[kQ], Kb[kQ];
+  for_nodes<0, 0>([&](auto kc, auto jc) {
+    constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
+    r0a[q] = node_r0a<k, j>(F, f, o, C, ns);
+    Kb[q] = sc * (float)ld8(qplane(seedF, q, ns), o.o_own);
+  });
+  if (f3)
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    Eeq[k] = sqrtf(Meq * Meq + M * M * (R)C.sh2[k]);
-    al[k] = MT * Gl * ut * M * (R)C.x[k] / Eeq[k];
-    be[k] = MT * Gl * cu * (R)C.inv_x[k];
-    ga[k] = MT * gu * (R)C.inv_x[k];
-  }
-  // forward right-hand side of the slice: R0, S2 and the three site sums
-  R R0[kQ], S2[kQ];
+    for (int q = 0; q < kQ; ++q) {
+      double gxf, gyf;
+      force_row(g3, F, g.site, ns, q * kL + l, &gxf, &gyf);
+      r0a[q] += (float)(S.gx * gxf + S.gy * gyf);
+    }
+  // forward right-hand side of the slice, node by node: the three site
+  // sums of the mass equation and the seed's projection on S2
   double sums[4];
   {
-    const int x = g.x, y = g.y;
-    const int s_x1 = y * a.nx + wrap(x - gm.dxr, a.nx), s_x2 = y * a.nx + wrap(x - 2 * gm.dxr, a.nx);
-    const int s_y1 = wrap(y - gm.dyr, a.ny) * a.nx + x, s_y2 = wrap(y - 2 * gm.dyr, a.ny) * a.nx + x;
-    const R ax = (R)gm.ax, ay = (R)gm.ay;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const R tr = (R)3 * (ax + ay) * f[q] - (R)4 * ax * (R)F[cix(q, l, s_x1, ns)] + ax * (R)F[cix(q, l, s_x2, ns)] -
-                   (R)4 * ay * (R)F[cix(q, l, s_y1, ns)] + ay * (R)F[cix(q, l, s_y2, ns)];
-      R0[q] = -(R)C.sigi[q] * tr;
-    }
-    const bool milne = a.metric == LB_METRIC_MILNE;
-    const R itau = (R)(1.0 / a.tau);
-#pragma unroll
-    for (int k = 0; k < 5; ++k)
-#pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        R s2 = 0, s1r = 0, s1p = 0;
-#pragma unroll
-        for (int kp = 0; kp < 5; ++kp) {
-          s2 += (R)C.A2[k * 5 + kp] * f[kp * 5 + j];
-          s1r += (R)C.A1[k * 5 + kp] * f[kp * 5 + j];
-        }
-#pragma unroll
-        for (int jp = 0; jp < 5; ++jp) s1p += (R)C.Ath[j * 5 + jp] * f[k * 5 + jp];
-        S2[k * 5 + j] = s2;
-        if (milne) R0[k * 5 + j] += ((R)C.mu2[j] * s1r - s1p) * itau;
-      }
-    if (f3)
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        double gxf, gyf;
-        force_row(g3, F, g.site, ns, q * kL + l, &gxf, &gyf);
-        R0[q] += (R)(S.gx * gxf + S.gy * gyf);
-      }
-    R s0 = 0, s1 = 0, s2s = 0, s3 = 0;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const int k = q / 5;
-      const R sg = (R)C.sig[q];
-      const R feq = (R)a.Z * expf((sg * M * cu - ut * Eeq[k]) * invT);
-      const R uvg = ut - (R)C.sigi[q] * cu;
-      const R poly = al[k] * sg - be[k] * (R)C.sig2[q] - ga[k];
-      const R ru = rate * uvg;
-      R0[q] += feq * (ru - poly) - ru * f[q];
-      const R wuv2 = (R)C.wx2[q] * uvg * uvg;
-      s0 += wuv2 * R0[q];
-      s1 += wuv2 * ((R)4 * f[q] + S2[q]);
-      s2s += (R)C.w[q] * f[q];
-      s3 += (R)(scale * seedF[cix(q, l, g.site, ns)]) * S2[q];
-    }
+    float s0 = 0, s1 = 0, s2s = 0, s3 = 0;
+    Radial32 rk;
+    for_nodes<0, 0>([&](auto kc, auto jc) {
+      constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
+      if constexpr (j == 0) rk = radial32(o, C, k);
+      const float s2 = node_s2<k, j>(f, C);
+      const float sg = C.sig[q];
+      const float feq = Zf * __expf((sg * o.M * o.cu - o.ut * rk.Eeq) * o.invT);
+      const float uvg = o.ut - C.sigi[q] * o.cu;
+      const float poly = rk.al * sg - rk.be * C.sig2[q] - rk.ga;
+      const float ru = o.rate * uvg;
+      const float r0 = r0a[q] + feq * (ru - poly) - ru * f[q];
+      const float wuv2 = C.wx2[q] * uvg * uvg;
+      s0 += wuv2 * r0;
+      s1 += wuv2 * (4.0f * f[q] + s2);
+      s2s += C.w[q] * f[q];
+      s3 += Kb[q] * s2;
+    });
     sums[0] = s0;
     sums[1] = s1;
     sums[2] = s2s;
@@ -658,87 +766,102 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
   const double nbd = -beta * Xb / Dd;
   const double Db = -Xd * Xb / Dd;
   const double betab = -nsum * Xb / Dd + Db * dsum;
-  const R nb = (R)nbd, wsb = (R)Db, dsb = (R)(beta * Db), X = (R)Xd;
-  // the slice's adjoint
-  R R0b[kQ], S2b[kQ], fb[kQ];
-  R cub = 0, Glb = 0, gub = 0, utb = 0, Mb = 0, invTb = 0, rateb = 0;
-  R alb[5] = {0, 0, 0, 0, 0}, beb[5] = {0, 0, 0, 0, 0}, gab[5] = {0, 0, 0, 0, 0}, Eeqb[5] = {0, 0, 0, 0, 0};
-  double g3xb = 0, g3yb = 0;
+  const float nb = (float)nbd, wsb = (float)Db, dsb = (float)(beta * Db), X = (float)Xd;
+  // the slice's adjoint, node by node; S2, F_eq and R0 are evaluated again
+  // (from opaque copies of f, the site scalars and the constants) rather
+  // than held from the forward sweep
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int k = q / 5;
-    const R sg = (R)C.sig[q];
-    const R feq = (R)a.Z * expf((sg * M * cu - ut * Eeq[k]) * invT);
-    const R uv = ut - (R)C.sigi[q] * cu;
-    const R poly = al[k] * sg - be[k] * (R)C.sig2[q] - ga[k];
-    const R wuv2 = (R)C.wx2[q] * uv * uv;
-    const R Kb = (R)(scale * seedF[cix(q, l, g.site, ns)]);
-    R0b[q] = Kb + wuv2 * nb;
-    if (f3) {
+  for (int q = 0; q < kQ; ++q) f[q] = opaque(f[q]);
+  Slice32 o2 = o;
+  o2.ut = opaque(o.ut);
+  o2.M = opaque(o.M);
+  o2.Meq = opaque(o.Meq);
+  o2.cu = opaque(o.cu);
+  o2.invT = opaque(o.invT);
+  o2.rate = opaque(o.rate);
+  const LCf& C2 = *opaque(Cg);
+  float R0b[kQ], S2b[kQ], fb[kQ];
+  float cub = 0, Glb = 0, gub = 0, utb = 0, Mb = 0, invTb = 0, rateb = 0, MTb = 0, Meqb = 0;
+  {
+    Radial32 rk;
+    float alb = 0, beb = 0, gab = 0, Eeqb = 0;
+    for_nodes<0, 0>([&](auto kc, auto jc) {
+      constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
+      if constexpr (j == 0) {
+        rk = radial32(o2, C2, k);
+        alb = beb = gab = Eeqb = 0.0f;
+      }
+      const float s2 = node_s2<k, j>(f, C2);
+      const float sg = C2.sig[q];
+      const float feq = Zf * __expf((sg * o2.M * o2.cu - o2.ut * rk.Eeq) * o2.invT);
+      const float uv = o2.ut - C2.sigi[q] * o2.cu;
+      const float poly = rk.al * sg - rk.be * C2.sig2[q] - rk.ga;
+      const float ru = o2.rate * uv;
+      const float r0 = r0a[q] + feq * (ru - poly) - ru * f[q];
+      const float wuv2 = C2.wx2[q] * uv * uv;
+      R0b[q] = Kb[q] + wuv2 * nb;
+      S2b[q] = X * Kb[q] + wuv2 * dsb;
+      fb[q] = 4.0f * wuv2 * dsb + C2.w[q] * wsb - ru * R0b[q];
+      const float uvb = 2.0f * C2.wx2[q] * uv * ((4.0f * f[q] + s2) * dsb + r0 * nb) + o2.rate * (feq - f[q]) * R0b[q];
+      rateb += uv * (feq - f[q]) * R0b[q];
+      const float feqb = (ru - poly) * R0b[q];
+      const float polyb = -feq * R0b[q];
+      alb += sg * polyb;
+      beb -= C2.sig2[q] * polyb;
+      gab -= polyb;
+      const float e = feq * feqb;
+      Mb += e * sg * o2.cu * o2.invT;
+      cub += e * sg * o2.M * o2.invT;
+      invTb += e * (sg * o2.M * o2.cu - o2.ut * rk.Eeq);
+      utb -= e * rk.Eeq * o2.invT;
+      Eeqb -= e * o2.ut * o2.invT;
+      utb += uvb;
+      cub -= C2.sigi[q] * uvb;
+      if constexpr (j == 4) {
+        // radial node k done: the adjoints of its alpha, beta, gamma and E_eq
+        const float c = C2.x[k] / rk.Eeq;
+        MTb += alb * o2.Gl * o2.ut * o2.M * c;
+        Glb += alb * o2.MT * o2.ut * o2.M * c;
+        utb += alb * o2.MT * o2.Gl * o2.M * c;
+        Mb += alb * o2.MT * o2.Gl * o2.ut * c;
+        Eeqb -= alb * rk.al / rk.Eeq;
+        MTb += beb * o2.Gl * o2.cu * C2.inv_x[k] + gab * o2.gu * C2.inv_x[k];
+        Glb += beb * o2.MT * o2.cu * C2.inv_x[k];
+        cub += beb * o2.MT * o2.Gl * C2.inv_x[k];
+        gub += gab * o2.MT * C2.inv_x[k];
+        Meqb += Eeqb * o2.Meq / rk.Eeq;
+        Mb += Eeqb * o2.M * C2.sh2[k] / rk.Eeq;
+      }
+    });
+  }
+  double g3xb = 0, g3yb = 0;
+  if (f3) {
+    Glb = 0;
+    gub = 0;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
       double gxf, gyf;
       force_row(g3, F, g.site, ns, q * kL + l, &gxf, &gyf);
       g3xb += (double)R0b[q] * gxf;
       g3yb += (double)R0b[q] * gyf;
     }
-    S2b[q] = X * Kb + wuv2 * dsb;
-    const R ru = rate * uv;
-    fb[q] = (R)4 * wuv2 * dsb + (R)C.w[q] * wsb - ru * R0b[q];
-    const R uvb = (R)2 * (R)C.wx2[q] * uv * (((R)4 * f[q] + S2[q]) * dsb + R0[q] * nb) + rate * (feq - f[q]) * R0b[q];
-    rateb += uv * (feq - f[q]) * R0b[q];
-    const R feqb = (ru - poly) * R0b[q];
-    const R polyb = -feq * R0b[q];
-    alb[k] += sg * polyb;
-    beb[k] -= (R)C.sig2[q] * polyb;
-    gab[k] -= polyb;
-    const R e = feq * feqb;
-    Mb += e * sg * cu * invT;
-    cub += e * sg * M * invT;
-    invTb += e * (sg * M * cu - ut * Eeq[k]);
-    utb -= e * Eeq[k] * invT;
-    Eeqb[k] -= e * ut * invT;
-    utb += uvb;
-    cub -= (R)C.sigi[q] * uvb;
   }
-  // transposed operators
-  {
-    const bool milne = a.metric == LB_METRIC_MILNE;
-    const R itau = (R)(1.0 / a.tau);
+  if (g.valid)
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
+    for (int q = 0; q < kQ; ++q) at4(qplane(Rb, q, ns), o.o_own / 2) = R0b[q];
+  // transposed operators: S2^T S2b and (S1/tau)^T R0b
 #pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        R acc = 0;
+  for (int k = 0; k < 5; ++k)
 #pragma unroll
-        for (int kk = 0; kk < 5; ++kk) {
-          acc += (R)C.A2[kk * 5 + k] * S2b[kk * 5 + j];
-          if (milne) acc += (R)C.mu2[j] * (R)C.A1[kk * 5 + k] * R0b[kk * 5 + j] * itau;
-        }
-        if (milne)
+    for (int j = 0; j < 5; ++j) {
+      float acc = 0;
 #pragma unroll
-          for (int jj = 0; jj < 5; ++jj) acc -= (R)C.Ath[jj * 5 + j] * R0b[k * 5 + jj] * itau;
-        fb[k * 5 + j] += acc;
-      }
-  }
-  R MTb = 0, Meqb = 0;
+      for (int kk = 0; kk < 5; ++kk)
+        acc += C2.A2[kk * 5 + k] * S2b[kk * 5 + j] + C2.mu2[j] * C2.A1[kk * 5 + k] * R0b[kk * 5 + j] * o2.itau;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const R c = (R)C.x[k] / Eeq[k];
-    MTb += alb[k] * Gl * ut * M * c;
-    Glb += alb[k] * MT * ut * M * c;
-    utb += alb[k] * MT * Gl * M * c;
-    Mb += alb[k] * MT * Gl * ut * c;
-    Eeqb[k] -= alb[k] * al[k] / Eeq[k];
-    MTb += beb[k] * Gl * cu * (R)C.inv_x[k] + gab[k] * gu * (R)C.inv_x[k];
-    Glb += beb[k] * MT * cu * (R)C.inv_x[k];
-    cub += beb[k] * MT * Gl * (R)C.inv_x[k];
-    gub += gab[k] * MT * (R)C.inv_x[k];
-    Meqb += Eeqb[k] * Meq / Eeq[k];
-    Mb += Eeqb[k] * M * (R)C.sh2[k] / Eeq[k];
-  }
-  if (f3) {
-    Glb = 0;
-    gub = 0;
-  }
+      for (int jj = 0; jj < 5; ++jj) acc -= C2.Ath[jj * 5 + j] * R0b[k * 5 + jj] * o2.itau;
+      fb[k * 5 + j] += acc;
+    }
   double v[kRed] = {(double)utb,
                     (double)cub * gm.cl + (double)gub * S.gx,
                     (double)cub * gm.sl + (double)gub * S.gy,
@@ -819,162 +942,93 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
   }
   __syncthreads();
   if (!g.valid) return;
-  const double c00 = S.mb[0], c01 = S.mb[1] * gm.cl + S.mb[2] * gm.sl;
-  const double c11 = S.mb[3] * gm.cl * gm.cl + S.mb[4] * gm.cl * gm.sl + S.mb[5] * gm.sl * gm.sl;
+  const float c00 = (float)S.mb[0], c01 = (float)(S.mb[1] * gm.cl + S.mb[2] * gm.sl);
+  const float c11 = (float)(S.mb[3] * gm.cl * gm.cl + S.mb[4] * gm.cl * gm.sl + S.mb[5] * gm.sl * gm.sl);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const size_t i = cix(q, l, g.site, ns);
-    const double v_ = (double)fb[q] + c00 * C.wx2[q] + c01 * C.wxs[q] + c11 * C.ws2[q];
-    outF[i] = accumulate ? outF[i] + v_ : v_;
-    Rb[i] = (double)R0b[q];
+    double& dst = at8(qplane(outF, q, ns), o.o_own);
+    const double v_ = (double)(fb[q] + c00 * C.wx2[q] + c01 * C.wxs[q] + c11 * C.ws2[q]);
+    dst = accumulate ? dst + v_ : v_;
   }
 }
 
 // adj_fwd_kernel for contexts whose forward runs in FP32: the same stage
 // with the node arithmetic in FP32, the site sums in FP64 and the site's
-// matching and EoS once per site (slice-0 thread, LDS), as adj_local32_kernel.
+// matching and EoS once per site (slice-0 thread, LDS), as
+// adj_local32_kernel.  R0 is held per node across the site sum; S2 is
+// evaluated again for the update.
 __global__ __launch_bounds__(kAdjThreads) void adj_fwd32_kernel(const double* __restrict__ Fin,
                                                                 const double* __restrict__ Lin,
                                                                 const double* __restrict__ Fbase,
                                                                 const double* __restrict__ Lbase,
                                                                 double* __restrict__ Fout,
-                                                                double* __restrict__ Lout, int stage, const LC C,
+                                                                double* __restrict__ Lout, int stage,
+                                                                const LCf* __restrict__ Cg,
                                                                 const double* __restrict__ g3, const EosTable tb,
                                                                 const StageArgs a, int* __restrict__ err) {
-  typedef float R;
+  const LCf& C = *Cg;
   __shared__ RedBuf red;
-  __shared__ double sdv[kSites][12];  // M, u[3], Meq, invT, MT, rate, beta, gx, gy, spare
+  __shared__ SiteLds sd[kSites];
   const Lane g = lane_of(a);
   const int ns = a.n_sites, l = g.l;
-  R f[kQ];
+  float f[kQ];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) f[q] = (R)Fin[cix(q, l, g.site, ns)];
+  for (int q = 0; q < kQ; ++q) f[q] = (float)ld8(qplane(Fin, q, ns), lane_off8(l, g.site, ns));
   const SliceGeom gm = slice_geom(C, a, l);
-  {
-    R q0 = 0, q1 = 0, q2 = 0;
+  site_chain32(f, Lin, g, C, gm.cl, gm.sl, tb, a, red, sd, err);
+  const SiteLds& S = sd[g.sl];
+  const bool f3 = g3 != nullptr;
+  const Slice32 o = slice32(S, g, gm, f3, a);
+  const float Zf = (float)a.Z;
+  float R0[kQ];
+  for_nodes<0, 0>([&](auto kc, auto jc) {
+    constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
+    R0[q] = node_r0a<k, j>(Fin, f, o, C, ns);
+  });
+  if (f3)
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-      q0 += (R)C.wx2[q] * f[q];
-      q1 += (R)C.wxs[q] * f[q];
-      q2 += (R)C.ws2[q] * f[q];
+      double gxf, gyf;
+      force_row(g3, Fin, g.site, ns, q * kL + l, &gxf, &gyf);
+      R0[q] += (float)(S.gx * gxf + S.gy * gyf);
     }
-    double v[6] = {(double)q0, (double)q1 * gm.cl, (double)q1 * gm.sl, (double)q2 * gm.cl * gm.cl,
-                   (double)q2 * gm.cl * gm.sl, (double)q2 * gm.sl * gm.sl};
-    slice_sum<6>(v, red, g);
-    if (l == 0) {
-      const double M = exp(Lin[g.site]);
-      const double G = M * M * M * M * (1.0 / (2.0 * kPi * kPi));
-      const double tk[6] = {G * v[0], G * v[1], G * v[2], G * v[3], G * v[4], G * v[5]};
-      double u[3], lam;
-      const bool matched = landau3(tk, &lam, u);
-      EosAt E;
-      EosDer D;
-      const bool eos_ok = eos_cell(tb, lam, &E, &D);
-      bool finite = true;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
-      if (g.valid) {
-        if (!finite) flag(err, kErrNonfinite);
-        else if (!matched) flag(err, kErrMatch);
-        else if (!eos_ok) flag(err, kErrEos);
-      }
-      double* d = sdv[g.sl];
-      d[0] = M;
-      d[1] = u[0];
-      d[2] = u[1];
-      d[3] = u[2];
-      d[4] = E.M_eq;
-      d[5] = 1.0 / E.T;
-      d[6] = M / E.T;
-      d[7] = E.T * a.inv_eta_hbarc / E.q;
-      d[8] = E.beta;
-      const int x = g.x, y = g.y;
-      d[9] = (Lin[y * a.nx + wrap(x + 1, a.nx)] - Lin[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
-      d[10] = (Lin[wrap(y + 1, a.ny) * a.nx + x] - Lin[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
-    }
-    __syncthreads();
-  }
-  const double* d = sdv[g.sl];
-  const bool f3 = g3 != nullptr;
-  const R M = (R)d[0], ut = (R)d[1], ux = (R)d[2], uy = (R)d[3], Meq = (R)d[4], invT = (R)d[5], MT = (R)d[6];
-  const R rate = (R)d[7];
-  const double beta = d[8], gxd = d[9], gyd = d[10];
-  const R cl = (R)gm.cl, sl = (R)gm.sl;
-  const R cu = ux * cl + uy * sl;
-  const R Gl = f3 ? (R)0 : (R)(gxd * gm.cl + gyd * gm.sl);
-  const R gu = f3 ? (R)0 : (R)(gxd * d[2] + gyd * d[3]);
-  R R0[kQ], S2[kQ];
   double sums[3];
   {
-    const int x = g.x, y = g.y;
-    const int s_x1 = y * a.nx + wrap(x - gm.dxr, a.nx), s_x2 = y * a.nx + wrap(x - 2 * gm.dxr, a.nx);
-    const int s_y1 = wrap(y - gm.dyr, a.ny) * a.nx + x, s_y2 = wrap(y - 2 * gm.dyr, a.ny) * a.nx + x;
-    const R ax = (R)gm.ax, ay = (R)gm.ay;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const R tr = (R)3 * (ax + ay) * f[q] - (R)4 * ax * (R)Fin[cix(q, l, s_x1, ns)] +
-                   ax * (R)Fin[cix(q, l, s_x2, ns)] - (R)4 * ay * (R)Fin[cix(q, l, s_y1, ns)] +
-                   ay * (R)Fin[cix(q, l, s_y2, ns)];
-      R0[q] = -(R)C.sigi[q] * tr;
-    }
-    const bool milne = a.metric == LB_METRIC_MILNE;
-    const R itau = (R)(1.0 / a.tau);
-#pragma unroll
-    for (int k = 0; k < 5; ++k)
-#pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        R s2 = 0, s1r = 0, s1p = 0;
-#pragma unroll
-        for (int kp = 0; kp < 5; ++kp) {
-          s2 += (R)C.A2[k * 5 + kp] * f[kp * 5 + j];
-          s1r += (R)C.A1[k * 5 + kp] * f[kp * 5 + j];
-        }
-#pragma unroll
-        for (int jp = 0; jp < 5; ++jp) s1p += (R)C.Ath[j * 5 + jp] * f[k * 5 + jp];
-        S2[k * 5 + j] = s2;
-        if (milne) R0[k * 5 + j] += ((R)C.mu2[j] * s1r - s1p) * itau;
-      }
-    if (f3)
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        double gxf, gyf;
-        force_row(g3, Fin, g.site, ns, q * kL + l, &gxf, &gyf);
-        R0[q] += (R)(gxd * gxf + gyd * gyf);
-      }
-    R s0 = 0, s1 = 0, s2s = 0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const R Eeq = sqrtf(Meq * Meq + M * M * (R)C.sh2[k]);
-      const R al = MT * Gl * ut * M * (R)C.x[k] / Eeq, be = MT * Gl * cu * (R)C.inv_x[k], ga = MT * gu * (R)C.inv_x[k];
-#pragma unroll
-      for (int j = 0; j < 5; ++j) {
-        const int q = k * 5 + j;
-        const R sg = (R)C.sig[q];
-        const R feq = (R)a.Z * expf((sg * M * cu - ut * Eeq) * invT);
-        const R uvg = ut - (R)C.sigi[q] * cu;
-        const R poly = al * sg - be * (R)C.sig2[q] - ga;
-        const R ru = rate * uvg;
-        R0[q] += feq * (ru - poly) - ru * f[q];
-        const R wuv2 = (R)C.wx2[q] * uvg * uvg;
-        s0 += wuv2 * R0[q];
-        s1 += wuv2 * ((R)4 * f[q] + S2[q]);
-        s2s += (R)C.w[q] * f[q];
-      }
-    }
+    float s0 = 0, s1 = 0, s2s = 0;
+    Radial32 rk;
+    for_nodes<0, 0>([&](auto kc, auto jc) {
+      constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
+      if constexpr (j == 0) rk = radial32(o, C, k);
+      const float s2 = node_s2<k, j>(f, C);
+      const float sg = C.sig[q];
+      const float feq = Zf * __expf((sg * o.M * o.cu - o.ut * rk.Eeq) * o.invT);
+      const float uvg = o.ut - C.sigi[q] * o.cu;
+      const float poly = rk.al * sg - rk.be * C.sig2[q] - rk.ga;
+      const float ru = o.rate * uvg;
+      R0[q] += feq * (ru - poly) - ru * f[q];
+      const float wuv2 = C.wx2[q] * uvg * uvg;
+      s0 += wuv2 * R0[q];
+      s1 += wuv2 * (4.0f * f[q] + s2);
+      s2s += C.w[q] * f[q];
+    });
     sums[0] = s0;
     sums[1] = s1;
     sums[2] = s2s;
   }
   slice_sum<3>(sums, red, g);
-  const double X = -beta * sums[0] / (sums[2] + beta * sums[1]);
+  const double X = -S.beta * sums[0] / (sums[2] + S.beta * sums[1]);
   if (!g.valid) return;
-  const R Xr = (R)X, dt = (R)a.dtau;
+  const float Xr = (float)X, dt = (float)a.dtau;
+  for_nodes<0, 0>([&](auto kc, auto jc) {
+    constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
+    float s2 = 0;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const R K = R0[q] + Xr * S2[q];
-    const size_t i = cix(q, l, g.site, ns);
-    Fout[i] = stage == 0 ? (double)(f[q] + dt * K) : (double)((R)0.5 * ((R)Fbase[i] + f[q]) + (R)0.5 * dt * K);
-  }
+    for (int kp = 0; kp < 5; ++kp) s2 += C.A2[k * 5 + kp] * f[kp * 5 + j];
+    const float K = R0[q] + Xr * s2;
+    double& dst = at8(qplane(Fout, q, ns), o.o_own);
+    dst = stage == 0 ? (double)(f[q] + dt * K)
+                     : (double)(0.5f * ((float)ld8(qplane(Fbase, q, ns), o.o_own) + f[q]) + 0.5f * dt * K);
+  });
   if (l == 0) {
     const double lm = Lin[g.site];
     Lout[g.site] = stage == 0 ? lm + a.dtau * X : 0.5 * (Lbase[g.site] + lm) + 0.5 * a.dtau * X;
@@ -986,55 +1040,66 @@ __global__ __launch_bounds__(kAdjThreads) void adj_fwd32_kernel(const double* __
 // weight times Rb_n(s'); outL(s) += (gb_x(s - 1) - gb_x(s + 1) + ...)/(2 dx).
 // With the weak-form 3-D force (g3) also the transposed force:
 // outF_m(s) += sum_n Rb_n(s) (g_x G_x[n][m] + g_y G_y[n][m]) at the site's
-// own ln M gradient (Lm, the state of the right-hand side).
-__global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const double* __restrict__ Rb,
+// own ln M gradient (Lm, the state of the right-hand side).  With combF
+// (and combL) the Heun combination of the step's adjoint follows on the
+// finished values: outF <- outF + combF/2, then combF <- combF/2 + outF
+// (with outF the corrector's adjoint of the predictor state and combF the
+// incoming adjoint of the new state).
+template <typename RB>
+__global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const RB* __restrict__ Rb,
                                                                  const double* __restrict__ gb,
                                                                  double* __restrict__ outF,
                                                                  double* __restrict__ outL, const LC C,
                                                                  const double* __restrict__ Lm,
                                                                  const double* __restrict__ g3,
-                                                                 const StageArgs a) {
+                                                                 const StageArgs a, double* __restrict__ combF,
+                                                                 double* __restrict__ combL) {
   const Lane g = lane_of(a);
   if (!g.valid) return;
   const int x = g.x, y = g.y, ns = a.n_sites, l = g.l, site = g.site;
   const SliceGeom gm = slice_geom(C, a, l);
   const int s1 = y * a.nx + wrap(x + gm.dxr, a.nx), s2 = y * a.nx + wrap(x + 2 * gm.dxr, a.nx);
   const int s3 = wrap(y + gm.dyr, a.ny) * a.nx + x, s4 = wrap(y + 2 * gm.dyr, a.ny) * a.nx + x;
-  for (int q = 0; q < kQ; ++q) {
-    const double t = 3.0 * (gm.ax + gm.ay) * Rb[cix(q, l, site, ns)] - 4.0 * gm.ax * Rb[cix(q, l, s1, ns)] +
-                     gm.ax * Rb[cix(q, l, s2, ns)] - 4.0 * gm.ay * Rb[cix(q, l, s3, ns)] +
-                     gm.ay * Rb[cix(q, l, s4, ns)];
-    outF[cix(q, l, site, ns)] -= C.sigi[q] * t;
-  }
+  double gx = 0, gy = 0;
   if (g3) {
-    const double gx = (Lm[y * a.nx + wrap(x + 1, a.nx)] - Lm[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
-    const double gy = (Lm[wrap(y + 1, a.ny) * a.nx + x] - Lm[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
-    const double* gxc = g3;
-    const double* gyc = g3 + (size_t)kN * kN;
-    for (int q = 0; q < kQ; ++q) {
+    gx = (Lm[y * a.nx + wrap(x + 1, a.nx)] - Lm[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
+    gy = (Lm[wrap(y + 1, a.ny) * a.nx + x] - Lm[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
+  }
+  for (int q = 0; q < kQ; ++q) {
+    const size_t i = cix(q, l, site, ns);
+    const double t = 3.0 * (gm.ax + gm.ay) * (double)Rb[i] - 4.0 * gm.ax * (double)Rb[cix(q, l, s1, ns)] +
+                     gm.ax * (double)Rb[cix(q, l, s2, ns)] - 4.0 * gm.ay * (double)Rb[cix(q, l, s3, ns)] +
+                     gm.ay * (double)Rb[cix(q, l, s4, ns)];
+    double v = outF[i] - C.sigi[q] * t;
+    if (g3) {
+      const double* gxc = g3;
+      const double* gyc = g3 + (size_t)kN * kN;
       const int m = q * kL + l;
       double acc = 0;
       for (int n = 0; n < kN; ++n)
-        acc += Rb[(size_t)n * ns + site] * (gx * gxc[(size_t)n * kN + m] + gy * gyc[(size_t)n * kN + m]);
-      outF[cix(q, l, site, ns)] += acc;
+        acc += (double)Rb[(size_t)n * ns + site] * (gx * gxc[(size_t)n * kN + m] + gy * gyc[(size_t)n * kN + m]);
+      v += acc;
+    }
+    if (combF) {
+      const double c = combF[i], t1 = v + 0.5 * c;
+      outF[i] = t1;
+      combF[i] = 0.5 * c + t1;
+    } else {
+      outF[i] = v;
     }
   }
   if (l == 0) {
     const int xm = y * a.nx + wrap(x - 1, a.nx), xp = y * a.nx + wrap(x + 1, a.nx);
     const int ym = wrap(y - 1, a.ny) * a.nx + x, yp = wrap(y + 1, a.ny) * a.nx + x;
-    outL[site] += (gb[xm] - gb[xp] + gb[ns + ym] - gb[ns + yp]) * a.inv2dx;
+    const double v = outL[site] + (gb[xm] - gb[xp] + gb[ns + ym] - gb[ns + yp]) * a.inv2dx;
+    if (combL) {
+      const double c = combL[site], t1 = v + 0.5 * c;
+      outL[site] = t1;
+      combL[site] = 0.5 * c + t1;
+    } else {
+      outL[site] = v;
+    }
   }
-}
-
-// The Heun combination of the step's adjoint: with a1 the corrector's
-// adjoint of the predictor state and a the incoming adjoint of the new
-// state, a1 <- a1 + a/2 and a <- a/2 + a1 (new), over n values.
-__global__ __launch_bounds__(256) void adj_combine_kernel(double* __restrict__ a1, double* __restrict__ a, size_t n) {
-  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const double t = a1[i] + 0.5 * a[i];
-  a1[i] = t;
-  a[i] = 0.5 * a[i] + t;
 }
 
 // *out += sum of v[0..n) (one block of 1024 threads, four accumulators per
@@ -1108,10 +1173,10 @@ dim3 sites_grid(int n) { return dim3((unsigned)((n + kSites - 1) / kSites)); }
 
 hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const double* Fbase, const double* Lbase,
                                 double* Fout, double* Lout, int stage, const void* lc, const double* g3,
-                                const EosTable& tb, const StageArgs& a, int* err, hipStream_t s, int fp32_nodes) {
-  if (fp32_nodes)
+                                const EosTable& tb, const StageArgs& a, int* err, hipStream_t s, const void* lc32) {
+  if (lc32)
     hipLaunchKernelGGL(adj_fwd32_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase,
-                       Fout, Lout, stage, *static_cast<const LC*>(lc), g3, tb, a, err);
+                       Fout, Lout, stage, static_cast<const LCf*>(lc32), g3, tb, a, err);
   else
     hipLaunchKernelGGL(adj_fwd_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout,
                        Lout, stage, *static_cast<const LC*>(lc), g3, tb, a, err);
@@ -1121,24 +1186,26 @@ hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const doub
 hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF, const double* seedL,
                           double scale, double* outF, double* outL, double* Rb, double* gb, double* eta_part,
                           int accumulate, const void* lc, const double* g3, const EosTable& tb,
-                          const StageArgs& a, int* err, hipStream_t s, int fp32_nodes) {
+                          const StageArgs& a, int* err, hipStream_t s, const void* lc32, double* combF,
+                          double* combL) {
   const LC& C = *static_cast<const LC*>(lc);
-  if (fp32_nodes)
+  if (lc32) {
+    float* Rb32 = reinterpret_cast<float*>(Rb);
     hipLaunchKernelGGL(adj_local32_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL,
-                       scale, outF, outL, Rb, gb, eta_part, accumulate, C, g3, tb, a, err);
-  else
-    hipLaunchKernelGGL(adj_local_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL, scale,
-                       outF, outL, Rb, gb, eta_part, accumulate, C, g3, tb, a, err);
+                       scale, outF, outL, Rb32, gb, eta_part, accumulate, static_cast<const LCf*>(lc32), g3, tb, a,
+                       err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(adj_gather_kernel<float>, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Rb32, gb, outF,
+                       outL, C, Lm, g3, a, combF, combL);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(adj_local_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL, scale,
+                     outF, outL, Rb, gb, eta_part, accumulate, C, g3, tb, a, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adj_gather_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Rb, gb, outF, outL, C, Lm,
-                     g3, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_combine(double* a1, double* a, size_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(adj_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a1, a, n);
+  hipLaunchKernelGGL(adj_gather_kernel<double>, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Rb, gb, outF, outL,
+                     C, Lm, g3, a, combF, combL);
   return hipGetLastError();
 }
 

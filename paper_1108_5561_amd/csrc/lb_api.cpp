@@ -32,6 +32,7 @@ struct lb_ctx {
   HostLattice lat;
   LatticeConst<float, 5, 5> cf{};
   LatticeConst<double, 5, 5> cd{};
+  void* lc32 = nullptr;  // device copy of cf (the adjoint's FP32 kernels)
   double* g3 = nullptr;  // dense weak-form force operators [2][N][N] (3-D force only)
   double tau = 0;
   bool initialised = false;
@@ -57,7 +58,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t F[3], lnM[3], sc[3], cst, tbd, pts, inv_ek, inv_ee, gpts, err, cst64, g3, total;
+  size_t F[3], lnM[3], sc[3], cst, tbd, pts, inv_ek, inv_ee, gpts, err, lc32, cst64, g3, total;
 };
 
 std::string validate(const lb_params* p) {
@@ -157,6 +158,8 @@ Layout layout(const lb_params* p) {
   off = align_up(off + (size_t)kGPoints * kGFields * 8);
   L.err = off;
   off = align_up(off + 256);
+  L.lc32 = off;  // FP32 lattice constants of the adjoint's FP32 kernels
+  off = align_up(off + sizeof(LatticeConst<float, 5, 5>));
   // the weak-form 3-D force: FP64 stage constants and the dense operators
   // [2][N][N] of the FP64 adjoint
   L.cst64 = L.g3 = 0;
@@ -582,6 +585,11 @@ int lb_init(lb_ctx** out, const lb_params* p, void* d_workspace, size_t ws_bytes
       return hip_fail(e, "upload of lattice constants");
     }
   } else {
+    c->lc32 = c->ws + L.lc32;
+    if ((e = hipMemcpy(c->lc32, &c->cf, sizeof(c->cf), hipMemcpyHostToDevice)) != hipSuccess) {
+      delete c;
+      return hip_fail(e, "upload of lattice constants");
+    }
     StageConst<float> sf;
     StageConst<double> sd;
     if (p->precision == LB_FP32_FP64MATCH) {
@@ -779,28 +787,29 @@ int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F,
   if (rc != LB_OK) return rc;
   if (!d_F || !d_lnM || !d_adj_F || !d_adj_lnM || !d_grad_eta_over_s)
     return fail(LB_E_ARG, "state, adjoint or gradient pointer is NULL");
-  const size_t ns = (size_t)c->p.nx * c->p.ny, nF = ns * (size_t)(c->lat.nxi * c->lat.nth * 2 * c->lat.nphi);
+  const size_t ns = (size_t)c->p.nx * c->p.ny;
   const StageArgs a0 = stage_args(c, tau_fm, dtau_fm);
   StageArgs a1 = a0;
   set_tau(&a1, c, tau_fm + dtau_fm);
   hipStream_t st = c->stream;
-  // an FP32 context's reverse sweep runs its node arithmetic in FP32
-  const int fp32 = c->p.precision == LB_FP32_FP64MATCH ? 1 : 0;
+  // an FP32 context's reverse sweep runs its node arithmetic in FP32 (with
+  // the FP32 lattice constants)
+  const bool fp32 = c->p.precision == LB_FP32_FP64MATCH;
   // predictor state F* = F + dtau K(F)
   hipError_t e =
-      launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->g3, c->tb, a0, c->err, st, fp32);
+      launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->g3, c->tb, a0, c->err, st,
+                           fp32 ? c->lc32 : nullptr);
   // corrector F_new = (F + F*)/2 + dtau/2 K(F*): adjoint of F*, and F's share
+  // with the Heun combination in the same pass: aF1 += adj_F/2 (the
+  // corrector's share through F*), adj_F <- adj_F/2 + aF1 (F's direct share
+  // and the predictor's identity)
   if (e == hipSuccess)
     e = launch_adj_rhs(B.Fp, B.Lp, d_adj_F, d_adj_lnM, 0.5 * dtau_fm, B.aF1, B.aL1, B.Rb, B.gb, B.eta, 0, &c->cd,
-                       c->g3, c->tb, a1, c->err, st, fp32);
-  // the Heun combination: aF1 += adj_F/2 (the corrector's share through F*),
-  // adj_F <- adj_F/2 + aF1 (F's direct share and the predictor's identity)
-  if (e == hipSuccess) e = launch_adj_combine(B.aF1, d_adj_F, nF, st);
-  if (e == hipSuccess) e = launch_adj_combine(B.aL1, d_adj_lnM, ns, st);
+                       c->g3, c->tb, a1, c->err, st, fp32 ? c->lc32 : nullptr, d_adj_F, d_adj_lnM);
   // predictor: F* = F + dtau K(F)
   if (e == hipSuccess)
     e = launch_adj_rhs(d_F, d_lnM, B.aF1, B.aL1, dtau_fm, d_adj_F, d_adj_lnM, B.Rb, B.gb, B.eta, 1, &c->cd, c->g3,
-                       c->tb, a0, c->err, st, fp32);
+                       c->tb, a0, c->err, st, fp32 ? c->lc32 : nullptr);
   if (e == hipSuccess) e = launch_adj_sum(B.eta, (int)ns, d_grad_eta_over_s, st);
   return e == hipSuccess ? LB_OK : hip_fail(e, "adjoint step");
 }
