@@ -682,11 +682,6 @@ __device__ __forceinline__ float opaque(float x) {
   asm volatile("" : "+v"(x));
   return x;
 }
-template <typename T>
-__device__ __forceinline__ const T* opaque(const T* p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
 
 // Unrolled loop over the nodes of a slice, k-major, with compile-time k, j.
 template <int k, int j, typename Fn>
@@ -696,7 +691,10 @@ __device__ __forceinline__ void for_nodes(Fn&& fn) {
   else if constexpr (k < 4) for_nodes<k + 1, 0>(fn);
 }
 
-__global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
+// Two waves per SIMD for the force on F_eq (a few registers spill, faster
+// than one wave with none); one for the weak-form 3-D force.
+template <bool kF3>
+__global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
     const double* __restrict__ F, const double* __restrict__ Lm, const double* __restrict__ seedF,
     const double* __restrict__ seedL, double scale, double* __restrict__ outF, double* __restrict__ outL,
     float* __restrict__ Rb, double* __restrict__ gb, double* __restrict__ eta_part, int accumulate,
@@ -713,7 +711,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
   const SliceGeom gm = slice_geom(C, a, l);
   site_chain32(f, Lm, g, C, gm.cl, gm.sl, tb, a, red, sd, err);
   const SiteLds& S = sd[g.sl];
-  const bool f3 = g3 != nullptr;
+  constexpr bool f3 = kF3;  // g3 != nullptr
   const Slice32 o = slice32(S, g, gm, f3, a);
   const float sc = (float)scale, Zf = (float)a.Z;
   // what both sweeps read from memory, once: the part of R0 without the
@@ -768,8 +766,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
   const double betab = -nsum * Xb / Dd + Db * dsum;
   const float nb = (float)nbd, wsb = (float)Db, dsb = (float)(beta * Db), X = (float)Xd;
   // the slice's adjoint, node by node; S2, F_eq and R0 are evaluated again
-  // (from opaque copies of f, the site scalars and the constants) rather
-  // than held from the forward sweep
+  // (from opaque copies of f and of the site scalars) rather than held from
+  // the forward sweep
 #pragma unroll
   for (int q = 0; q < kQ; ++q) f[q] = opaque(f[q]);
   Slice32 o2 = o;
@@ -779,7 +777,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
   o2.cu = opaque(o.cu);
   o2.invT = opaque(o.invT);
   o2.rate = opaque(o.rate);
-  const LCf& C2 = *opaque(Cg);
+  const LCf& C2 = C;
   float R0b[kQ], S2b[kQ], fb[kQ];
   float cub = 0, Glb = 0, gub = 0, utb = 0, Mb = 0, invTb = 0, rateb = 0, MTb = 0, Meqb = 0;
   {
@@ -957,6 +955,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_local32_kernel(
 // matching and EoS once per site (slice-0 thread, LDS), as
 // adj_local32_kernel.  R0 is held per node across the site sum; S2 is
 // evaluated again for the update.
+template <bool kF3>
 __global__ __launch_bounds__(kAdjThreads) void adj_fwd32_kernel(const double* __restrict__ Fin,
                                                                 const double* __restrict__ Lin,
                                                                 const double* __restrict__ Fbase,
@@ -977,7 +976,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_fwd32_kernel(const double* __
   const SliceGeom gm = slice_geom(C, a, l);
   site_chain32(f, Lin, g, C, gm.cl, gm.sl, tb, a, red, sd, err);
   const SiteLds& S = sd[g.sl];
-  const bool f3 = g3 != nullptr;
+  constexpr bool f3 = kF3;  // g3 != nullptr
   const Slice32 o = slice32(S, g, gm, f3, a);
   const float Zf = (float)a.Z;
   float R0[kQ];
@@ -1045,7 +1044,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_fwd32_kernel(const double* __
 // finished values: outF <- outF + combF/2, then combF <- combF/2 + outF
 // (with outF the corrector's adjoint of the predictor state and combF the
 // incoming adjoint of the new state).
-template <typename RB>
+template <typename RB, bool kG3, bool kComb>
 __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const RB* __restrict__ Rb,
                                                                  const double* __restrict__ gb,
                                                                  double* __restrict__ outF,
@@ -1058,41 +1057,53 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const RB* __res
   if (!g.valid) return;
   const int x = g.x, y = g.y, ns = a.n_sites, l = g.l, site = g.site;
   const SliceGeom gm = slice_geom(C, a, l);
-  const int s1 = y * a.nx + wrap(x + gm.dxr, a.nx), s2 = y * a.nx + wrap(x + 2 * gm.dxr, a.nx);
-  const int s3 = wrap(y + gm.dyr, a.ny) * a.nx + x, s4 = wrap(y + 2 * gm.dyr, a.ny) * a.nx + x;
+  // byte offsets in a node plane (see qplane): the site and the sites whose
+  // upwind stencil reads it
+  constexpr uint32_t e = sizeof(RB);
+  const uint32_t o0 = ((uint32_t)l * ns + site) * e;
+  const uint32_t o1 = ((uint32_t)l * ns + y * a.nx + wrap(x + gm.dxr, a.nx)) * e;
+  const uint32_t o2 = ((uint32_t)l * ns + y * a.nx + wrap(x + 2 * gm.dxr, a.nx)) * e;
+  const uint32_t o3 = ((uint32_t)l * ns + wrap(y + gm.dyr, a.ny) * a.nx + x) * e;
+  const uint32_t o4 = ((uint32_t)l * ns + wrap(y + 2 * gm.dyr, a.ny) * a.nx + x) * e;
+  const uint32_t od = ((uint32_t)l * ns + site) * 8u;
+  auto rb = [&](int q, uint32_t off) {
+    return (double)*reinterpret_cast<const RB*>(reinterpret_cast<const char*>(qplane(Rb, q, ns)) + off);
+  };
   double gx = 0, gy = 0;
-  if (g3) {
+  if constexpr (kG3) {
     gx = (Lm[y * a.nx + wrap(x + 1, a.nx)] - Lm[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
     gy = (Lm[wrap(y + 1, a.ny) * a.nx + x] - Lm[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
   }
+#pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    const size_t i = cix(q, l, site, ns);
-    const double t = 3.0 * (gm.ax + gm.ay) * (double)Rb[i] - 4.0 * gm.ax * (double)Rb[cix(q, l, s1, ns)] +
-                     gm.ax * (double)Rb[cix(q, l, s2, ns)] - 4.0 * gm.ay * (double)Rb[cix(q, l, s3, ns)] +
-                     gm.ay * (double)Rb[cix(q, l, s4, ns)];
-    double v = outF[i] - C.sigi[q] * t;
-    if (g3) {
+    const double t = 3.0 * (gm.ax + gm.ay) * rb(q, o0) - 4.0 * gm.ax * rb(q, o1) + gm.ax * rb(q, o2) -
+                     4.0 * gm.ay * rb(q, o3) + gm.ay * rb(q, o4);
+    double& dst = at8(qplane(outF, q, ns), od);
+    double v = dst - C.sigi[q] * t;
+    if constexpr (kG3) {
       const double* gxc = g3;
       const double* gyc = g3 + (size_t)kN * kN;
       const int m = q * kL + l;
       double acc = 0;
+#pragma unroll 1
       for (int n = 0; n < kN; ++n)
         acc += (double)Rb[(size_t)n * ns + site] * (gx * gxc[(size_t)n * kN + m] + gy * gyc[(size_t)n * kN + m]);
       v += acc;
     }
-    if (combF) {
-      const double c = combF[i], t1 = v + 0.5 * c;
-      outF[i] = t1;
-      combF[i] = 0.5 * c + t1;
+    if constexpr (kComb) {
+      double& cv = at8(qplane(combF, q, ns), od);
+      const double c = cv, t1 = v + 0.5 * c;
+      dst = t1;
+      cv = 0.5 * c + t1;
     } else {
-      outF[i] = v;
+      dst = v;
     }
   }
   if (l == 0) {
     const int xm = y * a.nx + wrap(x - 1, a.nx), xp = y * a.nx + wrap(x + 1, a.nx);
     const int ym = wrap(y - 1, a.ny) * a.nx + x, yp = wrap(y + 1, a.ny) * a.nx + x;
     const double v = outL[site] + (gb[xm] - gb[xp] + gb[ns + ym] - gb[ns + yp]) * a.inv2dx;
-    if (combL) {
+    if constexpr (kComb) {
       const double c = combL[site], t1 = v + 0.5 * c;
       outL[site] = t1;
       combL[site] = 0.5 * c + t1;
@@ -1102,19 +1113,47 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const RB* __res
   }
 }
 
-// *out += sum of v[0..n) (one block of 1024 threads, four accumulators per
-// thread, fixed order: deterministic).
+// The gather for a right-hand side's adjoint: Rb in RB, with or without the
+// weak-form 3-D force and the Heun combination.
+template <typename RB>
+hipError_t launch_gather(const RB* Rb, const double* gb, double* outF, double* outL, const LC& C, const double* Lm,
+                         const double* g3, const StageArgs& a, double* combF, double* combL, hipStream_t s) {
+  const dim3 grid((unsigned)((a.n_sites + kSites - 1) / kSites)), block(kAdjThreads);
+  if (combF && !combL) return hipErrorInvalidValue;
+  if (g3) {
+    if (combF)
+      hipLaunchKernelGGL((adj_gather_kernel<RB, true, true>), grid, block, 0, s, Rb, gb, outF, outL, C, Lm, g3, a,
+                         combF, combL);
+    else
+      hipLaunchKernelGGL((adj_gather_kernel<RB, true, false>), grid, block, 0, s, Rb, gb, outF, outL, C, Lm, g3, a,
+                         combF, combL);
+  } else {
+    if (combF)
+      hipLaunchKernelGGL((adj_gather_kernel<RB, false, true>), grid, block, 0, s, Rb, gb, outF, outL, C, Lm, g3, a,
+                         combF, combL);
+    else
+      hipLaunchKernelGGL((adj_gather_kernel<RB, false, false>), grid, block, 0, s, Rb, gb, outF, outL, C, Lm, g3, a,
+                         combF, combL);
+  }
+  return hipGetLastError();
+}
+
+// *out += sum of v[0..n) (one block of 1024 threads, eight accumulators per
+// thread whose loads are issued together, fixed order: deterministic).
 __global__ __launch_bounds__(1024) void adj_sum_kernel(const double* __restrict__ v, int n,
                                                        double* __restrict__ out) {
   __shared__ double part[1024];
-  double acc[4] = {0, 0, 0, 0};
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int i = threadIdx.x;
-  for (; i + 3 * 1024 < n; i += 4 * 1024) {
+  for (; i + 7 * 1024 < n; i += 8 * 1024) {
+    double t[8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += v[i + k * 1024];
+    for (int k = 0; k < 8; ++k) t[k] = v[i + k * 1024];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += t[k];
   }
   for (; i < n; i += 1024) acc[0] += v[i];
-  part[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  part[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   for (int st = 512; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
@@ -1175,8 +1214,9 @@ hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const doub
                                 double* Fout, double* Lout, int stage, const void* lc, const double* g3,
                                 const EosTable& tb, const StageArgs& a, int* err, hipStream_t s, const void* lc32) {
   if (lc32)
-    hipLaunchKernelGGL(adj_fwd32_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase,
-                       Fout, Lout, stage, static_cast<const LCf*>(lc32), g3, tb, a, err);
+    hipLaunchKernelGGL(g3 ? adj_fwd32_kernel<true> : adj_fwd32_kernel<false>, sites_grid(a.n_sites),
+                       dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout, Lout, stage,
+                       static_cast<const LCf*>(lc32), g3, tb, a, err);
   else
     hipLaunchKernelGGL(adj_fwd_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout,
                        Lout, stage, *static_cast<const LC*>(lc), g3, tb, a, err);
@@ -1191,22 +1231,18 @@ hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF
   const LC& C = *static_cast<const LC*>(lc);
   if (lc32) {
     float* Rb32 = reinterpret_cast<float*>(Rb);
-    hipLaunchKernelGGL(adj_local32_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL,
-                       scale, outF, outL, Rb32, gb, eta_part, accumulate, static_cast<const LCf*>(lc32), g3, tb, a,
-                       err);
+    hipLaunchKernelGGL(g3 ? adj_local32_kernel<true> : adj_local32_kernel<false>, sites_grid(a.n_sites),
+                       dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL, scale, outF, outL, Rb32, gb, eta_part,
+                       accumulate, static_cast<const LCf*>(lc32), g3, tb, a, err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(adj_gather_kernel<float>, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Rb32, gb, outF,
-                       outL, C, Lm, g3, a, combF, combL);
-    return hipGetLastError();
+    return launch_gather<float>(Rb32, gb, outF, outL, C, Lm, g3, a, combF, combL, s);
   }
   hipLaunchKernelGGL(adj_local_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL, scale,
                      outF, outL, Rb, gb, eta_part, accumulate, C, g3, tb, a, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(adj_gather_kernel<double>, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Rb, gb, outF, outL,
-                     C, Lm, g3, a, combF, combL);
-  return hipGetLastError();
+  return launch_gather<double>(Rb, gb, outF, outL, C, Lm, g3, a, combF, combL, s);
 }
 
 hipError_t launch_adj_sum(const double* v, int n, double* out, hipStream_t s) {
