@@ -203,6 +203,65 @@ class QuasiparticleEoS:
             raise FloatingPointError("non-positive entropy density at this chemical potential")
         return eta_over_s * s_mu / self.h(T) * HBARC
 
+    # ---- a mass depending on T and mu (eq. (cdef) at mu != 0, reading 26) ----
+    #
+    # Consistency, eq. (cdef), asks dB = -(1/2) int dchi f_eq dM^2 = -phi dM
+    # with phi(T, mu, M) = Z exp(mu/T) M^2 T K_1(M/T) / (2 pi^2) (the scalar
+    # density times M).  B(T, mu) exists only if this form is closed,
+    # d(phi dM) = 0, i.e. phi_T M_mu = phi_mu M_T with the partial derivatives
+    # of phi at fixed M: M is constant along the curves
+    # dmu/dT = -phi_T/phi_mu, and then so is B (dB = -phi dM = 0 there).
+    # With phi_mu = phi/T and phi_T = Z M^2 exp(mu/T) [(2 - mu/T) K_1 + x K_0]
+    # / (2 pi^2) (x = M/T; d[T K_1(M/T)]/dT = 2 K_1 + x K_0), the curve in
+    # alpha = mu/T is  d alpha / d ln T = -(2 + x K_0(x)/K_1(x)).  Each such
+    # curve meets alpha = 0 at one temperature T0, where the mass and B are
+    # those of the mu = 0 construction:
+    #   M(T, mu) = M(T0),  B(T, mu) = B(T0),
+    #   alpha = int_{ln T}^{ln T0} [2 + x K_0(x)/K_1(x)] d ln t,  x = M(T0)/t.
+    def char_integrand(self, x):
+        """2 + x K_0(x)/K_1(x): minus d alpha / d ln T at fixed M."""
+        return 2.0 + x * kv(0, x) / kv(1, x)
+
+    def alpha_on_char(self, T, T0, M):
+        """alpha at T on the curve of constant mass M through (T0, alpha = 0)."""
+        a, b = np.log(T), np.log(T0)
+        f = lambda t: self.char_integrand(M / np.exp(t))
+        from scipy.integrate import quad
+        v, _ = quad(f, a, b, epsabs=0.0, epsrel=1e-13, limit=200)
+        return v
+
+    def T0_of_T_alpha(self, T, alpha):
+        """The foot T0 of the constant-mass curve through (T, alpha).
+
+        The integrand is at least 2, so |alpha| >= 2 |ln(T0/T)|: T0 lies
+        between T and T exp(alpha/2), where the residual changes sign."""
+        from scipy.optimize import brentq
+        T, alpha = float(T), float(alpha)
+        if alpha == 0.0:
+            return T
+        g = lambda T0: self.alpha_on_char(T, T0, float(self.M(np.array(T0)))) - alpha
+        lo, hi = sorted((T, T * np.exp(alpha / 2.0)))
+        return brentq(g, lo, hi, xtol=1e-300, rtol=4 * np.finfo(float).eps, maxiter=200)
+
+    def M_mu(self, T, alpha):
+        """M(T, mu) at mu = alpha T."""
+        return float(self.M(np.array(self.T0_of_T_alpha(T, alpha))))
+
+    def B_mu(self, T, alpha):
+        """B(T, mu) at mu = alpha T."""
+        return float(self.B(np.array(self.T0_of_T_alpha(T, alpha))))
+
+    def thermo_mu(self, T, alpha):
+        """(p, eps, n) at (T, mu = alpha T) with M(T, mu) and B(T, mu), eq. (epsp)."""
+        M = self.M_mu(T, alpha)
+        B = self.B_mu(T, alpha)
+        x = M / T
+        c = self.Z * np.exp(alpha) * M ** 2 * T / (2 * PI2)
+        p = c * T * kv(2, x) - B
+        eps = c * T * (3 * kv(2, x) + x * kv(1, x)) + B
+        n = c * kv(2, x)
+        return p, eps, n
+
     # ---- inversions used by the lattice-Boltzmann step ----
     def T_from_eps_kin_eq(self, e, T_lo=0.05, T_hi=3.0):
         """Unique T with eps_kin_eq(T) = e (monotone in T), on [T_lo, T_hi]."""
