@@ -53,6 +53,18 @@ __device__ __forceinline__ size_t cix(int q, int l, int site, int ns) {
   return (size_t)(q * kL + l) * (size_t)ns + (size_t)site;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b on XCD
+// b mod 8).  Each XCD is given one contiguous band of blocks instead, so
+// that the stencil neighbours (two rows up and down) of a block were read
+// by blocks on the same XCD and are in its L2: XCD x takes blocks
+// [x base + min(x, rem), ...) with base = nb / 8, rem = nb % 8, which maps
+// the nb workgroups one-to-one onto the nb blocks.
+__device__ __forceinline__ int xcd_band_block() {
+  const int nb = gridDim.x, b = blockIdx.x, x = b & 7;
+  const int base = nb >> 3, rem = nb & 7;
+  return x * base + (x < rem ? x : rem) + (b >> 3);
+}
+
 // The slice and site of this thread (sites past the grid repeat the last
 // site and store nothing, but take part in the block's reductions).
 struct Lane {
@@ -63,7 +75,7 @@ __device__ __forceinline__ Lane lane_of(const StageArgs& a) {
   Lane g;
   g.l = threadIdx.x / kSites;
   g.sl = threadIdx.x % kSites;
-  const int s = blockIdx.x * kSites + g.sl;
+  const int s = xcd_band_block() * kSites + g.sl;
   g.valid = s < a.n_sites;
   g.site = g.valid ? s : a.n_sites - 1;
   g.x = g.site % a.nx;
@@ -955,8 +967,10 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
 // matching and EoS once per site (slice-0 thread, LDS), as
 // adj_local32_kernel.  R0 is held per node across the site sum; S2 is
 // evaluated again for the update.
+// At most two waves per SIMD: the compiler's own choice (153 VGPRs, three
+// waves) spilled scalar registers and ran 10% slower.
 template <bool kF3>
-__global__ __launch_bounds__(kAdjThreads) void adj_fwd32_kernel(const double* __restrict__ Fin,
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void adj_fwd32_kernel(const double* __restrict__ Fin,
                                                                 const double* __restrict__ Lin,
                                                                 const double* __restrict__ Fbase,
                                                                 const double* __restrict__ Lbase,
