@@ -251,12 +251,18 @@ int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_f
  * trajectory of an LB_FP32_FP64MATCH context).  For an LB_FP64 context all
  * of its arithmetic is FP64; for an LB_FP32_FP64MATCH context the reverse
  * sweep's per-node arithmetic is FP32 (the per-site chain through the
- * matching and the EoS, and the site sums, stay FP64), as the forward.  The calls only read the context's
- * parameters, lattice and EoS tables; its state is not used or changed.
- * The adjoint workspace is caller-owned device memory, 256-byte aligned, of
- * at least lb_adjoint_workspace_bytes(p) bytes, not touched by anyone else
- * during a call.  Calls are asynchronous on the context's stream.
- * LB_E_NOTIMPL for a context with particle_number LB_N_CONSERVED.
+ * matching and the EoS, and the site sums, stay FP64), as the forward.
+ * With particle_number LB_N_CONSERVED (constant mass) the step is the one
+ * with the n matching of eq. (sanity): T and mu/T from lambda and
+ * n = u_a N^a, the fugacity in F_eq and tau_R at (T, mu), all
+ * differentiated (the reverse sweep is then FP64 for either precision),
+ * and lb_adjoint_init takes the initial mu0/T0.  The calls only read the
+ * context's parameters, lattice and EoS tables; its state is not used or
+ * changed.  The adjoint workspace is caller-owned device memory, 256-byte
+ * aligned, of at least lb_adjoint_workspace_bytes(p) bytes, not touched by
+ * anyone else during a call.  Calls are asynchronous on the context's
+ * stream.  LB_E_NOTIMPL for the upwind ln M gradient and for momentum
+ * lattices other than 5 x 5 x 8.
  */
 
 /* Adjoint workspace size for these parameters (0 on invalid parameters). */

@@ -44,7 +44,7 @@ constexpr int kQ = 25;                     // nodes per phi slice
 constexpr int kL = 8;                      // phi slices
 constexpr int kSites = 32;                 // sites per block
 constexpr int kAdjThreads = kSites * kL;   // 256
-constexpr int kRed = 10;                   // most values reduced at once
+constexpr int kRed = 11;                   // most values reduced at once
 constexpr int kInitBlock = 128;           // adj_init_kernel: one thread per site
 using LC = LatticeConst<double, 5, 5>;
 typedef double RedBuf[kRed][kL][kSites];
@@ -125,7 +125,9 @@ __device__ __forceinline__ SliceGeom slice_geom(const LCT& C, const StageArgs& a
   return g;
 }
 
-// Site quantities of a state: moments, Landau matching, EoS.
+// Site quantities of a state: moments, Landau matching, EoS.  With the
+// conserved particle number (mu): the current sums c, n = u_a N^a, alpha =
+// mu/T and the table derivatives of the n matching.
 struct SiteFwd {
   double m[3][3];  // sum_n w F V^a V^b, a, b in (tau, x, y)
   double M, G;     // mass and M^4/(2 pi^2)
@@ -134,6 +136,9 @@ struct SiteFwd {
   EosDer D;
   double invT, MT, rate, beta;
   double gx, gy;   // centred gradient of ln M
+  bool mu;
+  double c[3], nd, alpha;  // sum_n w F V^a; n; mu/T
+  EosMuDer Dm;
 };
 
 __device__ void site_fwd(const double f[kQ], const double* __restrict__ lnM, const Lane& g, const LC& C,
@@ -146,8 +151,22 @@ __device__ void site_fwd(const double f[kQ], const double* __restrict__ lnM, con
     q2 += C.ws2[q] * f[q];
   }
   const double cl = C.cosl[g.l], sl = C.sinl[g.l];
-  double v[6] = {q0, q1 * cl, q1 * sl, q2 * cl * cl, q2 * cl * sl, q2 * sl * sl};
-  slice_sum<6>(v, red, g);
+  double v[9] = {q0, q1 * cl, q1 * sl, q2 * cl * cl, q2 * cl * sl, q2 * sl * sl, 0.0, 0.0, 0.0};
+  s->mu = a.mu_mode != 0;
+  if (s->mu) {
+    // the particle current N^a = M^3/(2 pi^2) sum w F V^a (eq. (NTdisc))
+    double n0 = 0, n1 = 0;
+    for (int q = 0; q < kQ; ++q) {
+      n0 += C.wx[q] * f[q];
+      n1 += C.w[q] * C.sig[q] * f[q];
+    }
+    v[6] = n0;
+    v[7] = n1 * cl;
+    v[8] = n1 * sl;
+    slice_sum<9>(v, red, g);
+  } else {
+    slice_sum<6>(v, red, g);
+  }
   s->m[0][0] = v[0];
   s->m[0][1] = s->m[1][0] = v[1];
   s->m[0][2] = s->m[2][0] = v[2];
@@ -158,7 +177,21 @@ __device__ void site_fwd(const double f[kQ], const double* __restrict__ lnM, con
   s->G = s->M * s->M * s->M * s->M * (1.0 / (2.0 * kPi * kPi));
   const double tk[6] = {s->G * v[0], s->G * v[1], s->G * v[2], s->G * v[3], s->G * v[4], s->G * v[5]};
   const bool matched = landau3(tk, &s->lam, s->u);
-  const bool eos_ok = eos_cell(tb, s->lam, &s->E, &s->D);
+  bool eos_ok;
+  s->alpha = 0.0;
+  if (s->mu) {
+    // n matching (eq. (sanity)): T and alpha from lambda and n; the mass is
+    // constant (beta = 0), as in the stage kernels' mu mode
+    s->c[0] = v[6];
+    s->c[1] = v[7];
+    s->c[2] = v[8];
+    s->nd = s->G / s->M * (s->u[0] * v[6] - s->u[1] * v[7] - s->u[2] * v[8]);
+    eos_ok = eos_mu(tb, s->lam, s->nd, &s->E, &s->alpha);
+    eos_mu_der(tb, s->E.T, &s->Dm);
+    s->E.beta = 0.0;
+  } else {
+    eos_ok = eos_cell(tb, s->lam, &s->E, &s->D);
+  }
   bool finite = true;
   for (int i = 0; i < 6; ++i) finite = finite && isfinite(tk[i]);
   if (g.valid && g.l == 0) {
@@ -202,7 +235,7 @@ __device__ __forceinline__ void node_terms(const SiteFwd& s, const SliceAux& o, 
                                            int q, double* feq, double* uvg, double* poly) {
   const int k = q / 5;
   const double sg = C.sig[q];
-  *feq = a.Z * exp((sg * s.M * o.cu - s.u[0] * o.Eeq[k]) * s.invT);
+  *feq = a.Z * exp(s.alpha + (sg * s.M * o.cu - s.u[0] * o.Eeq[k]) * s.invT);
   *uvg = s.u[0] - C.sigi[q] * o.cu;
   *poly = o.al[k] * sg - o.be[k] * C.sig2[q] - o.ga[k];
 }
@@ -354,7 +387,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   // the slice's adjoint: R0, S2 and everything they use
   const double ut = s.u[0], M = s.M, Meq = s.E.M_eq;
   double R0b[kQ], S2b[kQ], fb[kQ];
-  double cub = 0, Glb = 0, gub = 0, utb = 0, Mb = 0, invTb = 0, rateb = 0;
+  double cub = 0, Glb = 0, gub = 0, utb = 0, Mb = 0, invTb = 0, rateb = 0, alphab = 0;
   double alb[5] = {0, 0, 0, 0, 0}, beb[5] = {0, 0, 0, 0, 0}, gab[5] = {0, 0, 0, 0, 0};
   double Eeqb[5] = {0, 0, 0, 0, 0};
   double g3xb = 0, g3yb = 0;  // 3-D force: this slice's part of d/d g_x, d/d g_y
@@ -381,8 +414,9 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
     alb[k] += C.sig[q] * polyb;
     beb[k] -= C.sig2[q] * polyb;
     gab[k] -= polyb;
-    // F_eq = Z exp((sig M cu - ut E_eq) / T)
+    // F_eq = Z exp(alpha + (sig M cu - ut E_eq) / T)
     const double e = feq * feqb, sg = C.sig[q];
+    alphab += e;
     Mb += e * sg * o.cu * s.invT;
     cub += e * sg * M * s.invT;
     invTb += e * (sg * M * o.cu - ut * o.Eeq[k]);
@@ -440,10 +474,11 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
                     rateb,
                     Meqb,
                     Glb * gm.cl + gub * s.u[1] + g3xb,
-                    Glb * gm.sl + gub * s.u[2] + g3yb};
+                    Glb * gm.sl + gub * s.u[2] + g3yb,
+                    alphab};
   slice_sum<kRed>(v, red, g);
   utb = v[0];
-  const double uxb = v[1], uyb = v[2];
+  double uxb = v[1], uyb = v[2];
   Mb = v[3];
   invTb = v[4];
   MTb = v[5];
@@ -458,8 +493,29 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   const double qb = -rateb * s.rate / qv;
   const double etab = -rateb * s.rate * a.inv_eta_hbarc * kHbarC;  // dr/d(eta/s) = -r/(eta/s)
   const double z = Meq / T;
-  const double uub = Tb * T + Meqb * (s.D.dz * T + z * T) + betab * s.D.dbeta + qb * s.D.dq;
-  const double lamb = uub * s.D.du_dlam;
+  double lamb, cnb[3] = {0.0, 0.0, 0.0};
+  if (s.mu) {
+    // n matching: u = ln T from ln eps0_kin(u) - ln n0(u) = ln lambda - ln n,
+    // alpha = ln n - ln n0(u), q = q0(u) - alpha Nq(u); beta = 0
+    const double ab = v[10] - qb * s.Dm.Nq;
+    const double uub = Tb * T + Meqb * (s.Dm.dz * T + z * T) + qb * (s.Dm.dQ - s.alpha * s.Dm.dNq) -
+                       ab * s.Dm.dlnN;
+    const double Dd = s.Dm.dlnEk - s.Dm.dlnN;
+    lamb = uub / (Dd * s.lam);
+    const double nb_ = ab / s.nd - uub / (Dd * s.nd);
+    // n = (M^3 / (2 pi^2)) (u^tau c^tau - u^x c^x - u^y c^y)
+    const double gmv = s.G / s.M;
+    utb += nb_ * gmv * s.c[0];
+    uxb -= nb_ * gmv * s.c[1];
+    uyb -= nb_ * gmv * s.c[2];
+    cnb[0] = nb_ * gmv * s.u[0];
+    cnb[1] = -nb_ * gmv * s.u[1];
+    cnb[2] = -nb_ * gmv * s.u[2];
+    Mb += nb_ * 3.0 * s.nd / M;
+  } else {
+    const double uub = Tb * T + Meqb * (s.D.dz * T + z * T) + betab * s.D.dbeta + qb * s.D.dq;
+    lamb = uub * s.D.du_dlam;
+  }
   // eigenproblem A u = lambda u, A = T_kin g, u.u = 1: with u_low = g u and
   // B = A - lambda + u u_low^T, solve B^T w = u_bar - (u_bar.u) u_low; then
   // T_kin_bar = -w u_low^T + (w.u + lambda_bar) u_low u_low^T
@@ -498,9 +554,12 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   // the moments' adjoint, m^{ab} = sum_n w F V^a V^b, and the stores
   const double c00 = mb[0][0], c01 = (mb[0][1] + mb[1][0]) * gm.cl + (mb[0][2] + mb[2][0]) * gm.sl;
   const double c11 = mb[1][1] * gm.cl * gm.cl + (mb[1][2] + mb[2][1]) * gm.cl * gm.sl + mb[2][2] * gm.sl * gm.sl;
+  // and the particle current's adjoint (mu mode; zero otherwise)
+  const double n00 = cnb[0], n01 = cnb[1] * gm.cl + cnb[2] * gm.sl;
   for (int q = 0; q < kQ; ++q) {
     const size_t i = cix(q, l, g.site, ns);
-    const double v_ = fb[q] + c00 * C.wx2[q] + c01 * C.wxs[q] + c11 * C.ws2[q];
+    const double v_ = fb[q] + c00 * C.wx2[q] + c01 * C.wxs[q] + c11 * C.ws2[q] + n00 * C.wx[q] +
+                      n01 * C.w[q] * C.sig[q];
     outF[i] = accumulate ? outF[i] + v_ : v_;
     Rb[i] = R0b[q];
   }
@@ -872,7 +931,7 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
       for (int jj = 0; jj < 5; ++jj) acc -= C2.Ath[jj * 5 + j] * R0b[k * 5 + jj] * o2.itau;
       fb[k * 5 + j] += acc;
     }
-  double v[kRed] = {(double)utb,
+  double v[10] = {(double)utb,
                     (double)cub * gm.cl + (double)gub * S.gx,
                     (double)cub * gm.sl + (double)gub * S.gy,
                     (double)Mb,
@@ -882,7 +941,7 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
                     (double)Meqb,
                     (double)Glb * gm.cl + (double)gub * S.u[1] + g3xb,
                     (double)Glb * gm.sl + (double)gub * S.u[2] + g3yb};
-  slice_sum<kRed>(v, red, g);
+  slice_sum<10>(v, red, g);
   if (l == 0) {
     // the site's reverse chain, once (FP64): as adj_local_kernel
     SiteLds& W = sd[g.sl];
@@ -1178,7 +1237,9 @@ __global__ __launch_bounds__(1024) void adj_sum_kernel(const double* __restrict_
 
 // Adjoint of the initial state of lb_init: T0 from eps_EoS(T0) = e0, M =
 // z(T0) T0, F_n = Z exp(-z (u^tau gamma - u_perp.v_perp)) (z = M/T0, flow
-// held fixed).  grad_e0 = d/d e0 of (adjF . F + adjL . ln M).
+// held fixed).  grad_e0 = d/d e0 of (adjF . F + adjL . ln M).  With an
+// initial mu0 = alpha0 T0 (constant mass): eps0(T0) = e0 exp(-alpha0) and F
+// carries exp(alpha0).
 __global__ __launch_bounds__(kInitBlock) void adj_init_kernel(const double* __restrict__ e0,
                                                              const double* __restrict__ ux0,
                                                              const double* __restrict__ uy0,
@@ -1190,7 +1251,7 @@ __global__ __launch_bounds__(kInitBlock) void adj_init_kernel(const double* __re
   const int site = blockIdx.x * kInitBlock + threadIdx.x;
   if (site >= a.n_sites) return;
   const int ns = a.n_sites;
-  const double e = e0[site] * (kHbarC * kHbarC * kHbarC);
+  const double e = e0[site] * (kHbarC * kHbarC * kHbarC) * exp(-a.alpha0);
   const double vx = ux0 ? ux0[site] : 0.0, vy = uy0 ? uy0[site] : 0.0;
   double uu = tb.u_lo;
   if (!(e > 0.0) || !eos_invert(tb, kLnEeos, tb.inv_ee, tb.ge0, tb.ge_h, tb.ge_inv_h, log(e), &uu)) {
@@ -1210,7 +1271,7 @@ __global__ __launch_bounds__(kInitBlock) void adj_init_kernel(const double* __re
     const double cu = vx * C.cosl[l] + vy * C.sinl[l];
     for (int q = 0; q < kQ; ++q) {
       const double h = ut * C.x[q / 5] - cu * C.sig[q];
-      const double f = a.Z * exp(-z * h);
+      const double f = a.Z * exp(a.alpha0 - z * h);
       zb += aF[cix(q, l, site, ns)] * f * (-h);
     }
   }

@@ -463,7 +463,6 @@ struct AdjBufs {
 };
 int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBufs* B) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
-  if (c->p.particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the adjoint step has mu = 0 only");
   if (c->p.gradient_form != LB_GRAD_CENTRED) return fail(LB_E_NOTIMPL, "the adjoint step has the centred ln M gradient only");
   if (c->generic) return fail(LB_E_NOTIMPL, "the adjoint step has the 5 x 5 x 8 momentum lattice only");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
@@ -793,8 +792,9 @@ int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F,
   set_tau(&a1, c, tau_fm + dtau_fm);
   hipStream_t st = c->stream;
   // an FP32 context's reverse sweep runs its node arithmetic in FP32 (with
-  // the FP32 lattice constants)
-  const bool fp32 = c->p.precision == LB_FP32_FP64MATCH;
+  // the FP32 lattice constants); with the conserved particle number the
+  // FP64 reverse sweep serves both precisions
+  const bool fp32 = c->p.precision == LB_FP32_FP64MATCH && c->p.particle_number == LB_N_FREE;
   // predictor state F* = F + dtau K(F)
   hipError_t e =
       launch_adj_stage_fwd(d_F, d_lnM, nullptr, nullptr, B.Fp, B.Lp, 0, &c->cd, c->g3, c->tb, a0, c->err, st,
@@ -819,7 +819,6 @@ int lb_adjoint_init(lb_ctx* c, const double* d_e0, const double* d_ux0, const do
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
   if (!d_e0 || !d_adj_F || !d_adj_lnM || !d_grad_e0) return fail(LB_E_ARG, "pointer is NULL");
   if ((d_ux0 == nullptr) != (d_uy0 == nullptr)) return fail(LB_E_ARG, "give both ux0 and uy0 or neither");
-  if (c->p.particle_number != LB_N_FREE) return fail(LB_E_NOTIMPL, "the adjoint of lb_init has mu = 0 only");
   if (c->generic) return fail(LB_E_NOTIMPL, "the adjoint of lb_init has the 5 x 5 x 8 momentum lattice only");
   const StageArgs a = stage_args(c, c->p.tau0_fm, 0.0);
   hipError_t e = launch_adj_init(d_e0, d_ux0, d_uy0, d_adj_F, d_adj_lnM, d_grad_e0, &c->cd, c->tb, a, c->err,

@@ -167,16 +167,11 @@ def test_run_conserves_particle_number(lat, eos):
     assert drift[1] > 20 * drift[0]
 
 
-def test_adjoint_form_and_mixed_batch_reject_mu(eos):
+def test_mixed_batch_rejects_mu_with_3d_force(eos):
+    # (the adjoint form takes this mode: tests/test_gpu_adjoint_mu.py)
     nx, ny, dx = 8, 8, 0.2
     e0 = _e0(nx, ny, dx)
     p = _params(nx, ny, dx, lb.LB_FP64, 0.1, 0.2)
-    c = lb.Context(p, gpu(e0))
-    ws = c.adjoint_workspace()
-    F, lnM, _ = c.get_state()
-    with pytest.raises(lb.LbError) as ei:
-        c.adjoint_forward_step(0.5, 0.005, F, lnM, ws)
-    assert ei.value.code == lb.LB_E_NOTIMPL
     p.force_form = lb.LB_FORCE_WEAK3D   # the batched form takes one of the two
     with pytest.raises(lb.LbError) as ei:
         lb.Batch(p, [(nx, ny, dx, 0.1)], [gpu(e0)])
