@@ -167,25 +167,6 @@ __device__ inline bool eos_mu(const EosTable& tb, double lam, double n, EosAt* o
   return ok;
 }
 
-// Derivatives in u = ln T of the table fields that eos_mu uses, at the T it
-// returned (for the adjoint of the n matching): ln eps0_kin, ln n0, z, q
-// and T n0/h.
-struct EosMuDer {
-  double dlnEk, dlnN, dz, dQ, dNq, Nq;
-};
-__device__ inline void eos_mu_der(const EosTable& tb, double T, EosMuDer* d) {
-  double t, w[4], dw[4];
-  const int i = eos_locate(tb, log(T), &t);
-  lagrange4(t, w, dw);
-  const double ih = tb.inv_h;
-  d->dlnEk = eos_field(tb, i, dw, kLnEk) * ih;
-  d->dlnN = eos_field(tb, i, dw, kLnN) * ih;
-  d->dz = eos_field(tb, i, dw, kZ) * ih;
-  d->dQ = eos_field(tb, i, dw, kQ) * ih;
-  d->dNq = eos_field(tb, i, dw, kNq) * ih;
-  d->Nq = eos_field(tb, i, w, kNq);
-}
-
 // EoS at lambda = eps - B for the stage kernels' matching, given
 // g = ln(lambda) (lam_pos: lambda > 0): one read of the 4-point stencil of
 // the table on the uniform g grid and a cubic interpolation of T, M_eq/T,

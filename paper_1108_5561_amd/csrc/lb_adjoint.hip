@@ -125,6 +125,26 @@ __device__ __forceinline__ SliceGeom slice_geom(const LCT& C, const StageArgs& a
   return g;
 }
 
+// Derivatives in u = ln T of the table fields that eos_mu uses, at the T it
+// returned (for the adjoint of the n matching; the
+// table fields by their qualified names, kQ being the node count here): ln eps0_kin, ln n0, z, q
+// and T n0/h.
+struct EosMuDer {
+  double dlnEk, dlnN, dz, dQ, dNq, Nq;
+};
+__device__ inline void eos_mu_der(const EosTable& tb, double T, EosMuDer* d) {
+  double t, w[4], dw[4];
+  const int i = eos_locate(tb, log(T), &t);
+  lagrange4(t, w, dw);
+  const double ih = tb.inv_h;
+  d->dlnEk = eos_field(tb, i, dw, ::lbmi::kLnEk) * ih;
+  d->dlnN = eos_field(tb, i, dw, ::lbmi::kLnN) * ih;
+  d->dz = eos_field(tb, i, dw, ::lbmi::kZ) * ih;
+  d->dQ = eos_field(tb, i, dw, ::lbmi::kQ) * ih;
+  d->dNq = eos_field(tb, i, dw, ::lbmi::kNq) * ih;
+  d->Nq = eos_field(tb, i, w, ::lbmi::kNq);
+}
+
 // Site quantities of a state: moments, Landau matching, EoS.  With the
 // conserved particle number (mu): the current sums c, n = u_a N^a, alpha =
 // mu/T and the table derivatives of the n matching.
