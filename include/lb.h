@@ -435,8 +435,8 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
  * the spare state buffers (the state is unchanged), and keep the fastest.
  * variant_out (may be NULL) receives its index; ms_out (may be NULL) the
  * mean milliseconds per step of each variant ([12] in FP32, [3] in FP64).
- * With LB_FORCE_WEAK3D or LB_N_CONSERVED there are three variants, tile
- * rows 2, 4, 8 (v = 0, 1, 2) at the single-event kernel's occupancy.
+ * With LB_FORCE_WEAK3D, LB_N_CONSERVED or both there are three variants,
+ * tile rows 2, 4, 8 (v = 0, 1, 2) at the single-event kernel's occupancy.
  * Synchronous. */
 int lb_batch_tune(lb_batch* b, double dtau_fm, int32_t* variant_out, double* ms_out);
 

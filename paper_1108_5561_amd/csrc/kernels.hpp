@@ -62,9 +62,9 @@ struct StageTime {
 // kBatchTileRows[v % 3] tile rows (tiles are 8 sites wide) and, in FP32,
 // 4 ((v / 3) % 2 = 0) or 3 waves per SIMD as occupancy target, with
 // streaming (nontemporal) stores of the new state for v >= 6; FP64 has
-// variants 0..2 at 2 waves per SIMD.  With the weak-form 3-D force or the
-// conserved particle number (one of the two) there are three variants,
-// tile rows 2, 4, 8 at the occupancy of the single-event kernel.
+// variants 0..2 at 2 waves per SIMD.  With the weak-form 3-D force, the
+// conserved particle number or both there are three variants, tile rows
+// 2, 4, 8 at the occupancy of the single-event kernel.
 constexpr int kBatchTileRows[3] = {2, 4, 8};
 inline int batch_variants(int precision, int force_form = 0, int particle_number = 0) {
   return (force_form || particle_number) ? 3 : (precision == 1 ? 12 : 3);

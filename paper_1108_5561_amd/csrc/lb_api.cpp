@@ -1332,8 +1332,6 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
   if (!m.empty()) return fail(LB_E_ARG, m);
   if (p->gradient_form != LB_GRAD_CENTRED)
     return fail(LB_E_NOTIMPL, "the batched form takes gradient_form LB_GRAD_CENTRED");
-  if (p->force_form != LB_FORCE_FEQ && p->particle_number != LB_N_FREE)
-    return fail(LB_E_NOTIMPL, "the batched form has the 3-D force or the conserved particle number, not both");
   if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(LB_E_ARG, "workspace NULL or not 256-byte aligned");
   if (!d_e0) return fail(LB_E_ARG, "e0 pointer array is NULL");
   for (int i = 0; i < n_events; ++i)

@@ -1004,9 +1004,18 @@ hipError_t batch_launch_s(int variant, const BatchEvent* ev, const int32_t* te, 
   case V:                                                                                                        \
     return batch_launch_t<R, STAGE, TY, W, 0, F, MU>(ev, te, n_tiles, time, times, tidx, i_in, i_base, i_out, sc,  \
                                                      tb, a, err, s);
-  // the weak-form 3-D force or the conserved particle number: tile rows 2,
-  // 4, 8 at the occupancy of the single-event kernel (a block of 8 rows is
-  // 8 waves, so at least 2 waves per SIMD)
+  // the weak-form 3-D force and/or the conserved particle number: tile rows
+  // 2, 4, 8 at the occupancy of the single-event kernel (a block of 8 rows
+  // is 8 waves, so at least 2 waves per SIMD); both together at the
+  // force's occupancy, as lb_step runs them
+  if (a.force_form == LB_FORCE_WEAK3D && a.mu_mode) {
+    switch (variant) {
+      LB_BATCH_CASE_FM(0, 2, ForceWaves<R>::v, 1, 1)
+      LB_BATCH_CASE_FM(1, 4, ForceWaves<R>::v, 1, 1)
+      LB_BATCH_CASE_FM(2, 8, 2, 1, 1)
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (a.force_form == LB_FORCE_WEAK3D) {
     switch (variant) {
       LB_BATCH_CASE_FM(0, 2, ForceWaves<R>::v, 1, 0)

@@ -167,17 +167,6 @@ def test_run_conserves_particle_number(lat, eos):
     assert drift[1] > 20 * drift[0]
 
 
-def test_mixed_batch_rejects_mu_with_3d_force(eos):
-    # (the adjoint form takes this mode: tests/test_gpu_adjoint_mu.py)
-    nx, ny, dx = 8, 8, 0.2
-    e0 = _e0(nx, ny, dx)
-    p = _params(nx, ny, dx, lb.LB_FP64, 0.1, 0.2)
-    p.force_form = lb.LB_FORCE_WEAK3D   # the batched form takes one of the two
-    with pytest.raises(lb.LbError) as ei:
-        lb.Batch(p, [(nx, ny, dx, 0.1)], [gpu(e0)])
-    assert ei.value.code == lb.LB_E_NOTIMPL
-
-
 def test_bench_grid_sampled_parity(lat, eos):
     # the 256 x 256 grid that the benchmark's conserved-number leg times
     # (FP32, constant mass, mu0/T0 = 0.5): 30 steps, then one more step at
