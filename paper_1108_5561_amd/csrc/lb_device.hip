@@ -70,7 +70,14 @@ template <> struct TileRows<double> { static constexpr int v = 4; };
 template <typename R, int STAGE> struct MinWaves {
   static constexpr int v = STAGE == 0 ? LB_WAVES_PER_EU_F32 : LB_WAVES_PER_EU_F32_CORR;
 };
-template <int STAGE> struct MinWaves<double, STAGE> { static constexpr int v = LB_WAVES_PER_EU_F64; };
+// FP64: the predictor at one wave per SIMD (65 us against 72 at two, whose
+// register budget makes it spill), the corrector at two (89 us against 138)
+#ifndef LB_WAVES_PER_EU_F64_PRED
+#define LB_WAVES_PER_EU_F64_PRED 1
+#endif
+template <int STAGE> struct MinWaves<double, STAGE> {
+  static constexpr int v = STAGE == 0 ? LB_WAVES_PER_EU_F64_PRED : LB_WAVES_PER_EU_F64;
+};
 // with the weak-form 3-D force (about twice the registers in flight)
 #ifndef LB_FORCE_WAVES_F32
 #define LB_FORCE_WAVES_F32 2
