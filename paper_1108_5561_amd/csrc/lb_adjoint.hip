@@ -1,8 +1,8 @@
-// Discrete adjoint (reverse mode) of the Heun step of Sec. IV.D, FP64, for
-// the differentiable form: gradients of a function of the final state with
+// Discrete adjoint (reverse mode) of the Heun step of Sec. IV.D for the
+// differentiable form: gradients of a function of the final state with
 // respect to the initial energy density e0 and to eta/s.
 //
-// The step differentiated is the FP64 step of the stage kernels, written out
+// The step differentiated is the step of the stage kernels, written out
 // here in the canonical layout F[n][site], n = q 8 + l (q = k N_theta + j):
 // for state (F, ln M) at time tau the right-hand side is
 //   R0_n = A_n + S1_n/tau + F_eq,n ((u.V)/gamma r - poly_n) - (u.V)/gamma r F_n
@@ -12,21 +12,25 @@
 // and BGK of eqs. (Bmilne), (newBeq), (bgk); mass evolution of eqs.
 // (edchange), (masschange)), where r = 1/tau_R, u, T and M_eq come from the
 // Landau matching (eq. (sanity)) of the state's own moments (eq. (emtnew))
-// and the EoS inversion.
+// and the EoS inversion (with the conserved particle number also n =
+// u_a N^a, mu/T and the fugacity of F_eq; beta = 0 there).
 //
 // Work mapping: a block of 256 threads covers 32 sites; thread t owns phi
 // slice l = t / 32 of site t % 32, so a wavefront reads 64 consecutive
-// sites of one node (coalesced).  Sums over a site's eight slices go
-// through LDS in a fixed order (every thread of the site gets the same
-// bits), and the per-site FP64 work (matching, EoS, their adjoints) is
-// repeated by the eight threads of a site.  The reverse sweep of one
-// right-hand side evaluates the slice forward once, keeps R0 and S2 in
-// registers, propagates the adjoint through the collision, equilibrium,
-// force and operator terms, reduces the site adjoints over the slices, runs
-// the implicit-function adjoints of the EoS root and of the eigenproblem,
-// and adds the moments' adjoint.  The transposed streaming stencil and the
-// transposed centred ln M gradient are gathers over the neighbours
-// (adj_gather_kernel).
+// sites of one node (coalesced); each XCD takes a contiguous band of
+// blocks.  Sums over a site's eight slices go through LDS in a fixed order
+// (every thread of the site gets the same bits).  FP64 kernels
+// (adj_fwd_kernel, adj_local_kernel): the per-site work (matching, EoS,
+// their adjoints) is repeated by the eight threads of a site; the reverse
+// sweep of one right-hand side evaluates the slice forward once, keeps R0
+// and S2 in registers, propagates the adjoint through the collision,
+// equilibrium, force and operator terms, reduces the site adjoints over the
+// slices, runs the implicit-function adjoints of the EoS root and of the
+// eigenproblem, and adds the moments' adjoint.  FP32 kernels
+// (adj_fwd32_kernel, adj_local32_kernel, for contexts whose forward runs in
+// FP32): the node arithmetic in FP32, the per-site chain once per site in
+// FP64.  The transposed streaming stencil and the transposed centred ln M
+// gradient are gathers over the neighbours (adj_gather_kernel).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
