@@ -261,8 +261,9 @@ int lb_set_state(lb_ctx* c, const double* d_F, const double* d_lnM, double tau_f
  * changed.  The adjoint workspace is caller-owned device memory, 256-byte
  * aligned, of at least lb_adjoint_workspace_bytes(p) bytes, not touched by
  * anyone else during a call.  Calls are asynchronous on the context's
- * stream.  LB_E_NOTIMPL for the upwind ln M gradient and for momentum
- * lattices other than 5 x 5 x 8.
+ * stream.  Either gradient_form (the upwind ln M gradient differentiated
+ * per phi slice).  LB_E_NOTIMPL for momentum lattices other than
+ * 5 x 5 x 8.
  */
 
 /* Adjoint workspace size for these parameters (0 on invalid parameters). */
@@ -299,7 +300,8 @@ int lb_adjoint_step(lb_ctx* c, double tau_fm, double dtau_fm, const double* d_F,
  * harnesses that forbid hipMalloc): the scratch lives in a static device
  * array of the library, 80 MiB per device (held from the library's load
  * until the process ends), enough for grids of up to about 17000 sites
- * (4840 bytes per site; the 128 x 128 gradient workload fits).  Arguments,
+ * (4840 bytes per site, 4952 with the upwind ln M gradient; the 128 x 128
+ * gradient workload fits).  Arguments,
  * results and errors as lb_adjoint_step; LB_E_ARG with a message if the
  * grid needs more scratch than that.  Calls on one device share its array,
  * so calls that overlap on one device (other streams, other threads) race;

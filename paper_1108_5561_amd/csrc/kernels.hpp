@@ -119,7 +119,8 @@ hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const doub
 // Reverse sweep of one right-hand side at (F, ln M), time a.tau, with
 // K_bar = scale seedF, X_bar = scale seedL, into (outF, outL) (written, or
 // added with accumulate = 1), plus the per-site eta/s adjoint; Rb
-// ([N][sites] doubles; FP32 values with lc32) and gb ([2][sites]) are
+// ([N][sites] doubles; FP32 values with lc32) and gb ([2][sites], or
+// [2][8][sites] with the upwind ln M gradient: per phi slice) are
 // scratch.  lc32 as for launch_adj_stage_fwd.  With combF (combL) the Heun
 // combination follows in the same pass: outF <- outF + combF/2, then
 // combF <- combF/2 + outF.

@@ -233,19 +233,43 @@ __device__ void site_fwd(const double f[kQ], const double* __restrict__ lnM, con
   s->gy = (lnM[yp * a.nx + x] - lnM[ym * a.nx + x]) * a.inv2dx;
 }
 
-// Per-slice factors of the equilibrium and the mass-gradient force.
+// The ln M gradient that the force on F_eq of a slice uses: the site's
+// centred one (gxc, gyc), or with the upwind gradient (LB_GRAD_UPWIND) the
+// streaming's second-order upwind difference along the slice's direction
+// of motion, centred along an axis it does not move on (as the stage
+// kernels).
+__device__ __forceinline__ void slice_grad(const double* __restrict__ Lm, const Lane& g, const SliceGeom& gm,
+                                           const StageArgs& a, double gxc, double gyc, double* gx, double* gy,
+                                           bool upwind) {
+  *gx = gxc;
+  *gy = gyc;
+  if (!upwind) return;
+  const int x = g.x, y = g.y;
+  const double L0 = Lm[g.site];
+  if (gm.dxr != 0)
+    *gx = gm.dxr * (3.0 * L0 - 4.0 * Lm[y * a.nx + wrap(x - gm.dxr, a.nx)] + Lm[y * a.nx + wrap(x - 2 * gm.dxr, a.nx)]) *
+          a.inv2dx;
+  if (gm.dyr != 0)
+    *gy = gm.dyr * (3.0 * L0 - 4.0 * Lm[wrap(y - gm.dyr, a.ny) * a.nx + x] + Lm[wrap(y - 2 * gm.dyr, a.ny) * a.nx + x]) *
+          a.inv2dx;
+}
+
+// Per-slice factors of the equilibrium and the mass-gradient force (gx, gy:
+// the slice's ln M gradient).
 struct SliceAux {
-  double cu, Gl, gu;
+  double cu, Gl, gu, gx, gy;
   double Eeq[5], al[5], be[5], ga[5];
 };
 // With the weak-form 3-D force (f3) the force acts on F instead (force_row)
 // and the polynomial on F_eq vanishes: Gl = gu = 0.
 __device__ __forceinline__ void slice_aux(const SiteFwd& s, const SliceGeom& gm, const LC& C, bool f3,
+                                          const double* __restrict__ Lm, const Lane& g, const StageArgs& a,
                                           SliceAux* o) {
   const double ut = s.u[0], ux = s.u[1], uy = s.u[2], Meq = s.E.M_eq, M = s.M;
+  slice_grad(Lm, g, gm, a, s.gx, s.gy, &o->gx, &o->gy, a.grad_form == LB_GRAD_UPWIND);
   o->cu = ux * gm.cl + uy * gm.sl;
-  o->Gl = f3 ? 0.0 : s.gx * gm.cl + s.gy * gm.sl;
-  o->gu = f3 ? 0.0 : s.gx * ux + s.gy * uy;
+  o->Gl = f3 ? 0.0 : o->gx * gm.cl + o->gy * gm.sl;
+  o->gu = f3 ? 0.0 : o->gx * ux + o->gy * uy;
   for (int k = 0; k < 5; ++k) {
     o->Eeq[k] = sqrt(Meq * Meq + M * M * C.sh2[k]);
     o->al[k] = s.MT * o->Gl * ut * M * C.x[k] / o->Eeq[k];
@@ -351,7 +375,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_fwd_kernel(const double* __re
   site_fwd(f, Lin, g, C, tb, a, red, &s, err);
   const SliceGeom gm = slice_geom(C, a, g.l);
   SliceAux o;
-  slice_aux(s, gm, C, g3 != nullptr, &o);
+  slice_aux(s, gm, C, g3 != nullptr, Lin, g, a, &o);
   double R0[kQ], S2[kQ], sums[3];
   slice_rhs(Fin, f, g, gm, s, o, C, a, g3, R0, S2, sums);
   slice_sum<3>(sums, red, g);
@@ -391,7 +415,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   site_fwd(f, Lm, g, C, tb, a, red, &s, err);
   const SliceGeom gm = slice_geom(C, a, l);
   SliceAux o;
-  slice_aux(s, gm, C, g3 != nullptr, &o);
+  slice_aux(s, gm, C, g3 != nullptr, Lm, g, a, &o);
   double R0[kQ], S2[kQ], Kb[kQ];
   double sums[4];
   slice_rhs(F, f, g, gm, s, o, C, a, g3, R0, S2, sums);
@@ -490,8 +514,8 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
     gub = 0;
   }
   double v[kRed] = {utb,
-                    cub * gm.cl + gub * s.gx,
-                    cub * gm.sl + gub * s.gy,
+                    cub * gm.cl + gub * o.gx,
+                    cub * gm.sl + gub * o.gy,
                     Mb,
                     invTb,
                     MTb,
@@ -500,6 +524,13 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
                     Glb * gm.cl + gub * s.u[1] + g3xb,
                     Glb * gm.sl + gub * s.u[2] + g3yb,
                     alphab};
+  // with the upwind gradient the slice's own gradient adjoint goes out per
+  // slice ([2][8][sites]); otherwise the site totals below ([2][sites])
+  const bool upw = a.grad_form == LB_GRAD_UPWIND;
+  if (upw && g.valid) {
+    gb[(size_t)l * ns + g.site] = v[8];
+    gb[(size_t)(kL + l) * ns + g.site] = v[9];
+  }
   slice_sum<kRed>(v, red, g);
   utb = v[0];
   double uxb = v[1], uyb = v[2];
@@ -590,8 +621,10 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   if (l == 0) {
     const double lb = Mb * M;  // M = exp(ln M)
     outL[g.site] = accumulate ? outL[g.site] + lb : lb;
-    gb[g.site] = gxb;
-    gb[ns + g.site] = gyb;
+    if (!upw) {
+      gb[g.site] = gxb;
+      gb[ns + g.site] = gyb;
+    }
     eta_part[g.site] = accumulate ? eta_part[g.site] + etab : etab;
   }
 }
@@ -703,10 +736,13 @@ __device__ __forceinline__ uint32_t lane_off8(int l, int site, int ns) {
 struct Slice32 {
   float ut, M, Meq, invT, MT, rate, cu, Gl, gu, ax, ay, itau;
   uint32_t o_own, o_x1, o_x2, o_y1, o_y2;
+  double gx, gy;  // the slice's ln M gradient (slice_grad)
 };
+template <bool kUp>
 __device__ __forceinline__ Slice32 slice32(const SiteLds& S, const Lane& g, const SliceGeom& gm, bool f3,
-                                           const StageArgs& a) {
+                                           const double* __restrict__ Lm, const StageArgs& a) {
   Slice32 o;
+  slice_grad(Lm, g, gm, a, S.gx, S.gy, &o.gx, &o.gy, kUp);
   o.ut = (float)S.u[0];
   o.M = (float)S.M;
   o.Meq = (float)S.Meq;
@@ -714,8 +750,8 @@ __device__ __forceinline__ Slice32 slice32(const SiteLds& S, const Lane& g, cons
   o.MT = (float)S.MT;
   o.rate = (float)S.rate;
   o.cu = (float)S.u[1] * (float)gm.cl + (float)S.u[2] * (float)gm.sl;
-  o.Gl = f3 ? 0.0f : (float)(S.gx * gm.cl + S.gy * gm.sl);
-  o.gu = f3 ? 0.0f : (float)(S.gx * S.u[1] + S.gy * S.u[2]);
+  o.Gl = f3 ? 0.0f : (float)(o.gx * gm.cl + o.gy * gm.sl);
+  o.gu = f3 ? 0.0f : (float)(o.gx * S.u[1] + o.gy * S.u[2]);
   o.ax = (float)gm.ax;
   o.ay = (float)gm.ay;
   // S1/tau for the Milne metric, none for Minkowski
@@ -787,8 +823,9 @@ __device__ __forceinline__ void for_nodes(Fn&& fn) {
 }
 
 // Two waves per SIMD for the force on F_eq (a few registers spill, faster
-// than one wave with none); one for the weak-form 3-D force.
-template <bool kF3>
+// than one wave with none); one for the weak-form 3-D force.  kUp: the
+// upwind ln M gradient (force on F_eq only).
+template <bool kF3, bool kUp>
 __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
     const double* __restrict__ F, const double* __restrict__ Lm, const double* __restrict__ seedF,
     const double* __restrict__ seedL, double scale, double* __restrict__ outF, double* __restrict__ outL,
@@ -807,7 +844,7 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
   site_chain32(f, Lm, g, C, gm.cl, gm.sl, tb, a, red, sd, err);
   const SiteLds& S = sd[g.sl];
   constexpr bool f3 = kF3;  // g3 != nullptr
-  const Slice32 o = slice32(S, g, gm, f3, a);
+  const Slice32 o = slice32<kUp>(S, g, gm, f3, Lm, a);
   const float sc = (float)scale, Zf = (float)a.Z;
   // what both sweeps read from memory, once: the part of R0 without the
   // collision and the equilibrium (streaming, S1/tau, the 3-D force) and
@@ -956,8 +993,8 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
       fb[k * 5 + j] += acc;
     }
   double v[10] = {(double)utb,
-                    (double)cub * gm.cl + (double)gub * S.gx,
-                    (double)cub * gm.sl + (double)gub * S.gy,
+                    (double)cub * gm.cl + (double)gub * o.gx,
+                    (double)cub * gm.sl + (double)gub * o.gy,
                     (double)Mb,
                     (double)invTb,
                     (double)MTb,
@@ -965,6 +1002,12 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
                     (double)Meqb,
                     (double)Glb * gm.cl + (double)gub * S.u[1] + g3xb,
                     (double)Glb * gm.sl + (double)gub * S.u[2] + g3yb};
+  // with the upwind gradient the slice's own gradient adjoint goes out per
+  // slice ([2][8][sites]); otherwise the site totals below ([2][sites])
+  if (kUp && g.valid) {
+    gb[(size_t)l * ns + g.site] = v[8];
+    gb[(size_t)(kL + l) * ns + g.site] = v[9];
+  }
   slice_sum<10>(v, red, g);
   if (l == 0) {
     // the site's reverse chain, once (FP64): as adj_local_kernel
@@ -1028,8 +1071,10 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
     if (g.valid) {
       const double lb = Mbd * W.M;
       outL[g.site] = accumulate ? outL[g.site] + lb : lb;
-      gb[g.site] = gxb;
-      gb[ns + g.site] = gyb;
+      if (!kUp) {
+        gb[g.site] = gxb;
+        gb[ns + g.site] = gyb;
+      }
       eta_part[g.site] = accumulate ? eta_part[g.site] + etab : etab;
     }
   }
@@ -1052,7 +1097,7 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
 // evaluated again for the update.
 // At most two waves per SIMD: the compiler's own choice (153 VGPRs, three
 // waves) spilled scalar registers and ran 10% slower.
-template <bool kF3>
+template <bool kF3, bool kUp>
 __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void adj_fwd32_kernel(const double* __restrict__ Fin,
                                                                 const double* __restrict__ Lin,
                                                                 const double* __restrict__ Fbase,
@@ -1074,7 +1119,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   site_chain32(f, Lin, g, C, gm.cl, gm.sl, tb, a, red, sd, err);
   const SiteLds& S = sd[g.sl];
   constexpr bool f3 = kF3;  // g3 != nullptr
-  const Slice32 o = slice32(S, g, gm, f3, a);
+  const Slice32 o = slice32<kUp>(S, g, gm, f3, Lin, a);
   const float Zf = (float)a.Z;
   float R0[kQ];
   for_nodes<0, 0>([&](auto kc, auto jc) {
@@ -1199,7 +1244,30 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const RB* __res
   if (l == 0) {
     const int xm = y * a.nx + wrap(x - 1, a.nx), xp = y * a.nx + wrap(x + 1, a.nx);
     const int ym = wrap(y - 1, a.ny) * a.nx + x, yp = wrap(y + 1, a.ny) * a.nx + x;
-    const double v = outL[site] + (gb[xm] - gb[xp] + gb[ns + ym] - gb[ns + yp]) * a.inv2dx;
+    double v = outL[site];
+    if (a.grad_form == LB_GRAD_UPWIND) {
+      // the transposed per-slice gradients: each slice's upwind difference
+      // along its direction of motion (centred along an axis it does not
+      // move on), gb [2][8][sites]
+#pragma unroll
+      for (int k = 0; k < kL; ++k) {
+        const SliceGeom gk = slice_geom(C, a, k);
+        const double* bx = gb + (size_t)k * ns;
+        const double* by = gb + (size_t)(kL + k) * ns;
+        if (gk.dxr != 0)
+          v += gk.dxr * (3.0 * bx[site] - 4.0 * bx[y * a.nx + wrap(x + gk.dxr, a.nx)] +
+                         bx[y * a.nx + wrap(x + 2 * gk.dxr, a.nx)]) * a.inv2dx;
+        else
+          v += (bx[xm] - bx[xp]) * a.inv2dx;
+        if (gk.dyr != 0)
+          v += gk.dyr * (3.0 * by[site] - 4.0 * by[wrap(y + gk.dyr, a.ny) * a.nx + x] +
+                         by[wrap(y + 2 * gk.dyr, a.ny) * a.nx + x]) * a.inv2dx;
+        else
+          v += (by[ym] - by[yp]) * a.inv2dx;
+      }
+    } else {
+      v += (gb[xm] - gb[xp] + gb[ns + ym] - gb[ns + yp]) * a.inv2dx;
+    }
     if constexpr (kComb) {
       const double c = combL[site], t1 = v + 0.5 * c;
       outL[site] = t1;
@@ -1312,13 +1380,16 @@ dim3 sites_grid(int n) { return dim3((unsigned)((n + kSites - 1) / kSites)); }
 hipError_t launch_adj_stage_fwd(const double* Fin, const double* Lin, const double* Fbase, const double* Lbase,
                                 double* Fout, double* Lout, int stage, const void* lc, const double* g3,
                                 const EosTable& tb, const StageArgs& a, int* err, hipStream_t s, const void* lc32) {
-  if (lc32)
-    hipLaunchKernelGGL(g3 ? adj_fwd32_kernel<true> : adj_fwd32_kernel<false>, sites_grid(a.n_sites),
-                       dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout, Lout, stage,
-                       static_cast<const LCf*>(lc32), g3, tb, a, err);
-  else
+  if (lc32) {
+    const auto kern = g3 ? adj_fwd32_kernel<true, false>
+                         : (a.grad_form == LB_GRAD_UPWIND ? adj_fwd32_kernel<false, true>
+                                                          : adj_fwd32_kernel<false, false>);
+    hipLaunchKernelGGL(kern, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout, Lout,
+                       stage, static_cast<const LCf*>(lc32), g3, tb, a, err);
+  } else {
     hipLaunchKernelGGL(adj_fwd_kernel, sites_grid(a.n_sites), dim3(kAdjThreads), 0, s, Fin, Lin, Fbase, Lbase, Fout,
                        Lout, stage, *static_cast<const LC*>(lc), g3, tb, a, err);
+  }
   return hipGetLastError();
 }
 
@@ -1330,7 +1401,10 @@ hipError_t launch_adj_rhs(const double* F, const double* Lm, const double* seedF
   const LC& C = *static_cast<const LC*>(lc);
   if (lc32) {
     float* Rb32 = reinterpret_cast<float*>(Rb);
-    hipLaunchKernelGGL(g3 ? adj_local32_kernel<true> : adj_local32_kernel<false>, sites_grid(a.n_sites),
+    const auto kern = g3 ? adj_local32_kernel<true, false>
+                         : (a.grad_form == LB_GRAD_UPWIND ? adj_local32_kernel<false, true>
+                                                          : adj_local32_kernel<false, false>);
+    hipLaunchKernelGGL(kern, sites_grid(a.n_sites),
                        dim3(kAdjThreads), 0, s, F, Lm, seedF, seedL, scale, outF, outL, Rb32, gb, eta_part,
                        accumulate, static_cast<const LCf*>(lc32), g3, tb, a, err);
     hipError_t e = hipGetLastError();

@@ -451,8 +451,8 @@ AdjLayout adj_layout(const lb_params& p) {
   off = align_up(off + ns * sizeof(double));
   L.Rb = off;
   off = align_up(off + nF);
-  L.gb = off;
-  off = align_up(off + 2 * ns * sizeof(double));
+  L.gb = off;  // the ln M gradient's adjoint: per site, or per phi slice with the upwind gradient
+  off = align_up(off + 2 * ns * sizeof(double) * (p.gradient_form == LB_GRAD_UPWIND ? (size_t)(2 * p.n_phi) : 1));
   L.eta = off;
   off = align_up(off + ns * sizeof(double));
   L.total = off;
@@ -463,7 +463,6 @@ struct AdjBufs {
 };
 int adj_check(lb_ctx* c, double tau, double dtau, void* ws, size_t bytes, AdjBufs* B) {
   if (!c || !c->initialised) return fail(LB_E_STATE, "context not initialised");
-  if (c->p.gradient_form != LB_GRAD_CENTRED) return fail(LB_E_NOTIMPL, "the adjoint step has the centred ln M gradient only");
   if (c->generic) return fail(LB_E_NOTIMPL, "the adjoint step has the 5 x 5 x 8 momentum lattice only");
   if (!(dtau > 0) || !std::isfinite(dtau)) return fail(LB_E_ARG, "dtau must be finite and > 0");
   if (!std::isfinite(tau) || (c->p.metric == LB_METRIC_MILNE && !(tau > 0)))

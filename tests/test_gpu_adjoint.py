@@ -352,3 +352,75 @@ def test_fp32_context_adjoint_step_against_fp64(force):
     rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
     assert rel(F32, F64) < 2e-5 and rel(L32, L64) < 2e-5, (rel(F32, F64), rel(L32, L64))
     assert abs(e32 - e64) <= 1e-4 * abs(e64), (e32, e64)
+
+
+# ---- the upwind ln M gradient (gradient_form LB_GRAD_UPWIND): the force on
+# F_eq of each phi slice takes the streaming's upwind difference of ln M
+# along the slice's direction of motion; its adjoint is a per-slice
+# transposed stencil
+
+
+def _upwind_state(precision, nx=12, ny=10, dx=0.15, eta=0.12, seed=9):
+    p = lb.make_params(nx, ny, dx, eta_over_s=eta, precision=precision, gradient_form=lb.LB_GRAD_UPWIND)
+    ux, uy = wl.random_flow(nx, ny, 0.2, seed=5)
+    c = lb.Context(p, gpu(spots_e0(p, nx, ny, dx, seed)), gpu(ux), gpu(uy))
+    c.step(4, 0.01)
+    F, L, tau = c.get_state()
+    # a rough ln M, so that the gradient's stencil matters
+    L = L + gpu(0.02 * np.random.default_rng(seed).standard_normal(tuple(L.shape)))
+    return p, c, F, L, tau
+
+
+def test_upwind_forward_step_equals_lb_step():
+    print("adjoint forward step, upwind ln M gradient", flush=True)
+    _, c, F, L, tau = _upwind_state(lb.LB_FP64)
+    F1, L1 = c.adjoint_forward_step(tau, 0.01, F, L, c.adjoint_workspace())
+    F2, L2 = lib_step(c, F, L, tau, 0.01)
+    assert float((F1 - F2).abs().max()) <= 1e-12 * float(F2.abs().max())
+    assert float((L1 - L2).abs().max()) <= 1e-12
+    assert c.status() == lb.LB_OK
+
+
+@pytest.mark.parametrize("part", ["F", "lnM"])
+def test_upwind_step_adjoint_dot_product(part):
+    print(f"adjoint dot product, upwind ln M gradient, part {part}", flush=True)
+    _, c, F, L, tau = _upwind_state(lb.LB_FP64)
+    dtau = 0.01
+    rng = np.random.default_rng(23)
+    dF = F * gpu(rng.standard_normal(tuple(F.shape))) * (part != "lnM")
+    dL = gpu(rng.standard_normal(tuple(L.shape))) * (part != "F")
+    aF = gpu(rng.standard_normal(tuple(F.shape)))
+    aL = gpu(rng.standard_normal(tuple(L.shape)))
+    bF, bL = aF.clone(), aL.clone()
+    g_eta = torch.zeros(1, dtype=torch.float64, device=DEV)
+    c.adjoint_step(tau, dtau, F, L, bF, bL, g_eta, c.adjoint_workspace())
+    assert c.status() == lb.LB_OK
+    lhs = float((bF * dF).sum() + (bL * dL).sum())
+    h = 1e-6
+    Fp, Lp = lib_step(c, F + h * dF, L + h * dL, tau, dtau)
+    Fm, Lm = lib_step(c, F - h * dF, L - h * dL, tau, dtau)
+    rhs = float(((aF * (Fp - Fm)).sum() + (aL * (Lp - Lm)).sum()) / (2 * h))
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs), (lhs, rhs)
+
+
+def test_upwind_fp32_context_adjoint_step_against_fp64():
+    # as test_fp32_context_adjoint_step_against_fp64, with the upwind gradient
+    print("FP32 vs FP64 adjoint step, upwind ln M gradient", flush=True)
+    _, c64, F, L, tau = _upwind_state(lb.LB_FP64, nx=21, ny=17)
+    p32 = lb.make_params(21, 17, 0.15, eta_over_s=0.12, precision=lb.LB_FP32_FP64MATCH,
+                         gradient_form=lb.LB_GRAD_UPWIND)
+    c32 = lb.Context(p32, gpu(spots_e0(p32, 21, 17, 0.15, 9)))
+    rng = np.random.default_rng(41)
+    aF = gpu(rng.standard_normal(tuple(F.shape)))
+    aL = gpu(rng.standard_normal(tuple(L.shape)))
+    out = []
+    for c in (c64, c32):
+        bF, bL = aF.clone(), aL.clone()
+        g_eta = torch.zeros(1, dtype=torch.float64, device=DEV)
+        c.adjoint_step(tau, 0.01, F, L, bF, bL, g_eta, c.adjoint_workspace())
+        assert c.status() == lb.LB_OK
+        out.append((bF, bL, float(g_eta[0])))
+    (F64, L64, e64), (F32, L32, e32) = out
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    assert rel(F32, F64) < 2e-5 and rel(L32, L64) < 2e-5, (rel(F32, F64), rel(L32, L64))
+    assert abs(e32 - e64) <= 1e-4 * abs(e64), (e32, e64)
