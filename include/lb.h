@@ -172,8 +172,8 @@ typedef struct lb_params {
    * centred difference does not see, are held by the force (a white-noise
    * initial state at eta/s 0.2 on a 0.025 fm grid keeps its ln M spread
    * bounded instead of growing).  Requires force_form LB_FORCE_FEQ;
-   * lb_step, lb_moments and the batched form; the adjoint entry points
-   * return LB_E_NOTIMPL for it. */
+   * lb_step, lb_moments, the batched form and the adjoint entry points take
+   * it. */
   int32_t gradient_form;
 } lb_params;
 
@@ -437,13 +437,15 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
  * the spare state buffers (the state is unchanged), and keep the fastest.
  * variant_out (may be NULL) receives its index; ms_out (may be NULL) the
  * mean milliseconds per step of each variant ([12] in FP32, [3] in FP64).
- * With LB_FORCE_WEAK3D, LB_N_CONSERVED or both there are three variants,
- * tile rows 2, 4, 8 (v = 0, 1, 2) at the single-event kernel's occupancy.
+ * With LB_FORCE_WEAK3D, LB_N_CONSERVED (or both) or LB_GRAD_UPWIND there
+ * are three variants, tile rows 2, 4, 8 (v = 0, 1, 2) at the single-event
+ * kernel's occupancy.
  * Synchronous. */
 int lb_batch_tune(lb_batch* b, double dtau_fm, int32_t* variant_out, double* ms_out);
 
 /* Use kernel variant `variant` (0..11 in FP32, 0..2 in FP64 or with the 3-D
- * force or the conserved particle number, numbered as in lb_batch_tune)
+ * force, the conserved particle number or the upwind ln M gradient,
+ * numbered as in lb_batch_tune)
  * without timing: pins a tuned choice. */
 int lb_batch_set_variant(lb_batch* b, int32_t variant);
 

@@ -63,11 +63,12 @@ struct StageTime {
 // 4 ((v / 3) % 2 = 0) or 3 waves per SIMD as occupancy target, with
 // streaming (nontemporal) stores of the new state for v >= 6; FP64 has
 // variants 0..2 at 2 waves per SIMD.  With the weak-form 3-D force, the
-// conserved particle number or both there are three variants, tile rows
-// 2, 4, 8 at the occupancy of the single-event kernel.
+// conserved particle number (or both), or the upwind ln M gradient there
+// are three variants, tile rows 2, 4, 8 at the occupancy of the
+// single-event kernel.
 constexpr int kBatchTileRows[3] = {2, 4, 8};
-inline int batch_variants(int precision, int force_form = 0, int particle_number = 0) {
-  return (force_form || particle_number) ? 3 : (precision == 1 ? 12 : 3);
+inline int batch_variants(int precision, int force_form = 0, int particle_number = 0, int gradient_form = 0) {
+  return (force_form || particle_number || gradient_form) ? 3 : (precision == 1 ? 12 : 3);
 }
 inline int batch_tile_rows(int variant) { return kBatchTileRows[variant % 3]; }
 inline int batch_tiles(int nx, int ny, int tile_rows) { return ((nx + 7) / 8) * ((ny + tile_rows - 1) / tile_rows); }

@@ -1289,7 +1289,7 @@ hipError_t time_variant(lb_batch* b, int v, double dtau, int n, float* ms) {
 }
 
 int batch_tune(lb_batch* b, double dtau, int32_t* variant_out, double* ms_out) {
-  const int nv = batch_variants(b->p.precision, b->p.force_form, b->p.particle_number);
+  const int nv = batch_variants(b->p.precision, b->p.force_form, b->p.particle_number, b->p.gradient_form);
   int best = -1;
   float best_ms = 0;
   for (int v = 0; v < nv; ++v) {
@@ -1329,8 +1329,6 @@ int lb_batch_init(lb_batch** out, const lb_params* p, const lb_event* events, in
   *out = nullptr;
   std::string m = validate_batch(p, events, n_events);
   if (!m.empty()) return fail(LB_E_ARG, m);
-  if (p->gradient_form != LB_GRAD_CENTRED)
-    return fail(LB_E_NOTIMPL, "the batched form takes gradient_form LB_GRAD_CENTRED");
   if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(LB_E_ARG, "workspace NULL or not 256-byte aligned");
   if (!d_e0) return fail(LB_E_ARG, "e0 pointer array is NULL");
   for (int i = 0; i < n_events; ++i)
@@ -1451,7 +1449,7 @@ int lb_batch_tune(lb_batch* b, double dtau_fm, int32_t* variant_out, double* ms_
 
 int lb_batch_set_variant(lb_batch* b, int32_t variant) {
   if (!b) return fail(LB_E_STATE, "batch not initialised");
-  if (variant < 0 || variant >= batch_variants(b->p.precision, b->p.force_form, b->p.particle_number))
+  if (variant < 0 || variant >= batch_variants(b->p.precision, b->p.force_form, b->p.particle_number, b->p.gradient_form))
     return fail(LB_E_ARG, "no such kernel variant");
   hipError_t e = set_variant(b, variant);
   if (e != hipSuccess) return hip_fail(e, "batch tile map");

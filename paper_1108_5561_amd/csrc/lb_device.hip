@@ -704,7 +704,7 @@ __global__ __launch_bounds__(kTX * kTY * kSl, (kForce ? ForceWaves<R>::v : (kMu 
 // (event e owns tiles [tile0_e, tile0_e + tiles_e)), taken in the XCD-aware
 // order; each block looks up its event and runs the single-event tile code,
 // so an event's result does not depend on the batch it is in.
-template <typename R, int STAGE, int kTY, int kW, int kStream, int kForce, int kMu>
+template <typename R, int STAGE, int kTY, int kW, int kStream, int kForce, int kMu, int kGrad>
 __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
     const BatchEvent* __restrict__ ev, const int32_t* __restrict__ tile_event, int n_tiles, StageTime time,
     const StageTime* __restrict__ times, int time_idx, int i_in, int i_base, int i_out,
@@ -712,7 +712,6 @@ __global__ __launch_bounds__(kTX * kTY * kSl, kW) void batch_stage_kernel(
     int* __restrict__ err) {
   __shared__ double s_mom[kMomRows][kTX * kTY];
   __shared__ __attribute__((aligned(16))) R s_force[kForce ? kTY * 25 * 64 : 1];
-  constexpr int kGrad = 0;  // the batched form takes the centred ln M gradient
   const int tile = xcd_tile(n_tiles);
   if (tile >= n_tiles) return;  // whole block
   // the event, its buffers and the stage time through constant-address
@@ -986,12 +985,12 @@ hipError_t launch_stage(int precision, int stage, const void* Fin, const void* F
 }
 
 namespace {
-template <typename R, int STAGE, int kTY, int kW, int kStream, int kForce = 0, int kMu = 0>
+template <typename R, int STAGE, int kTY, int kW, int kStream, int kForce = 0, int kMu = 0, int kGrad = 0>
 hipError_t batch_launch_t(const BatchEvent* ev, const int32_t* te, int n_tiles, StageTime time,
                           const StageTime* times, int tidx, int i_in, int i_base, int i_out, const void* sc,
                           const EosTable* tb, const StageArgs& a, int* err, hipStream_t s) {
   const unsigned per = (unsigned)((n_tiles + kXcds - 1) / kXcds);
-  hipLaunchKernelGGL((batch_stage_kernel<R, STAGE, kTY, kW, kStream, kForce, kMu>), dim3(per * kXcds), dim3(kTX * kTY * kSl), 0, s, ev,
+  hipLaunchKernelGGL((batch_stage_kernel<R, STAGE, kTY, kW, kStream, kForce, kMu, kGrad>), dim3(per * kXcds), dim3(kTX * kTY * kSl), 0, s, ev,
                      te, n_tiles, time, times, tidx, i_in, i_base, i_out, static_cast<const StageConst<R>*>(sc), tb,
                      a, err);
   return hipGetLastError();
@@ -1011,10 +1010,33 @@ hipError_t batch_launch_s(int variant, const BatchEvent* ev, const int32_t* te, 
   case V:                                                                                                        \
     return batch_launch_t<R, STAGE, TY, W, 0, F, MU>(ev, te, n_tiles, time, times, tidx, i_in, i_base, i_out, sc,  \
                                                      tb, a, err, s);
+#define LB_BATCH_CASE_UP(V, TY, W, MU)                                                                            \
+  case V:                                                                                                        \
+    return batch_launch_t<R, STAGE, TY, W, 0, 0, MU, 1>(ev, te, n_tiles, time, times, tidx, i_in, i_base, i_out, \
+                                                        sc, tb, a, err, s);
   // the weak-form 3-D force and/or the conserved particle number: tile rows
   // 2, 4, 8 at the occupancy of the single-event kernel (a block of 8 rows
   // is 8 waves, so at least 2 waves per SIMD); both together at the
   // force's occupancy, as lb_step runs them
+  // the upwind ln M gradient (force on F_eq; with or without the conserved
+  // particle number): tile rows 2, 4, 8 at the default kernels' occupancy
+  if (a.grad_form == LB_GRAD_UPWIND) {
+    constexpr int W = sizeof(R) == 8 ? 2 : 4;
+    if (a.mu_mode) {
+      switch (variant) {
+        LB_BATCH_CASE_UP(0, 2, MuWaves<R>::v, 1)
+        LB_BATCH_CASE_UP(1, 4, MuWaves<R>::v, 1)
+        LB_BATCH_CASE_UP(2, 8, MuWaves<R>::v, 1)
+        default: return hipErrorInvalidValue;
+      }
+    }
+    switch (variant) {
+      LB_BATCH_CASE_UP(0, 2, W, 0)
+      LB_BATCH_CASE_UP(1, 4, W, 0)
+      LB_BATCH_CASE_UP(2, 8, W, 0)
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (a.force_form == LB_FORCE_WEAK3D && a.mu_mode) {
     switch (variant) {
       LB_BATCH_CASE_FM(0, 2, ForceWaves<R>::v, 1, 1)
@@ -1065,6 +1087,7 @@ hipError_t batch_launch_s(int variant, const BatchEvent* ev, const int32_t* te, 
   }
 #undef LB_BATCH_CASE
 #undef LB_BATCH_CASE_FM
+#undef LB_BATCH_CASE_UP
 }
 }  // namespace
 

@@ -68,13 +68,16 @@ def test_batch_equals_single_contexts_every_variant(precision):
 def _mode_params(mode, nx, ny, dx, eta, precision):
     if mode == "force3d":
         return lb.make_params(nx, ny, dx, eta_over_s=eta, precision=precision, force_form=lb.LB_FORCE_WEAK3D)
+    if mode == "upwind":
+        return lb.make_params(nx, ny, dx, eta_over_s=eta, precision=precision, gradient_form=lb.LB_GRAD_UPWIND)
     force = lb.LB_FORCE_WEAK3D if mode == "both" else lb.LB_FORCE_FEQ
+    grad = lb.LB_GRAD_UPWIND if mode == "upwind_mu" else lb.LB_GRAD_CENTRED
     return lb.make_params(nx, ny, dx, eta_over_s=eta, precision=precision, eos_kind=lb.LB_EOS_CONST_MASS,
                           eos_mass_GeV=0.4, Z=3.0, particle_number=lb.LB_N_CONSERVED, mu_over_T0=0.3,
-                          force_form=force)
+                          force_form=force, gradient_form=grad)
 
 
-@pytest.mark.parametrize("mode", ["force3d", "mu", "both"])
+@pytest.mark.parametrize("mode", ["force3d", "mu", "both", "upwind", "upwind_mu"])
 @pytest.mark.parametrize("precision", [lb.LB_FP64, lb.LB_FP32_FP64MATCH])
 def test_batch_modes_equal_single_contexts(precision, mode):
     # the weak-form 3-D force and the conserved particle number in the
@@ -82,7 +85,7 @@ def test_batch_modes_equal_single_contexts(precision, mode):
     p = _mode_params(mode, 8, 8, 0.3, 0.1, precision)
     # with the particle number conserved the heavy gas cools faster in the
     # expansion: a hotter background keeps the cold sites inside the EoS range
-    T_bg = 0.35 if mode in ("mu", "both") else 0.2
+    T_bg = 0.35 if mode in ("mu", "both", "upwind_mu") else 0.2
     e0s = [_e0(p, nx, ny, dx, 200 + i, T_bg) for i, (nx, ny, dx, _) in enumerate(EVENTS)]
     n1, n2 = 50, 2
     ref = []
