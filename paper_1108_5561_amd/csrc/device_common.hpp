@@ -19,6 +19,20 @@ __device__ __forceinline__ int wrap(int i, int n) {
   i = i >= n ? i - n : i;
   return i;
 }
+// The same for i within two of [0, n) where one correction on each side
+// suffices for every n >= 2 (n = 1 has the single index 0).
+__device__ __forceinline__ int wrap_near(int i, int n) {
+  if (n == 1) return 0;
+  i = i < 0 ? i + n : i;
+  return i >= n ? i - n : i;
+}
+// The stage kernels' choice: wrap_near for FP32, wrap for FP64 (whose
+// register allocation at one or two waves per SIMD was tuned with it).
+template <typename R>
+__device__ __forceinline__ int wrap_s(int i, int n) {
+  if constexpr (sizeof(R) == 4) return wrap_near(i, n);
+  else return wrap(i, n);
+}
 
 // Sum over the eight lanes of a site (lanes 8s .. 8s + 7) with DPP moves:
 // swap neighbours, swap pairs, then mirror within the eight.  Every lane

@@ -765,15 +765,26 @@ __device__ __forceinline__ Slice32 slice32(const SiteLds& S, const Lane& g, cons
   return o;
 }
 
-// The equilibrium's radial factors at radial node k: E_eq, and the force
-// polynomial's coefficients alpha, beta, gamma.
+// The equilibrium's radial factors at radial node k: E_eq and 1/E_eq, and
+// the force polynomial's coefficients alpha, beta, gamma.  kHw: the
+// hardware square root and reciprocal (as in the FP32 stage kernels; the
+// reverse sweep), else the correctly rounded ones (adj_fwd32_kernel, whose
+// register allocation is tuned with them).
 struct Radial32 {
-  float Eeq, al, be, ga;
+  float Eeq, iE, al, be, ga;
 };
+template <bool kHw = true>
 __device__ __forceinline__ Radial32 radial32(const Slice32& o, const LCf& C, int k) {
   Radial32 r;
-  r.Eeq = sqrtf(o.Meq * o.Meq + o.M * o.M * C.sh2[k]);
-  r.al = o.MT * o.Gl * o.ut * o.M * C.x[k] / r.Eeq;
+  if constexpr (kHw) {
+    r.Eeq = __builtin_amdgcn_sqrtf(o.Meq * o.Meq + o.M * o.M * C.sh2[k]);
+    r.iE = __builtin_amdgcn_rcpf(r.Eeq);
+    r.al = o.MT * o.Gl * o.ut * o.M * C.x[k] * r.iE;
+  } else {
+    r.Eeq = sqrtf(o.Meq * o.Meq + o.M * o.M * C.sh2[k]);
+    r.iE = 1.0f / r.Eeq;
+    r.al = o.MT * o.Gl * o.ut * o.M * C.x[k] / r.Eeq;
+  }
   r.be = o.MT * o.Gl * o.cu * C.inv_x[k];
   r.ga = o.MT * o.gu * C.inv_x[k];
   return r;
@@ -781,7 +792,7 @@ __device__ __forceinline__ Radial32 radial32(const Slice32& o, const LCf& C, int
 
 // The part of R0 of node q = k 5 + j that does not depend on the site's
 // matching: streaming (from the upwind neighbours) and S1/tau.
-template <int k, int j>
+template <int k, int j, bool kSkip = true>
 __device__ __forceinline__ float node_r0a(const double* __restrict__ F, const float f[kQ], const Slice32& o,
                                           const LCf& C, int ns) {
   constexpr int q = k * 5 + j;
@@ -790,11 +801,16 @@ __device__ __forceinline__ float node_r0a(const double* __restrict__ F, const fl
                    o.ax * (float)ld8(P, o.o_x2) - 4.0f * o.ay * (float)ld8(P, o.o_y1) +
                    o.ay * (float)ld8(P, o.o_y2);
   float s1r = 0, s1p = 0;
+  // kSkip: the radial part left out on the polar node mu = 0 (j = 2), as
+  // in the stage kernels (adj_fwd32_kernel evaluates it, with mu^2 = 0)
+  constexpr bool kRadial = !(kSkip && j == 2);
+  if constexpr (kRadial)
 #pragma unroll
-  for (int kp = 0; kp < 5; ++kp) s1r += C.A1[k * 5 + kp] * f[kp * 5 + j];
+    for (int kp = 0; kp < 5; ++kp) s1r += C.A1[k * 5 + kp] * f[kp * 5 + j];
 #pragma unroll
   for (int jp = 0; jp < 5; ++jp) s1p += C.Ath[j * 5 + jp] * f[k * 5 + jp];
-  return -C.sigi[q] * tr + (C.mu2[j] * s1r - s1p) * o.itau;
+  if constexpr (!kRadial) return -C.sigi[q] * tr - s1p * o.itau;
+  else return -C.sigi[q] * tr + (C.mu2[j] * s1r - s1p) * o.itau;
 }
 
 // S2 of node q = k 5 + j.
@@ -891,10 +907,10 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
   }
   slice_sum<4>(sums, red, g);
   const double nsum = sums[0], dsum = sums[1], wsum = sums[2];
-  const double beta = S.beta, Dd = wsum + beta * dsum, Xd = -beta * nsum / Dd;
+  const double beta = S.beta, Dd = wsum + beta * dsum, iD = 1.0 / Dd, Xd = -beta * nsum * iD;
   const double Xb = scale * seedL[g.site] + sums[3];
-  const double nbd = -beta * Xb / Dd;
-  const double Db = -Xd * Xb / Dd;
+  const double nbd = -beta * Xb * iD;
+  const double Db = -Xd * Xb * iD;
   const double betab = -nsum * Xb / Dd + Db * dsum;
   const float nb = (float)nbd, wsb = (float)Db, dsb = (float)(beta * Db), X = (float)Xd;
   // the slice's adjoint, node by node; S2, F_eq and R0 are evaluated again
@@ -949,18 +965,18 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
       cub -= C2.sigi[q] * uvb;
       if constexpr (j == 4) {
         // radial node k done: the adjoints of its alpha, beta, gamma and E_eq
-        const float c = C2.x[k] / rk.Eeq;
+        const float c = C2.x[k] * rk.iE;
         MTb += alb * o2.Gl * o2.ut * o2.M * c;
         Glb += alb * o2.MT * o2.ut * o2.M * c;
         utb += alb * o2.MT * o2.Gl * o2.M * c;
         Mb += alb * o2.MT * o2.Gl * o2.ut * c;
-        Eeqb -= alb * rk.al / rk.Eeq;
+        Eeqb -= alb * rk.al * rk.iE;
         MTb += beb * o2.Gl * o2.cu * C2.inv_x[k] + gab * o2.gu * C2.inv_x[k];
         Glb += beb * o2.MT * o2.cu * C2.inv_x[k];
         cub += beb * o2.MT * o2.Gl * C2.inv_x[k];
         gub += gab * o2.MT * C2.inv_x[k];
-        Meqb += Eeqb * o2.Meq / rk.Eeq;
-        Mb += Eeqb * o2.M * C2.sh2[k] / rk.Eeq;
+        Meqb += Eeqb * o2.Meq * rk.iE;
+        Mb += Eeqb * o2.M * C2.sh2[k] * rk.iE;
       }
     });
   }
@@ -979,19 +995,27 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
   if (g.valid)
 #pragma unroll
     for (int q = 0; q < kQ; ++q) at4(qplane(Rb, q, ns), o.o_own / 2) = R0b[q];
-  // transposed operators: S2^T S2b and (S1/tau)^T R0b
+  // transposed operators: S2^T S2b and (S1/tau)^T R0b, with R0b/tau formed
+  // once and the radial part of S1 absent on the polar node j = 2
+  {
+    float rt[kQ];
 #pragma unroll
-  for (int k = 0; k < 5; ++k)
+    for (int q = 0; q < kQ; ++q) rt[q] = R0b[q] * o2.itau;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      float acc = 0;
+    for (int k = 0; k < 5; ++k)
 #pragma unroll
-      for (int kk = 0; kk < 5; ++kk)
-        acc += C2.A2[kk * 5 + k] * S2b[kk * 5 + j] + C2.mu2[j] * C2.A1[kk * 5 + k] * R0b[kk * 5 + j] * o2.itau;
+      for (int j = 0; j < 5; ++j) {
+        float acc = 0, a1 = 0, ap = 0;
 #pragma unroll
-      for (int jj = 0; jj < 5; ++jj) acc -= C2.Ath[jj * 5 + j] * R0b[k * 5 + jj] * o2.itau;
-      fb[k * 5 + j] += acc;
-    }
+        for (int kk = 0; kk < 5; ++kk) acc += C2.A2[kk * 5 + k] * S2b[kk * 5 + j];
+        if (j != 2)
+#pragma unroll
+          for (int kk = 0; kk < 5; ++kk) a1 += C2.A1[kk * 5 + k] * rt[kk * 5 + j];
+#pragma unroll
+        for (int jj = 0; jj < 5; ++jj) ap += C2.Ath[jj * 5 + j] * rt[k * 5 + jj];
+        fb[k * 5 + j] += (j != 2 ? acc + C2.mu2[j] * a1 : acc) - ap;
+      }
+  }
   double v[10] = {(double)utb,
                     (double)cub * gm.cl + (double)gub * o.gx,
                     (double)cub * gm.sl + (double)gub * o.gy,
@@ -1017,11 +1041,11 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
     const double MTbd = v[5], ratebd = v[6], Meqbd = v[7], gxb = v[8], gyb = v[9];
     Mbd += MTbd * W.invT;
     invTbd += MTbd * W.M;
-    const double T = W.T, qv = W.q;
-    const double Tb = -invTbd * W.invT * W.invT + ratebd * a.inv_eta_hbarc / qv;
-    const double qb = -ratebd * W.rate / qv;
+    const double T = W.T, iq = 1.0 / W.q;
+    const double Tb = -invTbd * W.invT * W.invT + ratebd * a.inv_eta_hbarc * iq;
+    const double qb = -ratebd * W.rate * iq;
     const double etab = -ratebd * W.rate * a.inv_eta_hbarc * kHbarC;
-    const double z = W.Meq / T;
+    const double z = W.Meq * W.invT;
     const double uub = Tb * T + Meqbd * (W.dz * T + z * T) + betab * W.dbeta + qb * W.dq;
     const double lamb = uub * W.du_dlam;
     const double ub[3] = {utbd, uxb, uyb};
@@ -1039,6 +1063,7 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
     const double det = Bt[0][0] * (Bt[1][1] * Bt[2][2] - Bt[1][2] * Bt[2][1]) -
                        Bt[0][1] * (Bt[1][0] * Bt[2][2] - Bt[1][2] * Bt[2][0]) +
                        Bt[0][2] * (Bt[1][0] * Bt[2][1] - Bt[1][1] * Bt[2][0]);
+    const double idet = 1.0 / det;
     double w[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1049,7 +1074,7 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
         for (int j = 0; j < 3; ++j) Mx[i][j] = (j == c) ? rhs[i] : Bt[i][j];
       w[c] = (Mx[0][0] * (Mx[1][1] * Mx[2][2] - Mx[1][2] * Mx[2][1]) -
               Mx[0][1] * (Mx[1][0] * Mx[2][2] - Mx[1][2] * Mx[2][0]) +
-              Mx[0][2] * (Mx[1][0] * Mx[2][1] - Mx[1][1] * Mx[2][0])) / det;
+              Mx[0][2] * (Mx[1][0] * Mx[2][1] - Mx[1][1] * Mx[2][0])) * idet;
     }
     const double wu = w[0] * W.u[0] + w[1] * W.u[1] + w[2] * W.u[2] + lamb;
     double mb[3][3], Gb = 0;
@@ -1124,7 +1149,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   float R0[kQ];
   for_nodes<0, 0>([&](auto kc, auto jc) {
     constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
-    R0[q] = node_r0a<k, j>(Fin, f, o, C, ns);
+    R0[q] = node_r0a<k, j, false>(Fin, f, o, C, ns);
   });
   if (f3)
 #pragma unroll
@@ -1139,7 +1164,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
     Radial32 rk;
     for_nodes<0, 0>([&](auto kc, auto jc) {
       constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
-      if constexpr (j == 0) rk = radial32(o, C, k);
+      if constexpr (j == 0) rk = radial32<false>(o, C, k);
       const float s2 = node_s2<k, j>(f, C);
       const float sg = C.sig[q];
       const float feq = Zf * __expf((sg * o.M * o.cu - o.ut * rk.Eeq) * o.invT);

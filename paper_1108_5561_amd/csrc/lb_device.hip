@@ -8,7 +8,7 @@
 // evolution sums are reduced over the eight lanes with DPP moves (sum8:
 // all lanes end with bitwise-identical sums).  The per-site FP64 matching
 // of a state runs once per site, in the first wave of the block that
-// produced the state (match_tile).
+// produced the state (match_moments, match_sites).
 //
 // Distribution layout in HBM (NodeLayout): the 25 nodes of a slice in
 // 16-byte groups, group g in plane g as [site][l][V], so a lane moves its
@@ -284,10 +284,16 @@ __device__ __forceinline__ EosTable load_table(const EosTable* p) {
   return t;
 }
 // Entry l (0..7, this lane's phi slice) of an 8-value table in the stage
-// constants: the table is read with scalar loads (uniform addresses) and the
-// lane's value selected in registers, so that no per-lane memory read (whose
-// completion the in-order vector-memory counter would tie to the loads
-// issued before it) sits in front of the streaming loads that depend on it.
+// constants, two ways.  lane_load reads it per lane: the FP32 stage kernels
+// issue these reads before their streaming loads, so that the in-order
+// vector-memory counter lets the values be used without waiting for the
+// loads issued after them.  lane_entry reads the table with scalar loads
+// and selects the lane's value in registers (more instructions, no memory
+// latency: the FP64 kernels, at one or two waves per SIMD, are faster so).
+template <typename R>
+__device__ __forceinline__ R lane_load(const __attribute__((address_space(4))) R* tab, int l) {
+  return tab[l];
+}
 template <typename R>
 __device__ __forceinline__ R lane_entry(const __attribute__((address_space(4))) R* tab, int l) {
   R v[8];
@@ -558,20 +564,24 @@ __device__ __forceinline__ void slice_current(const R f[25], CPtr<R> C, R* p0, R
 }
 
 // Landau matching (eq. (sanity)) and EoS inversion of a tile's state from
-// the slices in registers, writing the site scalars.  Every thread of the
-// block calls it (one barrier inside); lane l of site ts holds slice l and
-// lnM = ln M of its site.  s_mom is the block's LDS scratch [7][tile sites].
-template <typename R, int kTY, int kMu>
-__device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM, int t, int bx,
-                                           int by, const EosTable* __restrict__ tbg, const StageArgs& a,
-                                           double* __restrict__ sc, int* __restrict__ err,
-                                           double (*s_mom)[kTX * kTY]) {
-  constexpr int kTile = kTX * kTY;
+// the slices in registers, writing the site scalars, in two calls made by
+// every thread of the block: match_moments puts the slice sums into LDS
+// (lane l of site ts holds slice l, cl and sl are the cosine and sine of
+// its angle, lnM = ln M of its site; s_mom is the block's LDS scratch
+// [rows][tile sites]), match_sites waits at the block's barrier and has one
+// thread per site match it and write its record.  A kernel may do other
+// work (its stores) between the two.
+template <typename R, int kTY, int kMu, bool kSelect = false>
+__device__ __forceinline__ void match_moments(const R f[25], CPtr<R> C, R cl, R sl, double lnM, int t,
+                                              double (*s_mom)[kTX * kTY]) {
   const int ts = t >> 3, l = t & 7;
   R p0, p1, p2, p3;
   slice_moments(f, C, &p0, &p1, &p2, &p3);
   (void)p3;
-  const R cl = lane_entry<R>(C->cosl, l), sl = lane_entry<R>(C->sinl, l);
+  if constexpr (kSelect) {  // the angles by lane_entry, here (cl, sl unused)
+    cl = lane_entry<R>(C->cosl, l);
+    sl = lane_entry<R>(C->sinl, l);
+  }
   const R m00 = sum8(p0), m01 = sum8(p1 * cl), m02 = sum8(p1 * sl);
   const R m11 = sum8(p2 * cl * cl), m12 = sum8(p2 * cl * sl), m22 = sum8(p2 * sl * sl);
   if (l == 0) {
@@ -593,10 +603,13 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
       s_mom[9][ts] = (double)n2;
     }
   }
-  __syncthreads();
-  if (t >= kTile) return;
-  const int sx = bx * kTX + (t % kTX), sy = by * kTY + (t / kTX);
-  if (sx >= a.nx || sy >= a.ny) return;
+}
+// Matching and record of site (sx, sy) of the tile from the sums in LDS
+// column t.
+template <typename R, int kTY, int kMu>
+__device__ __forceinline__ void match_site(int t, int sx, int sy, const EosTable* __restrict__ tbg,
+                                           const StageArgs& a, double* __restrict__ sc, int* __restrict__ err,
+                                           double (*s_mom)[kTX * kTY]) {
   const int ss = sy * a.nx + sx;
   const double lnMs = s_mom[6][t];
   // The mixed tensor T_kin g = G (sum w F V V) g with G = M^4/(2 pi^2): its
@@ -647,6 +660,16 @@ __device__ __forceinline__ void match_tile(const R f[25], CPtr<R> C, double lnM,
   rec.beta = kMu ? alpha : E.beta;  // beta = 0 for the constant mass of the mu mode
   rec.lnM = lnMs;
   store_record<R>(buf_rsrc(sc, (uint32_t)a.n_sites * SiteRecord<R>::kBytes), ss, rec);
+}
+// The block's barrier, then threads 0 .. 8 kTY - 1 match one site each.
+template <typename R, int kTY, int kMu>
+__device__ __forceinline__ void match_sites(int t, int bx, int by, const EosTable* __restrict__ tbg,
+                                            const StageArgs& a, double* __restrict__ sc, int* __restrict__ err,
+                                            double (*s_mom)[kTX * kTY]) {
+  constexpr int kTile = kTX * kTY;
+  __syncthreads();
+  const int sx = bx * kTX + (t % kTX), sy = by * kTY + (t / kTX);
+  if (t < kTile && sx < a.nx && sy < a.ny) match_site<R, kTY, kMu>(t, sx, sy, tbg, a, sc, err, s_mom);
 }
 
 // Tile of a block in the XCD-aware order: workgroups go round-robin over the
@@ -778,10 +801,12 @@ __global__ __launch_bounds__(kTX * TileRows<R>::v * kSl) void site_kernel(
   const int x0 = bx * kTX + (ts % kTX), y0 = by * kTY + (ts / kTX);
   const bool valid = (x0 < a.nx) && (y0 < a.ny);
   const int site = valid ? y0 * a.nx + x0 : 0;
+  const R cl = lane_load<R>(C->cosl, l), sl = lane_load<R>(C->sinl, l);
   R f[25];
   load_slice<R>(buf_rsrc(F, (uint32_t)a.n_sites * kSl * 25u * (uint32_t)sizeof(R)), (uint32_t)site * kSl + l,
                 NodeLayout<R>::gbytes(a.n_sites), f);
-  match_tile<R, kTY, kMu>(f, C, lnMv[site], t, bx, by, tbg, a, sc, err, s_mom);
+  match_moments<R, kTY, kMu>(f, C, cl, sl, lnMv[site], t, s_mom);
+  match_sites<R, kTY, kMu>(t, bx, by, tbg, a, sc, err, s_mom);
 }
 
 // Initial local equilibrium (Sec. IV.D): T0 from eps_EoS(T0) = e0.
