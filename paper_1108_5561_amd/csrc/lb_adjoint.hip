@@ -634,13 +634,13 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
 // reduced in FP64 and the per-site FP64 chain (moments -> Landau matching ->
 // EoS, and its reverse through the implicit-function adjoints) done once
 // per site, by the thread of slice 0, and handed to the site's other seven
-// threads through LDS.  Only F and its adjoint are held per node: the
-// forward values R0 and S2 of a node are evaluated again where the reverse
-// sweep needs them (the stencil neighbours come from cache), and the
-// adjoints of the operators S1 and S2 are scattered into the adjoint of F
-// as each node's R0b and S2b become known, so the register footprint
-// allows several waves per SIMD.  The lattice constants come in FP32
-// (LCf); R0b goes out in FP32 (Rb).
+// threads through LDS.  The forward values S2, F_eq and R0 of a node are
+// evaluated again where the reverse sweep needs them rather than held (the
+// part of R0 read from the stencil neighbours is read once and kept), and
+// the transposed operators S1^T and S2^T are applied to the slice's R0b and
+// S2b after the sweep, so the register footprint allows two waves per
+// SIMD.  The lattice constants come in FP32 (LCf); R0b goes out in FP32
+// (Rb).
 using LCf = LatticeConst<float, 5, 5>;
 struct SiteLds {
   double m[6];  // sum w F V^a V^b: tau tau, tau x, tau y, xx, xy, yy
