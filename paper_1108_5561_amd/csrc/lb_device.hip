@@ -98,9 +98,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uin
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
 }
 template <typename R> struct Buf;
-// kAux is the cache-policy operand of the buffer instruction: 0, or kNT
-// (nontemporal: the line is not kept for reuse, for data streamed once)
+// kAux is the cache-policy operand of the buffer instruction: 0, kNT
+// (nontemporal: the line is not kept for reuse, for data streamed once) or
+// kSC1 (device scope: a store is written through this XCD's L2 to the
+// memory side, where the next stage's blocks on every XCD read it)
 constexpr int kNT = 2;
+constexpr int kSC1 = 16;
 template <> struct Buf<float> {
   template <int kAux = 0>
   static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
