@@ -144,8 +144,13 @@ def test_one_step_upwind_gradient(lat, eos, nx, ny):
         assert tmunu_rel_err(obs_c, ref) > 1e-7
 
 
-def test_one_step_fp32(lat, eos):
-    Fg, lg, obs, Fo, lo, ref = _one_step_parity(lat, eos, lb.LB_FP32_FP64MATCH, 37, 23, 0.2, 0.01, seed=3)
+@pytest.mark.parametrize("nx,ny", [(37, 23), (1, 1), (2, 3), (3, 2)])
+def test_one_step_fp32(lat, eos, nx, ny):
+    # the grids of one to three sites per axis exercise the FP32 kernels'
+    # one-sided periodic wrap of the stencil indices (every neighbour of a
+    # one-site axis is the site itself)
+    Fg, lg, obs, Fo, lo, ref = _one_step_parity(lat, eos, lb.LB_FP32_FP64MATCH, nx, ny, 0.2, 0.01,
+                                                seed=3 if nx == 37 else 10 * nx + ny)
     assert tmunu_rel_err(obs, ref) < 1e-5
     assert np.max(np.abs(lg - lo)) < 1e-6
 
