@@ -801,14 +801,13 @@ __device__ __forceinline__ Radial32 radial32(const Slice32& o, const LCf& C, int
 
 // The part of R0 of node q = k 5 + j that does not depend on the site's
 // matching: streaming (from the upwind neighbours) and S1/tau.
+// The node's upwind neighbours (x - 1, x - 2, y - 1, y - 2 along the
+// slice's direction) are given (h) or read here.
 template <int k, int j, bool kSkip = true>
-__device__ __forceinline__ float node_r0a(const double* __restrict__ F, const float f[kQ], const Slice32& o,
-                                          const LCf& C, int ns) {
+__device__ __forceinline__ float node_r0a(const float h[4], const float f[kQ], const Slice32& o, const LCf& C) {
   constexpr int q = k * 5 + j;
-  const double* P = qplane(F, q, ns);
-  const float tr = 3.0f * (o.ax + o.ay) * f[q] - 4.0f * o.ax * (float)ld8(P, o.o_x1) +
-                   o.ax * (float)ld8(P, o.o_x2) - 4.0f * o.ay * (float)ld8(P, o.o_y1) +
-                   o.ay * (float)ld8(P, o.o_y2);
+  const float tr = 3.0f * (o.ax + o.ay) * f[q] - 4.0f * o.ax * h[0] + o.ax * h[1] - 4.0f * o.ay * h[2] +
+                   o.ay * h[3];
   float s1r = 0, s1p = 0;
   // kSkip: the radial part left out on the polar node mu = 0 (j = 2), as
   // in the stage kernels (adj_fwd32_kernel evaluates it, with mu^2 = 0)
@@ -820,6 +819,22 @@ __device__ __forceinline__ float node_r0a(const double* __restrict__ F, const fl
   for (int jp = 0; jp < 5; ++jp) s1p += C.Ath[j * 5 + jp] * f[k * 5 + jp];
   if constexpr (!kRadial) return -C.sigi[q] * tr - s1p * o.itau;
   else return -C.sigi[q] * tr + (C.mu2[j] * s1r - s1p) * o.itau;
+}
+template <int k, int j>
+__device__ __forceinline__ void node_nbrs(const double* __restrict__ F, const Slice32& o, int ns, double h[4]) {
+  const double* P = qplane(F, k * 5 + j, ns);
+  h[0] = ld8(P, o.o_x1);
+  h[1] = ld8(P, o.o_x2);
+  h[2] = ld8(P, o.o_y1);
+  h[3] = ld8(P, o.o_y2);
+}
+template <int k, int j, bool kSkip = true>
+__device__ __forceinline__ float node_r0a(const double* __restrict__ F, const float f[kQ], const Slice32& o,
+                                          const LCf& C, int ns) {
+  double hd[4];
+  node_nbrs<k, j>(F, o, ns, hd);
+  const float h[4] = {(float)hd[0], (float)hd[1], (float)hd[2], (float)hd[3]};
+  return node_r0a<k, j, kSkip>(h, f, o, C);
 }
 
 // S2 of node q = k 5 + j.
@@ -860,6 +875,11 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
   const LCf& C = *Cg;
   __shared__ RedBuf red;
   __shared__ SiteLds sd[kSites];
+  // the slice's adjoint, parked in LDS over the site's reverse chain (held
+  // in registers it was spilled to scratch and reloaded one value at a
+  // time after the chain)
+  __shared__ float4 s_fb4[6][kAdjThreads];
+  __shared__ float s_fb1[kAdjThreads];
   const Lane g = lane_of(a);
   const int ns = a.n_sites, l = g.l;
   float f[kQ];
@@ -875,11 +895,29 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
   // collision and the equilibrium (streaming, S1/tau, the 3-D force) and
   // the seed K_bar
   float r0a[kQ], Kb[kQ];
-  for_nodes<0, 0>([&](auto kc, auto jc) {
-    constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
-    r0a[q] = node_r0a<k, j>(F, f, o, C, ns);
-    Kb[q] = sc * (float)ld8(qplane(seedF, q, ns), o.o_own);
-  });
+  {
+    // one radial node's neighbours and seeds are all read before any is
+    // used, so that the reads are in flight together
+    double h[5][4];
+    double kb[5];
+    for_nodes<0, 0>([&](auto kc, auto jc) {
+      constexpr int k = decltype(kc)::value, j = decltype(jc)::value;
+      if constexpr (j == 0) {
+        node_nbrs<k, 0>(F, o, ns, h[0]);
+        node_nbrs<k, 1>(F, o, ns, h[1]);
+        node_nbrs<k, 2>(F, o, ns, h[2]);
+        node_nbrs<k, 3>(F, o, ns, h[3]);
+        node_nbrs<k, 4>(F, o, ns, h[4]);
+#pragma unroll
+        for (int jj = 0; jj < 5; ++jj) kb[jj] = ld8(qplane(seedF, k * 5 + jj, ns), o.o_own);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      constexpr int q = k * 5 + j;
+      const float hf[4] = {(float)h[j][0], (float)h[j][1], (float)h[j][2], (float)h[j][3]};
+      r0a[q] = node_r0a<k, j>(hf, f, o, C);
+      Kb[q] = sc * (float)kb[j];
+    });
+  }
   if (f3)
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
@@ -1025,6 +1063,10 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
         fb[k * 5 + j] += (j != 2 ? acc + C2.mu2[j] * a1 : acc) - ap;
       }
   }
+#pragma unroll
+  for (int gq = 0; gq < 6; ++gq)
+    s_fb4[gq][threadIdx.x] = make_float4(fb[4 * gq], fb[4 * gq + 1], fb[4 * gq + 2], fb[4 * gq + 3]);
+  s_fb1[threadIdx.x] = fb[24];
   double v[10] = {(double)utb,
                     (double)cub * gm.cl + (double)gub * o.gx,
                     (double)cub * gm.sl + (double)gub * o.gy,
@@ -1116,11 +1158,24 @@ __global__ __launch_bounds__(kAdjThreads, kF3 ? 1 : 2) void adj_local32_kernel(
   if (!g.valid) return;
   const float c00 = (float)S.mb[0], c01 = (float)(S.mb[1] * gm.cl + S.mb[2] * gm.sl);
   const float c11 = (float)(S.mb[3] * gm.cl * gm.cl + S.mb[4] * gm.cl * gm.sl + S.mb[5] * gm.sl * gm.sl);
+  float fbl[kQ];
+#pragma unroll
+  for (int gq = 0; gq < 6; ++gq) {
+    const float4 w = s_fb4[gq][threadIdx.x];
+    fbl[4 * gq] = w.x;
+    fbl[4 * gq + 1] = w.y;
+    fbl[4 * gq + 2] = w.z;
+    fbl[4 * gq + 3] = w.w;
+  }
+  fbl[24] = s_fb1[threadIdx.x];
+  // the accumulated values are all read before the first store
+  double prev[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) prev[q] = accumulate ? ld8(qplane(outF, q, ns), o.o_own) : 0.0;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
-    double& dst = at8(qplane(outF, q, ns), o.o_own);
-    const double v_ = (double)(fb[q] + c00 * C.wx2[q] + c01 * C.wxs[q] + c11 * C.ws2[q]);
-    st_dev(&dst, accumulate ? dst + v_ : v_);
+    const double v_ = (double)(fbl[q] + c00 * C.wx2[q] + c01 * C.wxs[q] + c11 * C.ws2[q]);
+    st_dev(&at8(qplane(outF, q, ns), o.o_own), prev[q] + v_);
   }
 }
 
