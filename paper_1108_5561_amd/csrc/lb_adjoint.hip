@@ -1211,10 +1211,24 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
   const Slice32 o = slice32<kUp>(S, g, gm, f3, Lin, a);
   const float Zf = (float)a.Z;
   float R0[kQ];
-  for_nodes<0, 0>([&](auto kc, auto jc) {
-    constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
-    R0[q] = node_r0a<k, j, false>(Fin, f, o, C, ns);
-  });
+  {
+    // one radial node's upwind neighbours read together, as in
+    // adj_local32_kernel
+    double h[5][4];
+    for_nodes<0, 0>([&](auto kc, auto jc) {
+      constexpr int k = decltype(kc)::value, j = decltype(jc)::value, q = k * 5 + j;
+      if constexpr (j == 0) {
+        node_nbrs<k, 0>(Fin, o, ns, h[0]);
+        node_nbrs<k, 1>(Fin, o, ns, h[1]);
+        node_nbrs<k, 2>(Fin, o, ns, h[2]);
+        node_nbrs<k, 3>(Fin, o, ns, h[3]);
+        node_nbrs<k, 4>(Fin, o, ns, h[4]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      const float hf[4] = {(float)h[j][0], (float)h[j][1], (float)h[j][2], (float)h[j][3]};
+      R0[q] = node_r0a<k, j, false>(hf, f, o, C);
+    });
+  }
   if (f3)
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
