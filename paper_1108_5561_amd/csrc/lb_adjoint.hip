@@ -1290,7 +1290,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(1, 
 // (with outF the corrector's adjoint of the predictor state and combF the
 // incoming adjoint of the new state).
 template <typename RB, bool kG3, bool kComb>
-__global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const RB* __restrict__ Rb,
+__global__ __launch_bounds__(kAdjThreads, kG3 ? 1 : 2) void adj_gather_kernel(const RB* __restrict__ Rb,
                                                                  const double* __restrict__ gb,
                                                                  double* __restrict__ outF,
                                                                  double* __restrict__ outL, const LC C,
@@ -1319,29 +1319,49 @@ __global__ __launch_bounds__(kAdjThreads) void adj_gather_kernel(const RB* __res
     gx = (Lm[y * a.nx + wrap(x + 1, a.nx)] - Lm[y * a.nx + wrap(x - 1, a.nx)]) * a.inv2dx;
     gy = (Lm[wrap(y + 1, a.ny) * a.nx + x] - Lm[wrap(y - 1, a.ny) * a.nx + x]) * a.inv2dx;
   }
+  if constexpr (!kG3 && !kComb) {
+    // every read of the slice (the stencil's R0_bar and F_bar) before its
+    // first store: with the stores in between, each node's reads waited for
+    // the previous node's round trip (13.3 -> 11.9 us at 128 x 128; with
+    // the Heun accumulator's reads as well, the gather below needs 256
+    // registers and ran 17.9 -> 19.9 us, so it keeps the node-by-node loop)
+    double tq[kQ], dq[kQ];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const double t = 3.0 * (gm.ax + gm.ay) * rb(q, o0) - 4.0 * gm.ax * rb(q, o1) + gm.ax * rb(q, o2) -
-                     4.0 * gm.ay * rb(q, o3) + gm.ay * rb(q, o4);
-    double& dst = at8(qplane(outF, q, ns), od);
-    double v = dst - C.sigi[q] * t;
-    if constexpr (kG3) {
-      const double* gxc = g3;
-      const double* gyc = g3 + (size_t)kN * kN;
-      const int m = q * kL + l;
-      double acc = 0;
-#pragma unroll 1
-      for (int n = 0; n < kN; ++n)
-        acc += (double)Rb[(size_t)n * ns + site] * (gx * gxc[(size_t)n * kN + m] + gy * gyc[(size_t)n * kN + m]);
-      v += acc;
+    for (int q = 0; q < kQ; ++q) {
+      tq[q] = 3.0 * (gm.ax + gm.ay) * rb(q, o0) - 4.0 * gm.ax * rb(q, o1) + gm.ax * rb(q, o2) -
+              4.0 * gm.ay * rb(q, o3) + gm.ay * rb(q, o4);
+      dq[q] = at8(qplane(outF, q, ns), od);
     }
-    if constexpr (kComb) {
-      double& cv = at8(qplane(combF, q, ns), od);
-      const double c = cv, t1 = v + 0.5 * c;
-      st_dev(&dst, t1);
-      st_dev(&cv, 0.5 * c + t1);
-    } else {
-      st_dev(&dst, v);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) st_dev(&at8(qplane(outF, q, ns), od), dq[q] - C.sigi[q] * tq[q]);
+  } else {
+    // node by node (with the 3-D force's transposed operator, its own reads
+    // per node)
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const double t = 3.0 * (gm.ax + gm.ay) * rb(q, o0) - 4.0 * gm.ax * rb(q, o1) + gm.ax * rb(q, o2) -
+                       4.0 * gm.ay * rb(q, o3) + gm.ay * rb(q, o4);
+      double& dst = at8(qplane(outF, q, ns), od);
+      double v = dst - C.sigi[q] * t;
+      if constexpr (kG3) {
+        const double* gxc = g3;
+        const double* gyc = g3 + (size_t)kN * kN;
+        const int m = q * kL + l;
+        double acc = 0;
+#pragma unroll 1
+        for (int n = 0; n < kN; ++n)
+          acc += (double)Rb[(size_t)n * ns + site] * (gx * gxc[(size_t)n * kN + m] + gy * gyc[(size_t)n * kN + m]);
+        v += acc;
+      }
+      if constexpr (kComb) {
+        double& cv = at8(qplane(combF, q, ns), od);
+        const double c = cv, t1 = v + 0.5 * c;
+        st_dev(&dst, t1);
+        st_dev(&cv, 0.5 * c + t1);
+      } else {
+        st_dev(&dst, v);
+      }
     }
   }
   if (l == 0) {
